@@ -1,0 +1,183 @@
+/*
+ * rbp.h -- C ABI of librbp: Monte-Carlo logical-error estimation with Relay-BP
+ * decoding of detector error models, on AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow the paper's decoding problem (Sec. 6.1 and Table
+ * "decoding latency"): a detector error model is a binary matrix H with
+ * N_det rows (detectors, here M) and N_loc columns (error mechanisms, here N),
+ * per-mechanism probabilities p_j and an observable matrix O (k x N).  Shots
+ * are sampled as independent Bernoulli faults; decoding maps a syndrome to a
+ * correction with Relay-BP (flooding min-sum with memory-damped marginals,
+ * sequential relay legs, the lowest-weight of stop_nconv solutions,
+ * single-precision messages; parameters named as in Sec. 6.1).
+ *
+ * Conventions shared by every call
+ *   - Bit vectors are packed LSB-first into uint32 words, row-major
+ *     [shot][word]: bit b of vector v is bit (b % 32) of word b / 32.  Unused
+ *     high bits of the last word are written as zero.
+ *   - Pointers named *_dev are device memory owned by the caller; host
+ *     pointers are read during the call only.  The library owns only the
+ *     handle-internal buffers it creates.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Sampling and decoding
+ *     are asynchronous on that stream; create/destroy/info are synchronous.
+ *   - A handle may be used by one host thread at a time.  Calls that overlap
+ *     on different streams with one handle are not supported.
+ *   - Outputs are a pure function of the inputs, the seeds and the
+ *     parameters: they do not depend on the stream, the launch configuration
+ *     or the order in which the device processes shots.
+ *   - Errors are returned as negative status codes; rbp_last_error() gives
+ *     the message of the last failing call on the calling thread.
+ */
+#ifndef RBP_H_
+#define RBP_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rbp_status;
+#define RBP_OK 0
+#define RBP_ERR_INVALID_ARG (-1) /* NULL pointer, bad enum or parameter range */
+#define RBP_ERR_SHAPE (-2)       /* inconsistent sizes, unsorted or duplicate CSC entries */
+#define RBP_ERR_UNSUPPORTED (-3) /* row degree outside [2, 32] (0 allowed), p outside (0, 0.5] */
+#define RBP_ERR_OOM (-4)         /* device or host allocation failed */
+#define RBP_ERR_HIP (-5)         /* HIP runtime error (message in rbp_last_error) */
+
+typedef struct rbp_code* rbp_code_t;
+
+/* Detector error model handle.
+ * H: M x N in CSC form, host arrays col_ptr[N+1], row_idx[nnz] (rows strictly
+ * ascending within each column, 0 <= row < M).  O: k x N in CSC form
+ * (obs_col_ptr[N+1], obs_row_idx), k may be 0 (then both may be NULL).
+ * Every row of H must have degree 0 or 2..32.  The handle keeps device copies
+ * of H in CSR and CSC order and of O. */
+rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const int32_t* row_idx, int32_t k,
+                           const int32_t* obs_col_ptr, const int32_t* obs_row_idx, rbp_code_t* out);
+rbp_status rbp_code_destroy(rbp_code_t code);
+/* Sizes of a handle; any output pointer may be NULL. */
+rbp_status rbp_code_info(rbp_code_t code, int32_t* M, int32_t* N, int32_t* nnz, int32_t* k, int32_t* max_row_deg,
+                         int32_t* max_col_deg);
+
+/* sample(H, priors, shots, seed)  -- Bernoulli faults and their syndromes.
+ * priors: host double[N], each in (0, 0.5].  Mechanism j of shot s faults iff
+ * word (j mod 4) of Philox4x32-10 with key (seed lo, seed hi) and counter
+ * (j / 4, shot lo, shot hi, 0), shot = shot_offset + s, is below
+ * min(floor(p_j 2^32), 2^32 - 1).  So any shot range is reproducible on its own.
+ * Outputs (device): syndromes_dev uint32[shots][ceil(M/32)] = H e,
+ * obs_dev uint32[shots][ceil(k/32)] = O e (may be NULL when k = 0),
+ * errors_dev uint32[shots][ceil(N/32)] = e (may be NULL). */
+rbp_status rbp_sample(rbp_code_t code, const double* priors, uint64_t shots, uint64_t seed, uint64_t shot_offset,
+                      uint32_t* syndromes_dev, uint32_t* obs_dev, uint32_t* errors_dev, void* stream);
+
+/* Relay-BP settings; names follow Sec. 6.1 of the paper. */
+typedef struct {
+    float gamma0;               /* memory strength of leg 0 (paper: 0.125) */
+    float gamma_min, gamma_max; /* gamma_dist of the relay legs, e.g. [-0.24, 0.66] */
+    int32_t pre_iter;           /* iteration budget of leg 0 (80), >= 1 */
+    int32_t max_iterations;     /* iteration budget of each relay leg (60), >= 1 */
+    int32_t num_sets;           /* number of relay legs after leg 0 (paper 1000), >= 0 */
+    int32_t stop_nconv;         /* solutions to collect before stopping (5), 1..255 */
+    int32_t stopping_criterion; /* 0: stop after stop_nconv solutions; 1: run every leg */
+    uint64_t gamma_seed;        /* relay-leg memory strengths: gamma_j^(r) = fmaf(u, gamma_max - gamma_min,
+                                   gamma_min), u = (Philox4x32-10(gamma_seed; j/4, r, 0, 1)_{j mod 4} >> 8)
+                                   * 2^-24, shared by every shot */
+} rbp_relay_params;
+
+/* Per-shot decode statistics (32 bytes). */
+typedef struct {
+    uint8_t converged; /* 1 if some leg converged (or the syndrome was zero) */
+    uint8_t nconv;     /* solutions found */
+    uint8_t path;      /* 0 plain Relay-BP, 1 learned proposal accepted, 2 proposal failed -> plain,
+                          3 zero syndrome */
+    uint8_t reserved;
+    uint16_t legs;     /* legs run (both phases) */
+    uint16_t reserved2;
+    uint32_t iters;    /* BP iterations run (both phases) */
+    uint32_t reserved3;
+    uint64_t t_start, t_end; /* device wall clock (100 MHz ticks) when the shot was taken and finished */
+} rbp_shot_stats;
+
+/* decode(H, priors, syndromes, relay params) -> corrections and logical flips.
+ * priors: host double[N] in (0, 0.5]; the decoder uses Lambda_j =
+ * (float) ln((1-p_j)/p_j).  syndromes_dev: uint32[shots][ceil(M/32)].
+ * prior_delta_dev: optional float[shots][N]; when given, each shot first runs
+ * one proposal leg (leg 0 with priors Lambda + delta, gamma0, pre_iter); if it
+ * converges its solution is returned (path 1), else plain Relay-BP runs from
+ * scratch (path 2).  Solution weights always use Lambda.
+ * Outputs (device): corrections_dev uint32[shots][ceil(N/32)] (the lowest
+ * weight solution, or the last hard decision when no leg converged),
+ * obs_pred_dev uint32[shots][ceil(k/32)] = O * correction (may be NULL when
+ * k = 0), stats_dev rbp_shot_stats[shots] (may be NULL). */
+rbp_status rbp_decode(rbp_code_t code, const double* priors, const uint32_t* syndromes_dev, uint64_t shots,
+                      const rbp_relay_params* params, const float* prior_delta_dev, uint32_t* corrections_dev,
+                      uint32_t* obs_pred_dev, rbp_shot_stats* stats_dev, void* stream);
+
+/* Batched decode of several detector error models in one persistent launch.
+ * Shot s belongs to model shot_code_dev[s] (uint8, < n_codes) and is the
+ * shot_index_dev[s]-th row of that model's syndrome / output arrays
+ * (syndromes_dev[c], corrections_dev[c], obs_pred_dev[c]; device pointers held
+ * in host arrays).  priors[c] are host arrays as in rbp_decode; stats_dev is
+ * indexed by s.  Every model uses the same params. */
+rbp_status rbp_decode_multi(int32_t n_codes, const rbp_code_t* codes, const double* const* priors,
+                            const uint8_t* shot_code_dev, const uint32_t* shot_index_dev, uint64_t shots,
+                            const uint32_t* const* syndromes_dev, const rbp_relay_params* params,
+                            uint32_t* const* corrections_dev, uint32_t* const* obs_pred_dev,
+                            rbp_shot_stats* stats_dev, void* stream);
+
+/* Launch shape of the persistent decoder for one handle (chosen by the
+ * autotuner; 0 = library default).  waves_per_shot: wavefronts that share one
+ * shot (1..16).  state: 0 auto, 1 per-shot state in LDS, 2 in device memory.
+ * max_slots: cap on the resident shot slots (0 = as many as fit). */
+typedef struct {
+    int32_t waves_per_shot;
+    int32_t state;
+    int32_t max_slots;
+} rbp_launch_config;
+rbp_status rbp_set_launch_config(rbp_code_t code, const rbp_launch_config* cfg);
+/* Launch shape rbp_decode would use for this handle (after defaults). */
+rbp_status rbp_get_launch_config(rbp_code_t code, rbp_launch_config* cfg, int32_t* slots, int32_t* lds_bytes);
+
+/* Debug trace of one shot: the marginals M (float[N]) and check-to-variable
+ * messages (float[nnz], CSC edge order of H) right after iteration t (>= 1) of
+ * leg `leg` of phase `phase` (0 plain Relay-BP, 1 proposal leg).  syndrome_dev
+ * holds one shot; prior_delta_dev is float[N] or NULL.  *reached (host) is 1 if
+ * the decode got there, else 0.  Synchronizes the stream. */
+rbp_status rbp_trace(rbp_code_t code, const double* priors, const uint32_t* syndrome_dev,
+                     const rbp_relay_params* params, const float* prior_delta_dev, int32_t phase, int32_t leg,
+                     int32_t t, float* M_out_dev, float* mu_out_dev, int32_t* reached, void* stream);
+
+/* ---- learned proposal network ------------------------------------------- *
+ * A multilayer perceptron x -> delta with x_i = syndrome bit i (0/1),
+ * two hidden ReLU layers and a linear output of one log-prior adjustment per
+ * mechanism: delta = W3 relu(W2 relu(W1 x + b1) + b2) + b3.  Weights are kept
+ * as FP32 masters and used as BF16 copies with FP32 accumulation. */
+typedef struct rbp_mlp* rbp_mlp_t;
+/* in_dim = M, out_dim = N of the model it serves; hidden >= 1.  Weights are
+ * initialised from `seed` (uniform in +-1/sqrt(fan_in)), biases zero. */
+rbp_status rbp_mlp_create(int32_t in_dim, int32_t hidden, int32_t out_dim, uint64_t seed, rbp_mlp_t* out);
+rbp_status rbp_mlp_destroy(rbp_mlp_t mlp);
+/* delta_dev float[shots][out_dim] from syndromes_dev uint32[shots][ceil(in_dim/32)]. */
+rbp_status rbp_mlp_forward(rbp_mlp_t mlp, const uint32_t* syndromes_dev, uint64_t shots, float* delta_dev,
+                           void* stream);
+/* One Adam step on a batch: loss = mean over the batch of
+ * sum_j BCEWithLogits(z_j, y_j), z_j = -(Lambda_j + delta_j), y = target bits
+ * (uint32[batch][ceil(out_dim/32)]), Lambda = llr_dev float[out_dim].
+ * loss_out_dev (float[1], may be NULL) receives the batch loss. */
+rbp_status rbp_mlp_train_step(rbp_mlp_t mlp, const uint32_t* syndromes_dev, const uint32_t* targets_dev,
+                              const float* llr_dev, uint64_t batch, float lr, float* loss_out_dev, void* stream);
+/* Copy parameters between the handle and a caller buffer (host float array
+ * laid out W1[h][in], b1[h], W2[h][h], b2[h], W3[out][h], b3[out]).  Set
+ * replaces the masters and resets the Adam state. */
+rbp_status rbp_mlp_num_params(rbp_mlp_t mlp, int64_t* n);
+rbp_status rbp_mlp_get_params(rbp_mlp_t mlp, float* host_out);
+rbp_status rbp_mlp_set_params(rbp_mlp_t mlp, const float* host_in);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* rbp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBP_H_ */

@@ -1,0 +1,95 @@
+// Shared host/device helpers of librbp (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rbp.h"
+
+namespace rbp {
+
+// ---------------------------------------------------------------------------
+// Errors: status code + thread-local message.
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+rbp_status fail(rbp_status st, const std::string& msg);
+
+#define RBP_HIP_CHECK(expr)                                                              \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::rbp::fail(RBP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Device buffer owned by a handle; grows on demand, never shrinks.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    rbp_status reserve(size_t n);
+    void release();
+    template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11).
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__host__ __device__ inline uint32_t u4_get(const U4& v, int w) {
+    return w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
+}
+
+// ---------------------------------------------------------------------------
+// Detector error model handle.
+// ---------------------------------------------------------------------------
+struct LaunchCfg {
+    int waves_per_shot = 0;
+    int state = 0;
+    int max_slots = 0;
+};
+
+}  // namespace rbp
+
+struct rbp_code {
+    int32_t M = 0, N = 0, E = 0, k = 0, nnzO = 0;
+    int32_t max_row_deg = 0, max_col_deg = 0;
+    int device = 0;
+    int num_cus = 0;
+    // device copies
+    rbp::DevBuf row_ptr, col_idx;      // CSR of H: row_ptr[M+1], col_idx[E] (variable of each edge)
+    rbp::DevBuf col_ptr, csc_row, csc_edge;  // CSC of H: col_ptr[N+1], csc_row[E], csc_edge[E] = CSR slot
+    rbp::DevBuf orow_ptr, ocol_idx;    // CSR of O: orow_ptr[k+1], ocol_idx[nnzO]
+    rbp::DevBuf ocol_ptr, orow_idx;    // CSC of O (sampler)
+    // per-call data (cached by content)
+    rbp::DevBuf thr;                   // uint32[N] sampling thresholds
+    std::vector<double> thr_key;
+    rbp::DevBuf lam;                   // float[N] LLRs
+    std::vector<double> lam_key;
+    rbp::DevBuf gtab;                  // float[R][N] relay-leg memory strengths
+    uint64_t gtab_seed = 0;
+    float gtab_lo = 0.f, gtab_hi = 0.f;
+    int32_t gtab_R = -1;
+    rbp::DevBuf queue;                 // work counters of the persistent decoder
+    rbp::DevBuf gstate;                // per-slot state when it does not fit in LDS
+    rbp::DevBuf trace_hit;
+    rbp::LaunchCfg cfg;
+};

@@ -1,0 +1,253 @@
+"""Thin ctypes binding of librbp (the C ABI in include/rbp.h).
+
+Argument marshalling only: every step of sampling and decoding runs in the HIP
+kernels of librbp.  torch provides device memory (tensors) and streams.  torch
+is imported first so that librbp binds to the HIP runtime torch already loaded.
+If librbp.so is missing this module raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librbp.so")
+
+RBP_OK = 0
+_ERRNAMES = {-1: "INVALID_ARG", -2: "SHAPE", -3: "UNSUPPORTED", -4: "OOM", -5: "HIP"}
+
+
+class RbpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"librbp {_ERRNAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class RelayParamsC(ctypes.Structure):
+    _fields_ = [("gamma0", ctypes.c_float), ("gamma_min", ctypes.c_float), ("gamma_max", ctypes.c_float),
+                ("pre_iter", ctypes.c_int32), ("max_iterations", ctypes.c_int32), ("num_sets", ctypes.c_int32),
+                ("stop_nconv", ctypes.c_int32), ("stopping_criterion", ctypes.c_int32),
+                ("gamma_seed", ctypes.c_uint64)]
+
+
+class LaunchConfigC(ctypes.Structure):
+    _fields_ = [("waves_per_shot", ctypes.c_int32), ("state", ctypes.c_int32), ("max_slots", ctypes.c_int32)]
+
+
+SHOT_STATS_DTYPE = np.dtype([("converged", np.uint8), ("nconv", np.uint8), ("path", np.uint8), ("r0", np.uint8),
+                             ("legs", np.uint16), ("r1", np.uint16), ("iters", np.uint32), ("r2", np.uint32),
+                             ("t_start", np.uint64), ("t_end", np.uint64)])
+assert SHOT_STATS_DTYPE.itemsize == 32
+
+
+@dataclasses.dataclass
+class RelayParams:
+    """Relay-BP settings (names as in the paper's Sec. 6.1)."""
+    gamma0: float = 0.125
+    gamma_min: float = -0.24
+    gamma_max: float = 0.66
+    pre_iter: int = 80
+    max_iterations: int = 60
+    num_sets: int = 100
+    stop_nconv: int = 5
+    stopping_criterion: int = 0  # 0 NConv, 1 All
+    gamma_seed: int = 7
+
+    def c(self) -> RelayParamsC:
+        return RelayParamsC(self.gamma0, self.gamma_min, self.gamma_max, self.pre_iter, self.max_iterations,
+                            self.num_sets, self.stop_nconv, self.stopping_criterion, self.gamma_seed)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, u64, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64
+    P = ctypes.POINTER
+    sigs = {
+        "rbp_code_create": [i32, i32, vp, vp, i32, vp, vp, P(vp)],
+        "rbp_code_destroy": [vp],
+        "rbp_code_info": [vp, P(i32), P(i32), P(i32), P(i32), P(i32), P(i32)],
+        "rbp_sample": [vp, vp, u64, u64, u64, vp, vp, vp, vp],
+        "rbp_decode": [vp, vp, vp, u64, P(RelayParamsC), vp, vp, vp, vp, vp],
+        "rbp_decode_multi": [i32, vp, vp, vp, vp, u64, vp, P(RelayParamsC), vp, vp, vp, vp],
+        "rbp_set_launch_config": [vp, P(LaunchConfigC)],
+        "rbp_get_launch_config": [vp, P(LaunchConfigC), P(i32), P(i32)],
+        "rbp_trace": [vp, vp, vp, P(RelayParamsC), vp, i32, i32, i32, vp, vp, P(i32), vp],
+        "rbp_mlp_create": [i32, i32, i32, u64, P(vp)],
+        "rbp_mlp_destroy": [vp],
+        "rbp_mlp_forward": [vp, vp, u64, vp, vp],
+        "rbp_mlp_train_step": [vp, vp, vp, vp, u64, ctypes.c_float, vp, vp],
+        "rbp_mlp_num_params": [vp, P(i64)],
+        "rbp_mlp_get_params": [vp, vp],
+        "rbp_mlp_set_params": [vp, vp],
+    }
+    for name, args in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    L.rbp_last_error.argtypes = []
+    L.rbp_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(status: int):
+    if status != RBP_OK:
+        raise RbpError(status, lib().rbp_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def words(nbits: int) -> int:
+    return (nbits + 31) // 32
+
+
+def csc_of(A: np.ndarray):
+    A = np.asarray(A, dtype=np.uint8)
+    rows, cols = np.nonzero(A.T)
+    ptr = np.zeros(A.shape[1] + 1, dtype=np.int32)
+    np.add.at(ptr, rows + 1, 1)
+    return np.cumsum(ptr).astype(np.int32), cols.astype(np.int32)
+
+
+class Code:
+    """A detector error model handle (rbp_code_create)."""
+
+    def __init__(self, H: np.ndarray, O: np.ndarray):
+        self.M, self.N = H.shape
+        self.k = O.shape[0]
+        cp, ri = csc_of(H)
+        ocp, ori = csc_of(O) if self.k > 0 else (np.zeros(self.N + 1, np.int32), np.zeros(1, np.int32))
+        self.nnz = int(cp[-1])
+        h = ctypes.c_void_p()
+        check(lib().rbp_code_create(self.M, self.N, cp.ctypes.data, ri.ctypes.data, self.k, ocp.ctypes.data,
+                                    ori.ctypes.data, ctypes.byref(h)))
+        self.h = h
+
+    @classmethod
+    def from_dem(cls, dem) -> "Code":
+        return cls(dem.H, dem.O)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rbp_code_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        vals = [ctypes.c_int32() for _ in range(6)]
+        check(lib().rbp_code_info(self.h, *[ctypes.byref(v) for v in vals]))
+        return dict(zip(["M", "N", "nnz", "k", "max_row_deg", "max_col_deg"], [v.value for v in vals]))
+
+    # -- sampling ---------------------------------------------------------
+    def sample(self, priors, shots: int, seed: int, shot_offset: int = 0, errors: bool = False, stream=None,
+               out=None):
+        dev = torch.device("cuda")
+        if out is None:
+            syn = torch.empty((shots, words(self.M)), dtype=torch.int32, device=dev)
+            obs = torch.empty((shots, max(words(self.k), 1)), dtype=torch.int32, device=dev)
+            err = torch.empty((shots, words(self.N)), dtype=torch.int32, device=dev) if errors else None
+        else:
+            syn, obs, err = out
+        pr = _f64(priors)
+        check(lib().rbp_sample(self.h, pr.ctypes.data, shots, seed, shot_offset, _ptr(syn), _ptr(obs), _ptr(err),
+                               _stream(stream)))
+        return syn, obs, err
+
+    # -- decoding ---------------------------------------------------------
+    def decode(self, priors, syndromes: torch.Tensor, params: RelayParams, delta: Optional[torch.Tensor] = None,
+               stats: bool = True, stream=None, out=None):
+        shots = syndromes.shape[0]
+        assert syndromes.dtype == torch.int32 and syndromes.is_contiguous()
+        assert syndromes.shape[1] == words(self.M)
+        if delta is not None:
+            assert delta.dtype == torch.float32 and delta.shape == (shots, self.N) and delta.is_contiguous()
+        dev = syndromes.device
+        if out is None:
+            corr = torch.empty((shots, words(self.N)), dtype=torch.int32, device=dev)
+            obsp = torch.empty((shots, max(words(self.k), 1)), dtype=torch.int32, device=dev)
+            st = torch.empty((shots, 32), dtype=torch.uint8, device=dev) if stats else None
+        else:
+            corr, obsp, st = out
+        pr = _f64(priors)
+        prm = params.c()
+        check(lib().rbp_decode(self.h, pr.ctypes.data, _ptr(syndromes), shots, ctypes.byref(prm), _ptr(delta),
+                               _ptr(corr), _ptr(obsp), _ptr(st), _stream(stream)))
+        return corr, obsp, st
+
+    def trace(self, priors, syndrome: torch.Tensor, params: RelayParams, leg: int, t: int, phase: int = 0,
+              delta: Optional[torch.Tensor] = None, stream=None):
+        dev = syndrome.device
+        Mo = torch.empty(self.N, dtype=torch.float32, device=dev)
+        mu = torch.empty(max(self.nnz, 1), dtype=torch.float32, device=dev)
+        reached = ctypes.c_int32()
+        pr = _f64(priors)
+        prm = params.c()
+        check(lib().rbp_trace(self.h, pr.ctypes.data, _ptr(syndrome), ctypes.byref(prm), _ptr(delta), phase, leg, t,
+                              _ptr(Mo), _ptr(mu), ctypes.byref(reached), _stream(stream)))
+        if not reached.value:
+            return None
+        return Mo.cpu().numpy(), mu[: self.nnz].cpu().numpy()
+
+    def set_launch_config(self, waves_per_shot: int = 0, state: int = 0, max_slots: int = 0):
+        cfg = LaunchConfigC(waves_per_shot, state, max_slots)
+        check(lib().rbp_set_launch_config(self.h, ctypes.byref(cfg)))
+
+    def launch_config(self):
+        cfg = LaunchConfigC()
+        slots, lds = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().rbp_get_launch_config(self.h, ctypes.byref(cfg), ctypes.byref(slots), ctypes.byref(lds)))
+        return dict(waves_per_shot=cfg.waves_per_shot, state=cfg.state, max_slots=cfg.max_slots,
+                    slots=slots.value, lds_bytes=lds.value)
+
+
+def decode_multi(codes: Sequence[Code], priors: Sequence, shot_code: torch.Tensor, shot_index: torch.Tensor,
+                 syndromes: Sequence[torch.Tensor], params: RelayParams, corrections: Sequence[torch.Tensor],
+                 obs_pred: Sequence[torch.Tensor], stats: Optional[torch.Tensor] = None, stream=None):
+    n = len(codes)
+    VP = ctypes.c_void_p * n
+    prs = [_f64(p) for p in priors]
+    pr_arr = VP(*[p.ctypes.data for p in prs])
+    shots = shot_code.shape[0]
+    prm = params.c()
+    check(lib().rbp_decode_multi(n, VP(*[c.h.value for c in codes]), pr_arr, _ptr(shot_code), _ptr(shot_index),
+                                 shots, VP(*[s.data_ptr() for s in syndromes]), ctypes.byref(prm),
+                                 VP(*[c.data_ptr() for c in corrections]), VP(*[o.data_ptr() for o in obs_pred]),
+                                 _ptr(stats), _stream(stream)))
+
+
+def stats_to_numpy(st: torch.Tensor) -> np.ndarray:
+    return st.cpu().numpy().reshape(-1).view(SHOT_STATS_DTYPE)
+
+
+def to_u32(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)

@@ -1,0 +1,71 @@
+"""Host-side checks of the C ABI library (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rbp.h")
+PKG = os.path.join(ROOT, "paper_2607_27644_amd")
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(rbp_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for must in ("rbp_code_create", "rbp_sample", "rbp_decode", "rbp_decode_multi", "rbp_trace",
+                 "rbp_mlp_forward", "rbp_mlp_train_step", "rbp_last_error"):
+        assert must in syms
+
+
+def test_library_exports_every_declared_symbol():
+    lib_path = os.path.join(PKG, "librbp.so")
+    if not os.path.exists(lib_path):
+        pytest.fail("librbp.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(lib_path)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+    lib.rbp_last_error.restype = ctypes.c_char_p
+    assert lib.rbp_last_error() is not None
+
+
+def test_host_validation_without_gpu():
+    """Argument checks run before any device call."""
+    lib = ctypes.CDLL(os.path.join(PKG, "librbp.so"))
+    lib.rbp_last_error.restype = ctypes.c_char_p
+    out = ctypes.c_void_p()
+    i32 = ctypes.c_int32
+    # row with degree 1 -> UNSUPPORTED
+    cp = (i32 * 3)(0, 1, 2)
+    ri = (i32 * 2)(0, 1)
+    assert lib.rbp_code_create(2, 2, cp, ri, 0, None, None, ctypes.byref(out)) == -3
+    # unsorted rows inside a column -> SHAPE
+    cp = (i32 * 2)(0, 2)
+    ri = (i32 * 2)(1, 0)
+    assert lib.rbp_code_create(2, 1, cp, ri, 0, None, None, ctypes.byref(out)) == -2
+    assert b"ascending" in lib.rbp_last_error()
+    # row index out of range -> SHAPE
+    ri = (i32 * 2)(0, 5)
+    assert lib.rbp_code_create(2, 1, cp, ri, 0, None, None, ctypes.byref(out)) == -2
+    # NULL handle -> INVALID_ARG
+    assert lib.rbp_decode(None, None, None, 0, None, None, None, None, None, None) == -1
+
+
+def test_product_never_touches_the_oracle():
+    for dirpath, _, files in os.walk(PKG):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b|orc_|liboracle", txt, re.M), f
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    from paper_2607_27644_amd import rbp
+    monkeypatch.setattr(rbp, "_lib", None)
+    monkeypatch.setattr(rbp, "LIB_PATH", os.path.join(PKG, "does_not_exist.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        rbp.lib()
