@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark of the Monte-Carlo Relay-BP path on one MI355X.
+
+One step = sample a batch of shots of the phenomenological ZSZ-LP-160 model
+(9 rounds, 576 detectors x 1952 mechanisms, priors 1e-3) on the GPU, decode it
+with Relay-BP (gamma0 0.125, pre_iter 80, max_iterations 60, 100 relay legs,
+stop_nconv 5, gamma in [-0.24, 0.66]), copy the predicted observables and
+per-shot statistics back and count block failures.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "decoded shots/s + p50/p99 latency at fixed LER: Relay-BP vs learned proposal"
+LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--shots", type=int, default=100000)
+    ap.add_argument("--workload", default="phen160")
+    ap.add_argument("--seed", type=int, default=20260101)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sequential", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("rbp_decode.hip", "rbp_common.h"):
+        h.update(open(os.path.join(ROOT, "paper_2607_27644_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, launch_shots: int):
+    """HBM bytes per decode launch from the committed counter summary, if it was
+    taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"relay_bp_{workload}_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("shots") != launch_shots:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(dem, shots_total: int, seed: int, params, target_s: float):
+    import numpy as np
+
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    g = oracle.Graph(dem.H, dem.O)
+    op = oracle.RelayParams(**{k: getattr(params, k) for k in oracle.RelayParams.__dataclass_fields__})
+
+    def run(n):
+        t0 = time.perf_counter()
+        syn, obs, _ = oracle.sample(g, dem.priors, n, seed)
+        r = oracle.decode(g, dem.priors, syn, op, nthreads=threads)
+        return time.perf_counter() - t0, r
+
+    dt, _ = run(2000)
+    n = int(min(shots_total, max(2000, 2000 * target_s / max(dt, 1e-3))))
+    dt, r = run(n)
+    return {"value": n / dt, "unit": "shots/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of the {shots_total} shots (same seed): oracle sampling + Relay-BP decode "
+                      f"on {threads} threads, {dt:.1f} s",
+            "mean_iters_per_shot": float(np.mean(r["iters"]))}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; shots shard across GPUs by "
+                                   "shot_offset with no communication, so run one process per GPU "
+                                   "(multi-GPU launch is not part of this build)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2607_27644_amd import rbp, stats, workloads
+
+    torch.cuda.set_device(0)
+    dem = workloads.workload(args.workload)
+    code = rbp.Code.from_dem(dem)
+    params = rbp.RelayParams()
+    S = args.shots
+    dev = torch.device("cuda")
+    syn = torch.empty((S, rbp.words(dem.M)), dtype=torch.int32, device=dev)
+    obs = torch.empty((S, max(rbp.words(dem.k), 1)), dtype=torch.int32, device=dev)
+    corr = torch.empty((S, rbp.words(dem.N)), dtype=torch.int32, device=dev)
+    obsp = torch.empty_like(obs)
+    st = torch.empty((S, 32), dtype=torch.uint8, device=dev)
+    h_obs = torch.empty(obs.shape, dtype=torch.int32, pin_memory=True)
+    h_obsp = torch.empty(obs.shape, dtype=torch.int32, pin_memory=True)
+    h_st = torch.empty(st.shape, dtype=torch.uint8, pin_memory=True)
+
+    ev = []
+
+    def step(i: int, record: bool):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)] if record else None
+        if record:
+            e[0].record()
+        code.sample(dem.priors, S, args.seed + i, out=(syn, obs, None))
+        if record:
+            e[1].record()
+        code.decode(dem.priors, syn, params, out=(corr, obsp, st))
+        if record:
+            e[2].record()
+            ev.append(e)
+        h_obs.copy_(obs, non_blocking=True)
+        h_obsp.copy_(obsp, non_blocking=True)
+        h_st.copy_(st, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        s = h_st.numpy().reshape(-1).view(rbp.SHOT_STATS_DTYPE)
+        fails = stats.block_failures(h_obsp.numpy(), h_obs.numpy(), s["converged"])
+        return int(fails.sum()), s
+
+    for i in range(args.warmup):
+        step(1000 + i, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fail_total, last = 0, None
+    for i in range(args.steps):
+        f, last = step(i, True)
+        fail_total += f
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+    value = S * args.steps / wall
+
+    dec_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    smp_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    iters = last["iters"].astype(np.int64)
+    B_it = 8 * dem.nnz + 8 * dem.N  # algorithmic bytes of one flooding iteration of one shot
+    alg_bytes = float(iters.sum()) * B_it
+    achieved = alg_bytes / (dec_ms * 1e-3) / 1e9
+    traffic = load_traffic(args.workload, S)
+
+    ticks = (last["t_end"] - last["t_start"]).astype(np.float64)
+    service_us = ticks * 0.01  # 100 MHz device wall clock
+    nz = last["path"] != 3
+    out = {
+        "metric": METRIC, "value": value, "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": f"phenomenological DEM of ZSZ-LP-160 [[160,32,10]] over 9 rounds "
+                        f"({dem.M} detectors x {dem.N} mechanisms, nnz {dem.nnz}), priors 1e-3, "
+                        f"{S} shots per step, Relay-BP gamma0=0.125 pre_iter=80 max_iterations=60 "
+                        f"num_sets=100 stop_nconv=5 gamma_dist=[-0.24,0.66], FP32 messages",
+            "shots_per_step": S, "path": "plain Relay-BP",
+        },
+        "decode_only_shots_per_s": S / (dec_ms * 1e-3),
+        "decode_kernel_ms": dec_ms, "sample_kernel_ms": smp_ms,
+        "latency_us": {"batched_service_time": stats.percentiles(service_us),
+                       "batched_service_time_nonzero_syndrome": stats.percentiles(service_us[nz])},
+        "ler": stats.ler_summary(fail_total, S * args.steps, dem.rounds, dem.k),
+        "mean_iters_per_shot": float(iters.mean()), "mean_legs_per_shot": float(last["legs"].mean()),
+        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / LDS_PEAK_GBS, "traffic": traffic,
+                     "kernel": "relay_bp_kernel", "algorithmic_bytes_per_shot_iteration": B_it,
+                     "shot_iterations_per_launch": int(iters.sum())},
+        "launch": code.launch_config(),
+    }
+
+    if not args.no_sequential:
+        # the paper's latency mode: one shot per decode call, host clock around each
+        one_syn = syn[:1]
+        lat = []
+        c1, o1, s1 = corr[:1], obsp[:1], st[:1]
+        for i in range(400):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            code.decode(dem.priors, syn[i:i + 1], params, out=(c1, o1, s1))
+            torch.cuda.synchronize()
+            lat.append(1e6 * (time.perf_counter() - ta))
+        del one_syn
+        out["latency_us"]["sequential_single_shot"] = stats.percentiles(np.array(lat))
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(dem, S, args.seed, params, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
