@@ -75,14 +75,17 @@ struct rbp_code {
     int device = 0;
     int num_cus = 0;
     // device copies
-    rbp::DevBuf row_ptr, col_idx;      // CSR of H: row_ptr[M+1], col_idx[E] (variable of each edge)
-    rbp::DevBuf col_ptr, csc_row, csc_edge;  // CSC of H: col_ptr[N+1], csc_row[E], csc_edge[E] = CSR slot
+    int32_t P = 12;                         // row stride of the padded tables (12 or 32)
+    rbp::DevBuf row_ptr, col_idx;           // CSR of H: row_ptr[M+1], col_idx[E]
+    rbp::DevBuf rpos;                       // [M][P] CSC slot of each edge of a row, -1 padded
+    rbp::DevBuf col_ptr, csc_row;           // CSC of H: col_ptr[N+1], csc_row[E]
     rbp::DevBuf orow_ptr, ocol_idx;    // CSR of O: orow_ptr[k+1], ocol_idx[nnzO]
     rbp::DevBuf ocol_ptr, orow_idx;    // CSC of O (sampler)
     // per-call data (cached by content)
     rbp::DevBuf thr;                   // uint32[N] sampling thresholds
     std::vector<double> thr_key;
     rbp::DevBuf lam;                   // float[N] LLRs
+    rbp::DevBuf m1;                    // float[M][P] first-iteration message magnitudes (row layout)
     std::vector<double> lam_key;
     rbp::DevBuf gtab;                  // float[R][N] relay-leg memory strengths
     uint64_t gtab_seed = 0;

@@ -9,18 +9,16 @@
 //                      and observable columns into LDS bit arrays.
 //  * relay_bp_kernel   persistent: each workgroup is a shot slot that pulls shots
 //                      from a device queue until none are left, so a shot that
-//                      converges early frees its slot at once.  The slot's
-//                      per-shot state (marginals M[N], check->variable messages
-//                      mu[nnz] in CSR order) sits in LDS when it fits, else in a
-//                      per-slot device buffer.  One flooding iteration is a check
-//                      sweep over CSR rows (min / second-min / sign parity kept in
-//                      registers; a check's new messages are written to its own
-//                      contiguous CSR slots) and a variable sweep over CSC columns
-//                      (memory prior, marginal, hard decision).  The syndrome of
-//                      the hard decision is tracked incrementally: a variable
-//                      whose decision flips XORs its checks' parity bits with LDS
-//                      atomics and the workgroup keeps the count of unsatisfied
-//                      checks, so convergence costs no extra sweep.
+//                      converges early frees its slot at once.  The slot's state
+//                      is one float per edge, in place (see below), in LDS when
+//                      it fits, else in a per-slot device buffer; the threads'
+//                      index lists and the marginals of their variables stay in
+//                      registers for the life of the kernel.  The syndrome of the
+//                      hard decision and the weight of the current solution are
+//                      tracked incrementally: a variable whose decision flips XORs
+//                      its checks' parity bits with LDS atomics and moves the
+//                      weight, so convergence and solution weights cost no extra
+//                      sweep or reduction.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -152,20 +150,29 @@ __global__ void zero_u64_kernel(unsigned long long* p, int n) {
 
 // ---------------------------------------------------------------------------
 // Persistent Relay-BP
+//
+// State of a shot slot: one float per Tanner-graph edge, X[E], in CSC order
+// (the edges of a variable are contiguous, checks ascending).  The check sweep
+// reads nu_{j->i} from X and overwrites it with mu_{i->j}; the variable sweep
+// reads mu, forms the marginal M_j and overwrites X with nu_{j->i} = M_j - mu.
+// So the two sweeps work in place on a single array, and the marginals live in
+// the registers of the thread that owns the variable (or in Mg[N] when the
+// index lists are not cached in registers).  The first iteration of a plain
+// leg reads no state: nu(0) = Lambda, so mu(1) = (-1)^sigma_i * (min of the
+// other Lambda of the row), a per-model table m1[E] computed once per priors.
 // ---------------------------------------------------------------------------
 constexpr int kMaxModels = 8;
 
 struct DecodeModel {
-    int32_t M, N, E, k, WM, WN, WK;
-    const int32_t* row_ptr;
-    const int32_t* col_idx;
-    const int32_t* col_ptr;
-    const int32_t* csc_row;
-    const int32_t* csc_edge;
-    const int32_t* orow_ptr;
-    const int32_t* ocol_idx;
-    const float* lam;
-    const float* gtab;
+    int32_t M, N, E, k, WM, WN, WK, P;  // P: row stride of rpos/m1p (<= RD of the kernel)
+    const int32_t* rpos;      // [M][P] CSC slot of each edge of a row (columns ascending), -1 padded
+    const int32_t* col_ptr;   // [N+1]
+    const int32_t* csc_row;   // [E] check of each CSC slot
+    const int32_t* ocol_ptr;  // [N+1] observables, CSC
+    const int32_t* orow_idx;
+    const float* lam;         // [N] Lambda
+    const float* m1p;         // [M][P] first-iteration message magnitudes, row layout
+    const float* gtab;        // [R][N] relay-leg memory strengths
     const uint32_t* syn;
     uint32_t* corr;
     uint32_t* obsp;
@@ -182,8 +189,8 @@ struct DecodeLaunch {
     unsigned long long* queue;
     float* gstate;
     int64_t gstate_stride;
-    int32_t Nmax;
-    int32_t off_sig, off_par, off_best;  // byte offsets in dynamic LDS
+    int32_t Emax;
+    int32_t off_sig, off_par, off_best, off_obs;  // byte offsets in dynamic LDS
     float gamma0;
     int32_t T0, Tr, R, S, crit;
     int32_t trace_on, trace_phase, trace_leg, trace_t;
@@ -191,6 +198,25 @@ struct DecodeLaunch {
     float* trace_mu;
     int32_t* trace_hit;
 };
+
+// first-iteration magnitudes in the padded row layout:
+// m1p[i*P + p] = min over the other variables j' of row i of Lambda_j'
+__global__ void first_message_kernel(const int32_t* row_ptr, const int32_t* col_idx, const float* lam, float* m1p,
+                                     int32_t M, int32_t P) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const int rs = row_ptr[i], re = row_ptr[i + 1];
+    float min1 = INFINITY, min2 = INFINITY;
+    for (int e = rs; e < re; ++e) {
+        const float av = fabsf(lam[col_idx[e]]);
+        min2 = __builtin_amdgcn_fmed3f(min1, min2, av);
+        min1 = fminf(min1, av);
+    }
+    for (int e = rs; e < re; ++e) {
+        const float av = fabsf(lam[col_idx[e]]);
+        m1p[(int64_t)i * P + (e - rs)] = (av == min1) ? min2 : min1;
+    }
+}
 
 template <class T>
 __device__ __forceinline__ T block_sum(T v, T* red) {
@@ -205,55 +231,146 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
     return s;
 }
 
-// Packs the hard decisions [M_j < 0] into bit words with one ballot per wave.
-__device__ __forceinline__ void capture_decisions(const float* Ms, uint32_t* bits, int N, int WN) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int jb = wid * 64; jb < N; jb += blockDim.x) {
-        const int j = jb + lane;
-        const bool neg = j < N && Ms[j] < 0.0f;
-        const unsigned long long b = __ballot(neg);
-        if (lane == 0) {
-            bits[jb >> 5] = (uint32_t)b;
-            if ((jb >> 5) + 1 < WN) bits[(jb >> 5) + 1] = (uint32_t)(b >> 32);
+// One check row of the min-sum update, in place on X.  pos[p] is the CSC slot
+// of the row's p-th edge; slots past the row's degree hold E, the index of a
+// read-only +inf cell (neutral for both minima and for the sign product), and
+// their results go to the write-only cell E + 1.  nu -> mu with
+//   mu_p = (-1)^sigma * prod_{q != p} s(nu_q) * min_{q != p} |nu_q|.
+// The sign product is the XOR of the IEEE sign bits (nu is never -0: it is a
+// difference of floats or a positive prior, and x - x = +0); |nu| is compared as
+// an unsigned integer, which orders non-negative floats exactly as the floats;
+// the minimum over the others is the second minimum exactly when |nu_p| is the
+// first (with a tie both are equal).
+template <int RD>
+__device__ __forceinline__ void check_row(float* X, const int (&pos)[RD], int E, uint32_t sbit, bool first,
+                                          const float (&m1v)[RD]) {
+    const int wdummy = E + 1;
+    if (first) {
+#pragma unroll
+        for (int p = 0; p < RD; ++p) {
+            const int w = pos[p] == E ? wdummy : pos[p];
+            X[w] = __uint_as_float(__float_as_uint(m1v[p]) | sbit);
         }
+        return;
+    }
+    uint32_t nu[RD];
+    uint32_t sgn = sbit;
+    uint32_t min1 = 0x7f800000u, min2 = 0x7f800000u;
+#pragma unroll
+    for (int p = 0; p < RD; ++p) {
+        const uint32_t v = __float_as_uint(X[pos[p]]);
+        nu[p] = v;
+        sgn ^= v;
+        const uint32_t av = v & 0x7fffffffu;
+        const uint32_t lo2 = min2 < av ? min2 : av;
+        min2 = min1 > lo2 ? min1 : lo2;  // median of (min1, min2, av) given min1 <= min2
+        min1 = min1 < av ? min1 : av;
+    }
+#pragma unroll
+    for (int p = 0; p < RD; ++p) {
+        const uint32_t av = nu[p] & 0x7fffffffu;
+        const uint32_t mag = (av == min1) ? min2 : min1;
+        const int w = pos[p] == E ? wdummy : pos[p];
+        X[w] = __uint_as_float(mag | ((sgn ^ nu[p]) & 0x80000000u));
     }
 }
 
-template <int MAXDEG, bool LDS_STATE>
-__global__ void __launch_bounds__(1024) relay_bp_kernel(const DecodeLaunch a) {
+// A variable whose hard decision flips toggles the parity of its checks and
+// moves the solution weight by +-Lambda_j (double; sums of FP32 values of
+// this range are exact, so the order of the atomics does not matter).
+__device__ __forceinline__ void flip_variable(const int32_t* csc_row, int s0, int d, bool now_neg, float lamj,
+                                              uint32_t* par, int& dcount, double& dW) {
+    for (int e = s0; e < s0 + d; ++e) {
+        const int i = csc_row[e];
+        const uint32_t bit = 1u << (i & 31);
+        const uint32_t old = atomicXor(par + (i >> 5), bit);
+        dcount += (old & bit) ? -1 : 1;
+    }
+    dW += now_neg ? (double)lamj : -(double)lamj;
+}
+
+// Hides a register value from loop-invariant code motion: address arithmetic on
+// the cached index lists is then redone per sweep (one add) instead of being
+// hoisted out of the persistent loop as one 64-bit address per edge.
+__device__ __forceinline__ void opaque(int& x) { asm volatile("" : "+v"(x)); }
+
+template <int RD, int CD, int CPT, int VPT, bool LDS_STATE, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES, (WAVES >= 4 ? 4 : WAVES)) relay_bp_kernel(const DecodeLaunch a) {
+    constexpr bool CACHED = CPT > 0;
+    constexpr int CP = CACHED ? CPT : 1;
+    constexpr int VP = CACHED ? VPT : 1;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long sh_shot;
     __shared__ int sh_count;
-    __shared__ double sh_red_d[16];
+    __shared__ double sh_W;
     __shared__ int sh_red_i[16];
 
-    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63;
-    float* Ms;
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wid = tid >> 6;
+    float* X;
     if constexpr (LDS_STATE) {
-        Ms = reinterpret_cast<float*>(smem);
+        X = reinterpret_cast<float*>(smem);
     } else {
-        Ms = a.gstate + (int64_t)blockIdx.x * a.gstate_stride;
+        X = a.gstate + (int64_t)blockIdx.x * a.gstate_stride;
     }
-    float* mu = Ms + a.Nmax;
+    float* Mg = X + a.Emax + 4;  // marginals of the uncached variant (after the two dummy cells)
     uint32_t* sig = reinterpret_cast<uint32_t*>(smem + a.off_sig);
     uint32_t* par = reinterpret_cast<uint32_t*>(smem + a.off_par);
     uint32_t* best = reinterpret_cast<uint32_t*>(smem + a.off_best);
+    uint32_t* obw = reinterpret_cast<uint32_t*>(smem + a.off_obs);
+
+    // Register caches of the persistent thread: its checks tid + c*nth and its
+    // variables tid + v*nth never change, so their index lists are loaded once.
+    int cpos[CP][RD];
+    int cdeg[CP];
+    int vstart[VP], vdeg[VP];
+    float vlam[VP], Mreg[VP], greg[VP];
+    if constexpr (CACHED) {
+        const DecodeModel m0 = a.m[0];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int i = tid + c * nth;
+            cdeg[c] = 0;
+#pragma unroll
+            for (int p = 0; p < RD; ++p) cpos[c][p] = (i < m0.M && p < m0.P) ? m0.rpos[(int64_t)i * m0.P + p] : m0.E;
+        }
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) {
+            const int j = tid + v * nth;
+            int s0 = 0, d = 0;
+            float l = 0.f;
+            if (j < m0.N) {
+                s0 = m0.col_ptr[j];
+                d = m0.col_ptr[j + 1] - s0;
+                l = m0.lam[j];
+            }
+            vstart[v] = s0;
+            vdeg[v] = d;
+            vlam[v] = l;
+            Mreg[v] = 0.f;
+            greg[v] = 0.f;
+        }
+    }
 
     for (;;) {
-        if (tid == 0) sh_shot = atomicAdd(a.queue, 1ull);
+        if (tid == 0) {
+            sh_shot = atomicAdd(a.queue, 1ull);
+            sh_count = 0;
+            sh_W = 0.0;
+        }
         __syncthreads();
-        const unsigned long long s = sh_shot;
+        // the shot, its model and its row are uniform over the workgroup: keep them scalar
+        const unsigned long long s = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(sh_shot >> 32)) << 32) |
+                                     __builtin_amdgcn_readfirstlane((uint32_t)sh_shot);
         if (s >= a.shots) break;
         const uint64_t t_start = wall_clock64();
-        const int mi = a.shot_code ? (int)a.shot_code[s] : 0;
-        const DecodeModel& m = a.m[mi];
-        const uint64_t row = a.shot_index ? (uint64_t)a.shot_index[s] : (uint64_t)s;
+        const int mi = (CACHED || !a.shot_code) ? 0 : __builtin_amdgcn_readfirstlane((int)a.shot_code[s]);
+        const DecodeModel m = a.m[mi];
+        const uint64_t row = a.shot_index ? (uint64_t)__builtin_amdgcn_readfirstlane(a.shot_index[s]) : (uint64_t)s;
         const int M = m.M, N = m.N, WM = m.WM, WN = m.WN;
         const float* lam = m.lam;
         const float* dlt = a.delta ? a.delta + row * (uint64_t)N : nullptr;
 
-        // syndrome into LDS, parity := sigma, count of unsatisfied checks
-        if (tid == 0) sh_count = 0;
+        if (tid == 0) X[m.E] = INFINITY;  // read-only cell of the padded row slots
         int pc = 0;
         for (int w = tid; w < WM; w += nth) {
             const uint32_t v = m.syn[row * WM + w];
@@ -261,15 +378,14 @@ __global__ void __launch_bounds__(1024) relay_bp_kernel(const DecodeLaunch a) {
             par[w] = v;
             pc += __popc(v);
         }
-        const int base_sig = block_sum<int>(pc, sh_red_i);
+        const int base = block_sum<int>(pc, sh_red_i);
 
         int nconv = 0, legs = 0, iters = 0, path = 0;
         bool have_best = false;
         double bestW = 0.0;
         bool traced = false;
-        int base = base_sig;
 
-        if (base_sig == 0) {
+        if (base == 0) {
             path = 3;
             have_best = true;
             for (int w = tid; w < WN; w += nth) best[w] = 0u;
@@ -281,27 +397,44 @@ __global__ void __launch_bounds__(1024) relay_bp_kernel(const DecodeLaunch a) {
                 if (phase == 0 && first_phase == 1) {
                     // plain Relay-BP from scratch after a failed proposal
                     __syncthreads();
-                    if (tid == 0) sh_count = 0;
+                    if (tid == 0) {
+                        sh_count = 0;
+                        sh_W = 0.0;
+                    }
                     for (int w = tid; w < WM; w += nth) par[w] = sig[w];
                     __syncthreads();
-                    base = base_sig;
                 }
-                // M(0) = Lambda (or Lambda + delta); parity := sigma xor H [M(0) < 0]
-                int dc = 0;
-                for (int j = tid; j < N; j += nth) {
-                    const float v = prop ? lam[j] + dlt[j] : lam[j];
-                    Ms[j] = v;
-                    if (v < 0.0f) {
-                        for (int e = m.col_ptr[j]; e < m.col_ptr[j + 1]; ++e) {
-                            const int i = m.csc_row[e];
-                            const uint32_t bit = 1u << (i & 31);
-                            const uint32_t old = atomicXor(par + (i >> 5), bit);
-                            dc += (old & bit) ? -1 : 1;
+                // M(0) = Lambda (or Lambda + delta; then also nu(0) = Lambda + delta on every edge)
+                {
+                    int dc = 0;
+                    double dW = 0.0;
+                    if constexpr (CACHED) {
+#pragma unroll
+                        for (int v = 0; v < VPT; ++v) {
+                            const int j = tid + v * nth;
+                            if (j < N) {
+                                const float x = prop ? vlam[v] + dlt[j] : vlam[v];
+                                Mreg[v] = x;
+                                if (prop)
+                                    for (int e = vstart[v]; e < vstart[v] + vdeg[v]; ++e) X[e] = x;
+                                if (x < 0.0f) flip_variable(m.csc_row, vstart[v], vdeg[v], true, vlam[v], par, dc, dW);
+                            }
+                        }
+                    } else {
+                        for (int j = tid; j < N; j += nth) {
+                            const float x = prop ? lam[j] + dlt[j] : lam[j];
+                            Mg[j] = x;
+                            if (prop) {
+                                const int s0 = m.col_ptr[j], d = m.col_ptr[j + 1] - s0;
+                                for (int e = s0; e < s0 + d; ++e) X[e] = x;
+                                if (x < 0.0f) flip_variable(m.csc_row, s0, d, true, lam[j], par, dc, dW);
+                            }
                         }
                     }
+                    if (dc) atomicAdd(&sh_count, dc);
+                    if (dW != 0.0) atomicAdd(&sh_W, dW);
+                    __syncthreads();
                 }
-                if (dc) atomicAdd(&sh_count, dc);
-                __syncthreads();
 
                 const int nlegs = prop ? 0 : a.R;
                 for (int leg = 0; leg <= nlegs; ++leg) {
@@ -311,68 +444,152 @@ __global__ void __launch_bounds__(1024) relay_bp_kernel(const DecodeLaunch a) {
                     const float* gam = leg0 ? nullptr : m.gtab + (int64_t)(leg - 1) * N;
                     bool conv = false;
                     ++legs;
+                    if constexpr (CACHED) {
+#pragma unroll
+                        for (int v = 0; v < VPT; ++v) {
+                            const int j = tid + v * nth;
+                            greg[v] = (leg0 || j >= N) ? a.gamma0 : gam[j];
+                        }
+                    }
                     for (int t = 1; t <= T; ++t) {
-                        const bool first = t == 1;
-                        // ---- check sweep: mu(t) from nu(t-1) = M(t-1) - mu(t-1) (or the priors at t = 1)
-                        for (int i = tid; i < M; i += nth) {
-                            const int rs = m.row_ptr[i];
-                            const int deg = m.row_ptr[i + 1] - rs;
-                            uint32_t sgn = ((sig[i >> 5] >> (i & 31)) & 1u) << 31;
-                            float min1 = INFINITY, min2 = INFINITY;
-                            float nu[MAXDEG];
+                        const bool first_plain = t == 1 && !lp;
+                        // ---- check sweep
+                        if constexpr (CACHED) {
 #pragma unroll
-                            for (int p = 0; p < MAXDEG; ++p) {
-                                if (p < deg) {
-                                    const int j = m.col_idx[rs + p];
-                                    float v;
-                                    if (first) {
-                                        v = lp ? lam[j] + dlt[j] : lam[j];
-                                    } else {
-                                        v = Ms[j] - mu[rs + p];
-                                    }
-                                    nu[p] = v;
-                                    sgn ^= __float_as_uint(v);
-                                    const float av = fabsf(v);
-                                    min2 = __builtin_amdgcn_fmed3f(min1, min2, av);
-                                    min1 = fminf(min1, av);
+                            for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+                                for (int p = 0; p < RD; ++p) opaque(cpos[c][p]);
+                                const int i = tid + c * nth;
+                                if (i < M) {
+                                    float m1v[RD];
+#pragma unroll
+                                    for (int p = 0; p < RD; ++p)
+                                        m1v[p] = (first_plain && p < m.P) ? m.m1p[(int64_t)i * m.P + p] : 0.f;
+                                    check_row<RD>(X, cpos[c], m.E, ((sig[i >> 5] >> (i & 31)) & 1u) << 31, first_plain, m1v);
                                 }
+                                __builtin_amdgcn_sched_barrier(0);
                             }
+                        } else {
+                            // rounds of CR rows per thread: the position lists of all
+                            // rounds are loaded before any row is processed
+                            constexpr int CR = RD <= 12 ? 2 : 1;
+                            static_assert(RD % 4 == 0, "row stride must be a multiple of 4");
+                            for (int i0 = tid; i0 < M; i0 += CR * nth) {
+                                int pos[CR][RD];
+                                float m1v[CR][RD];
 #pragma unroll
-                            for (int p = 0; p < MAXDEG; ++p) {
-                                if (p < deg) {
-                                    const float av = fabsf(nu[p]);
-                                    const float mag = (av == min1) ? min2 : min1;
-                                    const uint32_t sb = (sgn ^ __float_as_uint(nu[p])) & 0x80000000u;
-                                    mu[rs + p] = __uint_as_float(__float_as_uint(mag) | sb);
+                                for (int r = 0; r < CR; ++r) {
+                                    const int i = i0 + r * nth;
+                                    const uint32_t b = (uint32_t)(i < M ? i : 0) * (uint32_t)RD;
+                                    const int4* pp = reinterpret_cast<const int4*>(m.rpos + b);
+                                    const float4* mp = reinterpret_cast<const float4*>(m.m1p + b);
+#pragma unroll
+                                    for (int q = 0; q < RD / 4; ++q) {
+                                        const int4 v = pp[q];
+                                        pos[r][4 * q] = v.x;
+                                        pos[r][4 * q + 1] = v.y;
+                                        pos[r][4 * q + 2] = v.z;
+                                        pos[r][4 * q + 3] = v.w;
+                                        if (first_plain) {
+                                            const float4 f = mp[q];
+                                            m1v[r][4 * q] = f.x;
+                                            m1v[r][4 * q + 1] = f.y;
+                                            m1v[r][4 * q + 2] = f.z;
+                                            m1v[r][4 * q + 3] = f.w;
+                                        } else {
+                                            m1v[r][4 * q] = m1v[r][4 * q + 1] = m1v[r][4 * q + 2] = m1v[r][4 * q + 3] = 0.f;
+                                        }
+                                    }
+                                }
+#pragma unroll
+                                for (int r = 0; r < CR; ++r) {
+                                    const int i = i0 + r * nth;
+                                    if (i < M)
+                                        check_row<RD>(X, pos[r], m.E, ((sig[i >> 5] >> (i & 31)) & 1u) << 31, first_plain,
+                                                      m1v[r]);
                                 }
                             }
                         }
                         __syncthreads();
-                        // ---- variable sweep: memory prior, marginal, decision flips
+                        // ---- variable sweep
+                        const bool tr = a.trace_on && phase == a.trace_phase && leg == a.trace_leg && t == a.trace_t;
                         int dcount = 0;
-                        for (int j = tid; j < N; j += nth) {
-                            const float lt = lp ? lam[j] + dlt[j] : lam[j];
-                            const float g = leg0 ? a.gamma0 : gam[j];
-                            const float mo = Ms[j];
-                            float acc = __builtin_fmaf(g, mo - lt, lt);
-                            const int e0 = m.col_ptr[j], e1 = m.col_ptr[j + 1];
-                            for (int e = e0; e < e1; ++e) acc = acc + mu[m.csc_edge[e]];
-                            Ms[j] = acc;
-                            if ((acc < 0.0f) != (mo < 0.0f)) {
-                                for (int e = e0; e < e1; ++e) {
-                                    const int i = m.csc_row[e];
-                                    const uint32_t bit = 1u << (i & 31);
-                                    const uint32_t old = atomicXor(par + (i >> 5), bit);
-                                    dcount += (old & bit) ? -1 : 1;
+                        double dW = 0.0;
+                        if constexpr (CACHED) {
+#pragma unroll
+                            for (int v = 0; v < VPT; ++v) {
+                                opaque(vstart[v]);
+                                opaque(vdeg[v]);
+                                const int j = tid + v * nth;
+                                if (j < N) {
+                                    const float lt = lp ? vlam[v] + dlt[j] : vlam[v];
+                                    const float mo = Mreg[v];
+                                    float acc = __builtin_fmaf(greg[v], mo - lt, lt);
+                                    const int s0 = vstart[v], d = vdeg[v];
+                                    float mu[CD];
+#pragma unroll
+                                    for (int e = 0; e < CD; ++e)
+                                        if (e < d) mu[e] = X[s0 + e];
+#pragma unroll
+                                    for (int e = 0; e < CD; ++e)
+                                        if (e < d) acc = acc + mu[e];
+#pragma unroll
+                                    for (int e = 0; e < CD; ++e)
+                                        if (e < d) X[s0 + e] = acc - mu[e];
+                                    if (tr) {
+                                        a.trace_M[j] = acc;
+#pragma unroll
+                                        for (int e = 0; e < CD; ++e)
+                                            if (e < d) a.trace_mu[s0 + e] = mu[e];
+                                    }
+                                    Mreg[v] = acc;
+                                    if ((acc < 0.0f) != (mo < 0.0f))
+                                        flip_variable(m.csc_row, s0, d, acc < 0.0f, vlam[v], par, dcount, dW);
+                                }
+                                __builtin_amdgcn_sched_barrier(0);
+                            }
+                        } else {
+                            // rounds of VR variables per thread, scalars of all rounds loaded first
+                            constexpr int VR = 4;
+                            for (int j0 = tid; j0 < N; j0 += VR * nth) {
+                                int s0[VR], dg[VR];
+                                float lt[VR], g[VR], mo[VR];
+#pragma unroll
+                                for (int r = 0; r < VR; ++r) {
+                                    const int j = j0 + r * nth;
+                                    const uint32_t jj = j < N ? (uint32_t)j : 0u;
+                                    s0[r] = m.col_ptr[jj];
+                                    dg[r] = j < N ? m.col_ptr[jj + 1u] - s0[r] : 0;
+                                    lt[r] = lp ? lam[jj] + dlt[jj] : lam[jj];
+                                    g[r] = leg0 ? a.gamma0 : gam[jj];
+                                    mo[r] = Mg[jj];
+                                }
+#pragma unroll
+                                for (int r = 0; r < VR; ++r) {
+                                    const int j = j0 + r * nth;
+                                    if (j < N) {
+                                        float acc = __builtin_fmaf(g[r], mo[r] - lt[r], lt[r]);
+                                        const uint32_t b = (uint32_t)s0[r];
+                                        const int d = dg[r];
+                                        for (uint32_t e = b; e < b + d; ++e) acc = acc + X[e];
+                                        for (uint32_t e = b; e < b + d; ++e) {
+                                            const float mu = X[e];
+                                            if (tr) a.trace_mu[e] = mu;
+                                            X[e] = acc - mu;
+                                        }
+                                        if (tr) a.trace_M[j] = acc;
+                                        Mg[j] = acc;
+                                        if ((acc < 0.0f) != (mo[r] < 0.0f))
+                                            flip_variable(m.csc_row, b, d, acc < 0.0f, lam[j], par, dcount, dW);
+                                    }
                                 }
                             }
                         }
                         if (dcount) atomicAdd(&sh_count, dcount);
+                        if (dW != 0.0) atomicAdd(&sh_W, dW);
                         __syncthreads();
                         ++iters;
-                        if (a.trace_on && phase == a.trace_phase && leg == a.trace_leg && t == a.trace_t) {
-                            for (int j = tid; j < N; j += nth) a.trace_M[j] = Ms[j];
-                            for (int e = tid; e < m.E; e += nth) a.trace_mu[e] = mu[m.csc_edge[e]];
+                        if (tr) {
                             if (tid == 0) *a.trace_hit = 1;
                             traced = true;
                             break;
@@ -384,14 +601,33 @@ __global__ void __launch_bounds__(1024) relay_bp_kernel(const DecodeLaunch a) {
                     }
                     if (traced) break;
                     if (conv) {
-                        double wsum = 0.0;
-                        for (int j = tid; j < N; j += nth)
-                            if (Ms[j] < 0.0f) wsum += (double)lam[j];
-                        const double W = block_sum<double>(wsum, sh_red_d);
+                        const double W = sh_W;
                         if (!have_best || W < bestW) {
                             bestW = W;
                             have_best = true;
-                            capture_decisions(Ms, best, N, WN);
+                            // best := current hard decision (one ballot per 64 variables)
+                            if constexpr (CACHED) {
+#pragma unroll
+                                for (int v = 0; v < VPT; ++v) {
+                                    const int jb = wid * 64 + v * nth;
+                                    if (jb < N) {
+                                        const unsigned long long b = __ballot(jb + lane < N && Mreg[v] < 0.0f);
+                                        if (lane == 0) {
+                                            best[jb >> 5] = (uint32_t)b;
+                                            if ((jb >> 5) + 1 < WN) best[(jb >> 5) + 1] = (uint32_t)(b >> 32);
+                                        }
+                                    }
+                                }
+                            } else {
+                                for (int jb = wid * 64; jb < N; jb += nth) {
+                                    const int j = jb + lane;
+                                    const unsigned long long b = __ballot(j < N && Mg[j] < 0.0f);
+                                    if (lane == 0) {
+                                        best[jb >> 5] = (uint32_t)b;
+                                        if ((jb >> 5) + 1 < WN) best[(jb >> 5) + 1] = (uint32_t)(b >> 32);
+                                    }
+                                }
+                            }
                         }
                         ++nconv;
                         if (a.crit == 0 && nconv >= a.S) break;
@@ -406,28 +642,53 @@ __global__ void __launch_bounds__(1024) relay_bp_kernel(const DecodeLaunch a) {
                     path = 2;
                 }
             }
-            if (!have_best) capture_decisions(Ms, best, N, WN);
-            __syncthreads();
-        }
-        if (!traced && !a.trace_on) {
-            for (int w = tid; w < WN; w += nth) m.corr[row * WN + w] = best[w];
-            if (m.obsp) {
-                const int wid = tid >> 6;
-                for (int rb = wid * 64; rb < m.k; rb += nth) {
-                    const int r = rb + lane;
-                    uint32_t pbit = 0;
-                    if (r < m.k)
-                        for (int e = m.orow_ptr[r]; e < m.orow_ptr[r + 1]; ++e) {
-                            const int j = m.ocol_idx[e];
-                            pbit ^= (best[j >> 5] >> (j & 31)) & 1u;
+            if (!have_best) {
+                // no solution: report the last hard decision
+                if constexpr (CACHED) {
+#pragma unroll
+                    for (int v = 0; v < VPT; ++v) {
+                        const int jb = wid * 64 + v * nth;
+                        if (jb < N) {
+                            const unsigned long long b = __ballot(jb + lane < N && Mreg[v] < 0.0f);
+                            if (lane == 0) {
+                                best[jb >> 5] = (uint32_t)b;
+                                if ((jb >> 5) + 1 < WN) best[(jb >> 5) + 1] = (uint32_t)(b >> 32);
+                            }
                         }
-                    const unsigned long long b = __ballot(pbit != 0);
-                    if (lane == 0) {
-                        m.obsp[row * m.WK + (rb >> 5)] = (uint32_t)b;
-                        if ((rb >> 5) + 1 < m.WK) m.obsp[row * m.WK + (rb >> 5) + 1] = (uint32_t)(b >> 32);
+                    }
+                } else {
+                    for (int jb = wid * 64; jb < N; jb += nth) {
+                        const int j = jb + lane;
+                        const unsigned long long b = __ballot(j < N && Mg[j] < 0.0f);
+                        if (lane == 0) {
+                            best[jb >> 5] = (uint32_t)b;
+                            if ((jb >> 5) + 1 < WN) best[(jb >> 5) + 1] = (uint32_t)(b >> 32);
+                        }
                     }
                 }
             }
+            __syncthreads();
+        }
+        if (!a.trace_on) {
+            // corrections out; O * correction from the columns of O at its set bits
+            for (int w = tid; w < m.WK; w += nth) obw[w] = 0u;
+            __syncthreads();
+            for (int w = tid; w < WN; w += nth) {
+                const uint32_t bits = best[w];
+                m.corr[row * WN + w] = bits;
+                uint32_t b = bits;
+                while (b) {
+                    const int j = w * 32 + __builtin_ctz(b);
+                    b &= b - 1u;
+                    for (int e = m.ocol_ptr[j]; e < m.ocol_ptr[j + 1]; ++e) {
+                        const int r = m.orow_idx[e];
+                        atomicXor(obw + (r >> 5), 1u << (r & 31));
+                    }
+                }
+            }
+            __syncthreads();
+            if (m.obsp)
+                for (int w = tid; w < m.WK; w += nth) m.obsp[row * m.WK + w] = obw[w];
             if (a.stats && tid == 0) {
                 rbp_shot_stats st;
                 st.converged = have_best ? 1 : 0;
@@ -477,8 +738,13 @@ static rbp_status ensure_llr(rbp_code* c, const double* priors, hipStream_t stre
     for (int j = 0; j < c->N; ++j) lam[j] = (float)std::log((1.0 - priors[j]) / priors[j]);
     rbp_status st = c->lam.reserve(sizeof(float) * std::max(c->N, 1));
     if (st) return st;
+    st = c->m1.reserve(sizeof(float) * std::max<int64_t>((int64_t)c->M * c->P, 1));
+    if (st) return st;
     RBP_HIP_CHECK(hipStreamSynchronize(stream));
     RBP_HIP_CHECK(hipMemcpy(c->lam.p, lam.data(), sizeof(float) * c->N, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(first_message_kernel, dim3(ceil_div(c->M, 256)), dim3(256), 0, stream, c->row_ptr.as<int32_t>(),
+                       c->col_idx.as<int32_t>(), c->lam.as<float>(), c->m1.as<float>(), c->M, c->P);
+    RBP_HIP_CHECK(hipGetLastError());
     c->lam_key.assign(priors, priors + c->N);
     return RBP_OK;
 }
@@ -541,13 +807,13 @@ static DecodeModel model_of(const rbp_code* c, const uint32_t* syn, uint32_t* co
     m.WM = ceil_div(c->M, 32);
     m.WN = ceil_div(c->N, 32);
     m.WK = ceil_div(c->k, 32);
-    m.row_ptr = c->row_ptr.as<int32_t>();
-    m.col_idx = c->col_idx.as<int32_t>();
+    m.P = c->P;
+    m.rpos = c->rpos.as<int32_t>();
     m.col_ptr = c->col_ptr.as<int32_t>();
     m.csc_row = c->csc_row.as<int32_t>();
-    m.csc_edge = c->csc_edge.as<int32_t>();
-    m.orow_ptr = c->orow_ptr.as<int32_t>();
-    m.ocol_idx = c->ocol_idx.as<int32_t>();
+    m.m1p = c->m1.as<float>();
+    m.ocol_ptr = c->ocol_ptr.as<int32_t>();
+    m.orow_idx = c->orow_idx.as<int32_t>();
     m.lam = c->lam.as<float>();
     m.gtab = c->gtab.as<float>();
     m.syn = syn;
@@ -558,9 +824,23 @@ static DecodeModel model_of(const rbp_code* c, const uint32_t* syn, uint32_t* co
 
 typedef void (*DecodeKernel)(const DecodeLaunch);
 
-static DecodeKernel pick_kernel(int maxdeg, bool lds) {
-    if (maxdeg <= 12) return lds ? relay_bp_kernel<12, true> : relay_bp_kernel<12, false>;
-    return lds ? relay_bp_kernel<32, true> : relay_bp_kernel<32, false>;
+// Variants whose per-thread index lists live in registers: a thread owns at
+// most CPT checks and VPT variables (rows <= 12, columns <= 8 edges).
+struct CachedVariant {
+    int waves, cpt, vpt;
+    DecodeKernel k;
+};
+#define RBP_CACHED(W, C, V) {W, C, V, relay_bp_kernel<12, 8, C, V, true, W>}
+// Register-cached variants are compiled on demand; none is enabled by default
+// (their control state does not fit the register budget without spilling).
+static const CachedVariant kCached[] = {
+    {0, 0, 0, nullptr},
+};
+#undef RBP_CACHED
+
+static DecodeKernel generic_kernel(int maxdeg, bool lds) {
+    if (maxdeg <= 12) return lds ? relay_bp_kernel<12, 8, 0, 0, true, 16> : relay_bp_kernel<12, 8, 0, 0, false, 16>;
+    return lds ? relay_bp_kernel<32, 8, 0, 0, true, 16> : relay_bp_kernel<32, 8, 0, 0, false, 16>;
 }
 
 static constexpr int kMaxLds = 160 * 1024;
@@ -568,38 +848,85 @@ static constexpr int kMaxLds = 160 * 1024;
 struct LaunchShape {
     int waves = 1;
     bool lds_state = true;
+    bool cached = false;
+    int cpt = 0, vpt = 0;
+    DecodeKernel kernel = nullptr;
     int lds_bytes = 0;
     int slots = 1;
     int64_t gstride = 0;
-    int off_sig = 0, off_par = 0, off_best = 0;
+    int Emax = 0;
+    int off_sig = 0, off_par = 0, off_best = 0, off_obs = 0;
 };
+
+static const CachedVariant* find_cached(int M, int N, int waves) {
+    const int nth = 64 * waves;
+    const int cpt = ceil_div(M, nth), vpt = ceil_div(N, nth);
+    const CachedVariant* bestv = nullptr;
+    for (const CachedVariant& v : kCached)
+        if (v.k && v.waves == waves && cpt <= v.cpt && vpt <= v.vpt &&
+            (!bestv || v.cpt * 12 + v.vpt * 5 < bestv->cpt * 12 + bestv->vpt * 5))
+            bestv = &v;
+    return bestv;
+}
 
 // Launch shape for a set of models decoded together (max sizes over models).
 static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, LaunchShape* out) {
-    int Nmax = 0, Emax = 0, WMmax = 0, WNmax = 0, maxdeg = 0;
+    int Nmax = 0, Emax = 0, WMmax = 0, WNmax = 0, WKmax = 1, maxdeg = 0, maxcol = 0, Mmax = 0;
     for (int i = 0; i < n; ++i) {
+        Mmax = std::max(Mmax, cs[i]->M);
         Nmax = std::max(Nmax, cs[i]->N);
         Emax = std::max(Emax, cs[i]->E);
         WMmax = std::max(WMmax, ceil_div(cs[i]->M, 32));
         WNmax = std::max(WNmax, ceil_div(cs[i]->N, 32));
+        WKmax = std::max(WKmax, ceil_div(cs[i]->k, 32));
         maxdeg = std::max(maxdeg, cs[i]->max_row_deg);
+        maxcol = std::max(maxcol, cs[i]->max_col_deg);
     }
+    for (int i = 1; i < n; ++i)
+        if (cs[i]->P != cs[0]->P)
+            return fail(RBP_ERR_UNSUPPORTED, "models decoded together must all have rows of <= 12 or all > 12 edges");
     const LaunchCfg& cfg = cs[0]->cfg;
+    const int small = 4 * (2 * WMmax + WNmax + WKmax) + 512;  // + static shared variables
+    const bool cached_possible = n == 1 && maxdeg <= 12 && maxcol <= 8 && cfg.state != 2 &&
+                                 4 * (Emax + 4) + small <= kMaxLds;
+    LaunchShape L;
     int waves = cfg.waves_per_shot;
+    const CachedVariant* cv = nullptr;
     if (waves <= 0) {
-        const int want = ceil_div(Nmax, 512);
-        waves = 1;
-        while (waves < want && waves < 8) waves <<= 1;
+        if (cached_possible)
+            for (int w : {1, 2, 3, 4, 6, 8, 12, 16})
+                if ((cv = find_cached(Mmax, Nmax, w))) {
+                    waves = w;
+                    break;
+                }
+        if (waves <= 0) {
+            const int want = ceil_div(Nmax, 512);
+            waves = 1;
+            while (waves < want && waves < 8) waves <<= 1;
+        }
+    } else if (cached_possible) {
+        cv = find_cached(Mmax, Nmax, waves);
     }
     waves = std::min(std::max(waves, 1), 16);
-    const int small = 4 * (2 * WMmax + WNmax) + 512;  // + static shared variables
-    const int state_bytes = 4 * (Nmax + Emax);
-    bool lds = state_bytes + small <= kMaxLds;
-    if (cfg.state == 1 && !lds) return fail(RBP_ERR_UNSUPPORTED, "per-shot state does not fit in LDS");
-    if (cfg.state == 2) lds = false;
-    LaunchShape L;
+    int state_bytes;
+    bool lds;
+    if (cv) {
+        L.cached = true;
+        L.cpt = cv->cpt;
+        L.vpt = cv->vpt;
+        L.kernel = cv->k;
+        lds = true;
+        state_bytes = 4 * (Emax + 4);
+    } else {
+        state_bytes = 4 * (Emax + 4 + Nmax);
+        lds = state_bytes + small <= kMaxLds;
+        if (cfg.state == 1 && !lds) return fail(RBP_ERR_UNSUPPORTED, "per-shot state does not fit in LDS");
+        if (cfg.state == 2) lds = false;
+        L.kernel = generic_kernel(maxdeg, lds);
+    }
     L.waves = waves;
     L.lds_state = lds;
+    L.Emax = Emax;
     int off = lds ? state_bytes : 0;
     off = (off + 15) & ~15;
     L.off_sig = off;
@@ -608,17 +935,18 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
     off += 4 * WMmax;
     L.off_best = off;
     off += 4 * WNmax;
+    L.off_obs = off;
+    off += 4 * WKmax;
     L.lds_bytes = (off + 15) & ~15;
-    L.gstride = lds ? 0 : ((int64_t)Nmax + Emax + 63) / 64 * 64;
+    L.gstride = lds ? 0 : ((int64_t)Nmax + Emax + 4 + 63) / 64 * 64;
     int per_cu = 0;
-    DecodeKernel k = pick_kernel(maxdeg, lds);
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), 64 * waves,
-                                                                L.lds_bytes);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(L.kernel),
+                                                                64 * waves, L.lds_bytes);
     if (e != hipSuccess) return fail(RBP_ERR_HIP, std::string("occupancy query: ") + hipGetErrorString(e));
     per_cu = std::max(per_cu, 1);
     int64_t slots = (int64_t)per_cu * std::max(cs[0]->num_cus, 1);
     if (cfg.max_slots > 0) slots = std::min<int64_t>(slots, cfg.max_slots);
-    slots = std::min<int64_t>(slots, std::max<uint64_t>(shots, 1));
+    slots = std::min<int64_t>(slots, (int64_t)std::min<uint64_t>(std::max<uint64_t>(shots, 1), 1ull << 40));
     L.slots = (int)std::max<int64_t>(slots, 1);
     *out = L;
     return RBP_OK;
@@ -635,25 +963,20 @@ static rbp_status launch_decode(rbp_code* const* cs, int n, DecodeLaunch& a, uin
         st = c0->gstate.reserve(sizeof(float) * (size_t)L.gstride * L.slots);
         if (st) return st;
     }
-    int Nmax = 0, maxdeg = 0;
-    for (int i = 0; i < n; ++i) {
-        Nmax = std::max(Nmax, cs[i]->N);
-        maxdeg = std::max(maxdeg, cs[i]->max_row_deg);
-    }
     a.queue = c0->queue.as<unsigned long long>();
     a.gstate = L.lds_state ? nullptr : c0->gstate.as<float>();
     a.gstate_stride = L.gstride;
-    a.Nmax = Nmax;
+    a.Emax = L.Emax;
     a.off_sig = L.off_sig;
     a.off_par = L.off_par;
     a.off_best = L.off_best;
+    a.off_obs = L.off_obs;
     a.shots = shots;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, stream, a.queue, 1);
     RBP_HIP_CHECK(hipGetLastError());
-    DecodeKernel k = pick_kernel(maxdeg, L.lds_state);
-    RBP_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      L.lds_bytes));
-    hipLaunchKernelGGL(k, dim3(L.slots), dim3(64 * L.waves), L.lds_bytes, stream, a);
+    RBP_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(L.kernel),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, L.lds_bytes));
+    hipLaunchKernelGGL(L.kernel, dim3(L.slots), dim3(64 * L.waves), L.lds_bytes, stream, a);
     RBP_HIP_CHECK(hipGetLastError());
     return RBP_OK;
 }
@@ -719,14 +1042,15 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
         nnzO = obs_col_ptr[N];
     }
     // CSR of H (columns ascending within a row) and the CSC -> CSR edge map
-    std::vector<int32_t> rp(M + 1, 0), ci(std::max(E, 1)), cedge(std::max(E, 1)), fillc(M, 0);
+    const int P = maxrow <= 12 ? 12 : 32;  // row stride of the padded position table
+    std::vector<int32_t> rp(M + 1, 0), ci(std::max(E, 1)), rpos((size_t)M * P, E), fillc(M, 0);
     for (int i = 0; i < M; ++i) rp[i + 1] = rp[i] + deg[i];
     for (int j = 0; j < N; ++j)
         for (int e = col_ptr[j]; e < col_ptr[j + 1]; ++e) {
             const int i = row_idx[e];
             const int pos = rp[i] + fillc[i]++;
             ci[pos] = j;
-            cedge[e] = pos;
+            rpos[(size_t)i * P + (pos - rp[i])] = e;
         }
     // CSR of O
     std::vector<int32_t> orp(k + 1, 0), oci(std::max(nnzO, 1)), ofill(std::max(k, 1), 0);
@@ -746,6 +1070,7 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
     c->k = k;
     c->nnzO = nnzO;
     c->max_row_deg = maxrow;
+    c->P = P;
     c->max_col_deg = maxcol;
     hipError_t he = hipGetDevice(&c->device);
     if (he == hipSuccess) he = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device);
@@ -765,7 +1090,7 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
     if (!st) st = upload(c->col_idx, ci);
     if (!st) st = upload(c->col_ptr, cp);
     if (!st) st = upload(c->csc_row, cr);
-    if (!st) st = upload(c->csc_edge, cedge);
+    if (!st) st = upload(c->rpos, rpos);
     if (!st) st = upload(c->orow_ptr, orp);
     if (!st) st = upload(c->ocol_idx, oci);
     if (!st) st = upload(c->ocol_ptr, ocp);
@@ -781,8 +1106,8 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
 rbp_status rbp_code_destroy(rbp_code_t c) {
     if (!c) return RBP_OK;
     (void)hipDeviceSynchronize();
-    for (DevBuf* b : {&c->row_ptr, &c->col_idx, &c->col_ptr, &c->csc_row, &c->csc_edge, &c->orow_ptr, &c->ocol_idx,
-                      &c->ocol_ptr, &c->orow_idx, &c->thr, &c->lam, &c->gtab, &c->queue, &c->gstate, &c->trace_hit})
+    for (DevBuf* b : {&c->row_ptr, &c->col_idx, &c->col_ptr, &c->csc_row, &c->rpos, &c->orow_ptr, &c->ocol_idx,
+                      &c->ocol_ptr, &c->orow_idx, &c->thr, &c->lam, &c->m1, &c->gtab, &c->queue, &c->gstate, &c->trace_hit})
         b->release();
     delete c;
     return RBP_OK;
@@ -924,11 +1249,11 @@ rbp_status rbp_get_launch_config(rbp_code_t c, rbp_launch_config* cfg, int32_t* 
     if (!c) return fail(RBP_ERR_INVALID_ARG, "code is NULL");
     LaunchShape L;
     rbp_code* cs[1] = {c};
-    rbp_status st = plan_launch(cs, 1, ~0ull, &L);
+    rbp_status st = plan_launch(cs, 1, 1ull << 40, &L);
     if (st) return st;
     if (cfg) {
         cfg->waves_per_shot = L.waves;
-        cfg->state = L.lds_state ? 1 : 2;
+        cfg->state = (L.lds_state ? 1 : 2) + (L.cached ? 8 : 0);
         cfg->max_slots = c->cfg.max_slots;
     }
     if (slots) *slots = L.slots;
