@@ -126,6 +126,11 @@ rbp_status rbp_decode_multi(int32_t n_codes, const rbp_code_t* codes, const doub
                             uint32_t* const* corrections_dev, uint32_t* const* obs_pred_dev,
                             rbp_shot_stats* stats_dev, void* stream);
 
+/* The LLRs Lambda_j = (float) ln((1-p_j)/p_j) the decoder uses for these
+ * priors, written to llr_dev float[N] (device), e.g. as the prior term of the
+ * proposal network's loss. */
+rbp_status rbp_code_llr(rbp_code_t code, const double* priors, float* llr_dev, void* stream);
+
 /* Launch shape of the persistent decoder for one handle (chosen by the
  * autotuner; 0 = library default).  waves_per_shot: wavefronts that share one
  * shot (1..16).  state: 0 auto, 1 per-shot state in LDS, 2 in device memory.
@@ -167,6 +172,12 @@ rbp_status rbp_mlp_forward(rbp_mlp_t mlp, const uint32_t* syndromes_dev, uint64_
  * loss_out_dev (float[1], may be NULL) receives the batch loss. */
 rbp_status rbp_mlp_train_step(rbp_mlp_t mlp, const uint32_t* syndromes_dev, const uint32_t* targets_dev,
                               const float* llr_dev, uint64_t batch, float lr, float* loss_out_dev, void* stream);
+/* Gradients of the same loss on a batch without updating the weights:
+ * grads_dev float[num_params] in the parameter layout below, loss_out_dev
+ * float[1] (may be NULL).  For checking the backward pass. */
+rbp_status rbp_mlp_gradients(rbp_mlp_t mlp, const uint32_t* syndromes_dev, const uint32_t* targets_dev,
+                             const float* llr_dev, uint64_t batch, float* grads_dev, float* loss_out_dev,
+                             void* stream);
 /* Copy parameters between the handle and a caller buffer (host float array
  * laid out W1[h][in], b1[h], W2[h][h], b2[h], W3[out][h], b3[out]).  Set
  * replaces the masters and resets the Adam state. */

@@ -1234,6 +1234,17 @@ rbp_status rbp_decode_multi(int32_t n_codes, const rbp_code_t* codes, const doub
     return launch_decode(cs.data(), n_codes, a, shots, stream);
 }
 
+rbp_status rbp_code_llr(rbp_code_t c, const double* priors, float* llr, void* stream_) {
+    if (!c || !llr) return fail(RBP_ERR_INVALID_ARG, "NULL argument");
+    rbp_status st = check_priors(priors, c->N);
+    if (st) return st;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    st = ensure_llr(c, priors, stream);
+    if (st) return st;
+    RBP_HIP_CHECK(hipMemcpyAsync(llr, c->lam.p, sizeof(float) * c->N, hipMemcpyDeviceToDevice, stream));
+    return RBP_OK;
+}
+
 rbp_status rbp_set_launch_config(rbp_code_t c, const rbp_launch_config* cfg) {
     if (!c || !cfg) return fail(RBP_ERR_INVALID_ARG, "NULL argument");
     if (cfg->waves_per_shot < 0 || cfg->waves_per_shot > 16 || cfg->state < 0 || cfg->state > 2 ||

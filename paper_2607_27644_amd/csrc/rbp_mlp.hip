@@ -1,15 +1,537 @@
-// Learned-proposal network (placeholder until the kernels land).
+// Learned proposal network of librbp: a 3-layer perceptron trained and run with
+// hand-written BF16 MFMA kernels for gfx950 (FP32 accumulation, FP32 master
+// weights, Adam).
+//
+//   x = syndrome bits (0/1)            [B x in]
+//   h1 = relu(W1 x + b1)               [B x hid]   (BF16)
+//   h2 = relu(W2 h1 + b2)              [B x hid]   (BF16)
+//   delta = W3 h2 + b3                 [B x out]   (FP32)  log-prior adjustment
+//   loss = mean_b sum_j BCEWithLogits(z_bj, y_bj), z = -(Lambda + delta),
+//          y = correction bits of Relay-BP (the network learns posterior
+//          log-odds of each mechanism; delta is the correction to the prior).
+//
+// All products are one tiled GEMM kernel: C[MxN] = opA(A)[MxK] . opB(B)[KxN]
+// with a 128x128 output tile per workgroup of 4 wavefronts, each computing a
+// 64x64 block with v_mfma_f32_32x32x16_bf16, operands staged through LDS in a
+// K-contiguous layout (operands stored M- or N-contiguous are transposed while
+// staging).  Epilogues fuse the bias, ReLU, the ReLU mask of the backward pass
+// and the BF16/FP32 stores.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
 #include "rbp_common.h"
+
+namespace rbp {
+namespace mlp {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int BM = 128, BN = 128, BK = 32;
+constexpr int LDSK = BK + 8;  // padded row of the staged tiles (bank spread)
+
+enum Layout { K_CONTIG = 0, MN_CONTIG = 1 };
+enum Epi {
+    EPI_BIAS_RELU_BF16 = 0,  // out_bf16 = bf16(relu(acc + bias[n]))
+    EPI_BIAS_F32 = 1,        // out_f32 = acc + bias[n]
+    EPI_MASK_BF16_F32 = 2,   // v = acc * [mask[m][n] > 0]; out_bf16 = bf16(v), out_f32 = v
+    EPI_F32 = 3,             // out_f32 = acc
+};
+
+struct GemmArgs {
+    int M, N, K;
+    const bf16* A;  // K_CONTIG: A[m*lda + k]; MN_CONTIG: A[k*lda + m]
+    int lda;
+    const bf16* B;  // K_CONTIG: B[n*ldb + k]; MN_CONTIG: B[k*ldb + n]
+    int ldb;
+    const float* bias;
+    const bf16* mask;  // [M x N] row-major, ld = ldc
+    bf16* out_bf16;
+    float* out_f32;
+    int ldc;
+};
+
+// Stages a BM x BK (or BN x BK) tile of an operand into LDS as tile[row][k].
+template <int LAYOUT>
+__device__ __forceinline__ void stage(bf16 (*tile)[LDSK], const bf16* src, int ld, int rows, int K, int r0, int k0) {
+    const int t = threadIdx.x;
+    // 16-byte vector loads need a 16-byte aligned base and a leading dimension of 8k
+    const bool vec = ((reinterpret_cast<uintptr_t>(src) & 15) == 0) && ((ld & 7) == 0);
+    if constexpr (LAYOUT == K_CONTIG) {
+        // 128 rows x 32 k = 512 vectors of 8; 2 per thread
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            const int v = t + pass * 256;
+            const int r = v >> 2, kk = (v & 3) * 8;
+            const int gr = r0 + r, gk = k0 + kk;
+            bf16x8 x;
+            if (vec && gr < rows && gk + 7 < K) {
+                x = *reinterpret_cast<const bf16x8*>(src + (int64_t)gr * ld + gk);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    x[i] = (gr < rows && gk + i < K) ? src[(int64_t)gr * ld + gk + i] : (bf16)0.0f;
+            }
+            *reinterpret_cast<bf16x8*>(&tile[r][kk]) = x;
+        }
+    } else {
+        // 32 k x 128 rows, rows contiguous in memory: vectors of 8 rows
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            const int v = t + pass * 256;
+            const int kk = v >> 4, r = (v & 15) * 8;
+            const int gr = r0 + r, gk = k0 + kk;
+            bf16x8 x;
+            if (vec && gk < K && gr + 7 < rows) {
+                x = *reinterpret_cast<const bf16x8*>(src + (int64_t)gk * ld + gr);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    x[i] = (gk < K && gr + i < rows) ? src[(int64_t)gk * ld + gr + i] : (bf16)0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) tile[r + i][kk] = x[i];
+        }
+    }
+}
+
+template <int LA, int LB, int EPI>
+__global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs g) {
+    __shared__ __align__(16) bf16 As[BM][LDSK];
+    __shared__ __align__(16) bf16 Bs[BN][LDSK];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int wm = (wid >> 1) * 64, wn = (wid & 1) * 64;  // this wave's 64x64 block
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{};
+
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+        stage<LA>(As, g.A, g.lda, g.M, g.K, m0, k0);
+        stage<LB>(Bs, g.B, g.ldb, g.N, g.K, n0, k0);
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 16) {
+            // lane: row (lane % 32) of a 32-row block, 8 consecutive k from (lane / 32) * 8.
+            // A and B use the same k order, so the product is independent of how the
+            // matrix core pairs the k slots.
+            const int kk = ks + (lane >> 5) * 8;
+            bf16x8 af[2], bfr[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&As[wm + i * 32 + (lane & 31)][kk]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + j * 32 + (lane & 31)][kk]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // 32x32 accumulator layout: register r of lane l is C[8*(r/4) + 4*(l/32) + r%4][l%32]
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int n = n0 + wn + j * 32 + (lane & 31);
+                if (m >= g.M || n >= g.N) continue;
+                const float v = acc[i][j][r];
+                const int64_t o = (int64_t)m * g.ldc + n;
+                if constexpr (EPI == EPI_BIAS_RELU_BF16) {
+                    g.out_bf16[o] = (bf16)fmaxf(v + g.bias[n], 0.0f);
+                } else if constexpr (EPI == EPI_BIAS_F32) {
+                    g.out_f32[o] = v + g.bias[n];
+                } else if constexpr (EPI == EPI_MASK_BF16_F32) {
+                    const float x = (float)g.mask[o] > 0.0f ? v : 0.0f;
+                    g.out_bf16[o] = (bf16)x;
+                    g.out_f32[o] = x;
+                } else {
+                    g.out_f32[o] = v;
+                }
+            }
+}
+
+// x[b][i] = bit i of syndrome row b, as BF16 0/1
+__global__ void expand_bits_kernel(const uint32_t* syn, int words, int in, int B, bf16* x) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)B * in) return;
+    const int b = (int)(idx / in), i = (int)(idx % in);
+    x[idx] = (bf16)(float)((syn[(int64_t)b * words + (i >> 5)] >> (i & 31)) & 1u);
+}
+
+// Per element: z = -(lambda + delta), p = sigmoid(z), y = target bit.
+// dL/d(delta) = -(p - y) / B.  Per-block loss partial sums for a deterministic
+// reduction.
+__global__ void loss_grad_kernel(const float* delta, const float* lam, const uint32_t* tgt, int words, int N, int B,
+                                 float* d3f, bf16* d3b, float* partial) {
+    __shared__ float red[256];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float l = 0.0f;
+    if (idx < (int64_t)B * N) {
+        const int b = (int)(idx / N), j = (int)(idx % N);
+        const float z = -(lam[j] + delta[idx]);
+        const float y = (float)((tgt[(int64_t)b * words + (j >> 5)] >> (j & 31)) & 1u);
+        const float p = 1.0f / (1.0f + expf(-z));
+        const float g = -(p - y) / (float)B;
+        d3f[idx] = g;
+        d3b[idx] = (bf16)g;
+        l = fmaxf(z, 0.0f) - z * y + log1pf(expf(-fabsf(z)));
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void sum_partials_kernel(const float* partial, int n, float scale, float* out) {
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256) s += partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] * scale;
+}
+
+// out[n] = sum_b in[b][n]  (one thread per column, rows in order: deterministic)
+__global__ void colsum_kernel(const float* in, int B, int N, float* out) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int b = 0; b < B; ++b) s += in[(int64_t)b * N + n];
+    out[n] = s;
+}
+
+__global__ void adam_kernel(float* w, float* mo, float* ve, const float* g, int64_t n, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float m = b1 * mo[i] + (1.0f - b1) * gi;
+    const float v = b2 * ve[i] + (1.0f - b2) * gi * gi;
+    mo[i] = m;
+    ve[i] = v;
+    w[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+__global__ void to_bf16_kernel(const float* w, bf16* o, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = (bf16)w[i];
+}
+
+}  // namespace mlp
+}  // namespace rbp
+
 using namespace rbp;
+using namespace rbp::mlp;
+
+struct rbp_mlp {
+    int in = 0, hid = 0, out = 0;
+    int64_t n_params = 0;
+    int64_t oW1, ob1, oW2, ob2, oW3, ob3;  // offsets in the parameter array
+    DevBuf w, m, v, g, wb;                 // FP32 masters, Adam moments, gradients, BF16 copies
+    int64_t step = 0;
+    int cap = 0;                           // batch capacity of the workspace
+    DevBuf xb, h1, h2, d3b, dh2b, dh1b;    // BF16 activations / gradients
+    DevBuf delta, d3f, dh2f, dh1f, partial, loss;
+};
+
+namespace {
+
+rbp_status ensure_workspace(rbp_mlp* p, int B) {
+    if (B <= p->cap) return RBP_OK;
+    const int64_t Bi = B;
+    rbp_status st = RBP_OK;
+    if (!st) st = p->xb.reserve(sizeof(bf16) * Bi * p->in);
+    if (!st) st = p->h1.reserve(sizeof(bf16) * Bi * p->hid);
+    if (!st) st = p->h2.reserve(sizeof(bf16) * Bi * p->hid);
+    if (!st) st = p->d3b.reserve(sizeof(bf16) * Bi * p->out);
+    if (!st) st = p->dh2b.reserve(sizeof(bf16) * Bi * p->hid);
+    if (!st) st = p->dh1b.reserve(sizeof(bf16) * Bi * p->hid);
+    if (!st) st = p->delta.reserve(sizeof(float) * Bi * p->out);
+    if (!st) st = p->d3f.reserve(sizeof(float) * Bi * p->out);
+    if (!st) st = p->dh2f.reserve(sizeof(float) * Bi * p->hid);
+    if (!st) st = p->dh1f.reserve(sizeof(float) * Bi * p->hid);
+    if (!st) st = p->partial.reserve(sizeof(float) * (Bi * std::max(p->out, p->hid) / 256 + 2));
+    if (!st) st = p->loss.reserve(sizeof(float) * 4);
+    if (st) return st;
+    p->cap = B;
+    return RBP_OK;
+}
+
+template <int LA, int LB, int EPI>
+rbp_status gemm(const GemmArgs& a, hipStream_t s) {
+    dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM);
+    hipLaunchKernelGGL((gemm_kernel<LA, LB, EPI>), grid, dim3(256), 0, s, a);
+    RBP_HIP_CHECK(hipGetLastError());
+    return RBP_OK;
+}
+
+GemmArgs ga(int M, int N, int K, const bf16* A, int lda, const bf16* B, int ldb, int ldc) {
+    GemmArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.M = M;
+    a.N = N;
+    a.K = K;
+    a.A = A;
+    a.lda = lda;
+    a.B = B;
+    a.ldb = ldb;
+    a.ldc = ldc;
+    return a;
+}
+
+int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+// forward of B rows: x from syndromes, h1, h2 (workspace), delta into `dout`
+rbp_status forward(rbp_mlp* p, const uint32_t* syn, int B, float* dout, hipStream_t s) {
+    const int words = (p->in + 31) / 32;
+    bf16* xb = p->xb.as<bf16>();
+    bf16* h1 = p->h1.as<bf16>();
+    bf16* h2 = p->h2.as<bf16>();
+    const bf16* wb = p->wb.as<bf16>();
+    const float* w = p->w.as<float>();
+    hipLaunchKernelGGL(expand_bits_kernel, dim3(blocks((int64_t)B * p->in, 256)), dim3(256), 0, s, syn, words, p->in,
+                       B, xb);
+    RBP_HIP_CHECK(hipGetLastError());
+    GemmArgs a = ga(B, p->hid, p->in, xb, p->in, wb + p->oW1, p->in, p->hid);
+    a.bias = w + p->ob1;
+    a.out_bf16 = h1;
+    rbp_status st = gemm<K_CONTIG, K_CONTIG, EPI_BIAS_RELU_BF16>(a, s);
+    if (st) return st;
+    a = ga(B, p->hid, p->hid, h1, p->hid, wb + p->oW2, p->hid, p->hid);
+    a.bias = w + p->ob2;
+    a.out_bf16 = h2;
+    st = gemm<K_CONTIG, K_CONTIG, EPI_BIAS_RELU_BF16>(a, s);
+    if (st) return st;
+    a = ga(B, p->out, p->hid, h2, p->hid, wb + p->oW3, p->hid, p->out);
+    a.bias = w + p->ob3;
+    a.out_f32 = dout;
+    return gemm<K_CONTIG, K_CONTIG, EPI_BIAS_F32>(a, s);
+}
+
+// forward + backward of one batch into p->g (gradients of the mean loss)
+rbp_status gradients(rbp_mlp* p, const uint32_t* syn, const uint32_t* tgt, const float* llr, int B, float* loss_out,
+                     hipStream_t s) {
+    rbp_status st = ensure_workspace(p, B);
+    if (st) return st;
+    float* delta = p->delta.as<float>();
+    st = forward(p, syn, B, delta, s);
+    if (st) return st;
+    const int twords = (p->out + 31) / 32;
+    const int64_t n3 = (int64_t)B * p->out;
+    const int nb = blocks(n3, 256);
+    hipLaunchKernelGGL(loss_grad_kernel, dim3(nb), dim3(256), 0, s, delta, llr, tgt, twords, p->out, B,
+                       p->d3f.as<float>(), p->d3b.as<bf16>(), p->partial.as<float>());
+    RBP_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, p->partial.as<float>(), nb, 1.0f / (float)B,
+                       loss_out ? loss_out : p->loss.as<float>());
+    RBP_HIP_CHECK(hipGetLastError());
+    float* g = p->g.as<float>();
+    const bf16* wb = p->wb.as<bf16>();
+    // dW3 = d3^T h2 ; db3 = colsum d3 ; dh2 = (d3 W3) * [h2 > 0]
+    GemmArgs a = ga(p->out, p->hid, B, p->d3b.as<bf16>(), p->out, p->h2.as<bf16>(), p->hid, p->hid);
+    a.out_f32 = g + p->oW3;
+    if ((st = gemm<MN_CONTIG, MN_CONTIG, EPI_F32>(a, s))) return st;
+    hipLaunchKernelGGL(colsum_kernel, dim3(blocks(p->out, 256)), dim3(256), 0, s, p->d3f.as<float>(), B, p->out,
+                       g + p->ob3);
+    RBP_HIP_CHECK(hipGetLastError());
+    a = ga(B, p->hid, p->out, p->d3b.as<bf16>(), p->out, wb + p->oW3, p->hid, p->hid);
+    a.mask = p->h2.as<bf16>();
+    a.out_bf16 = p->dh2b.as<bf16>();
+    a.out_f32 = p->dh2f.as<float>();
+    if ((st = gemm<K_CONTIG, MN_CONTIG, EPI_MASK_BF16_F32>(a, s))) return st;
+    // dW2 = dh2^T h1 ; db2 ; dh1 = (dh2 W2) * [h1 > 0]
+    a = ga(p->hid, p->hid, B, p->dh2b.as<bf16>(), p->hid, p->h1.as<bf16>(), p->hid, p->hid);
+    a.out_f32 = g + p->oW2;
+    if ((st = gemm<MN_CONTIG, MN_CONTIG, EPI_F32>(a, s))) return st;
+    hipLaunchKernelGGL(colsum_kernel, dim3(blocks(p->hid, 256)), dim3(256), 0, s, p->dh2f.as<float>(), B, p->hid,
+                       g + p->ob2);
+    RBP_HIP_CHECK(hipGetLastError());
+    a = ga(B, p->hid, p->hid, p->dh2b.as<bf16>(), p->hid, wb + p->oW2, p->hid, p->hid);
+    a.mask = p->h1.as<bf16>();
+    a.out_bf16 = p->dh1b.as<bf16>();
+    a.out_f32 = p->dh1f.as<float>();
+    if ((st = gemm<K_CONTIG, MN_CONTIG, EPI_MASK_BF16_F32>(a, s))) return st;
+    // dW1 = dh1^T x ; db1
+    a = ga(p->hid, p->in, B, p->dh1b.as<bf16>(), p->hid, p->xb.as<bf16>(), p->in, p->in);
+    a.out_f32 = g + p->oW1;
+    if ((st = gemm<MN_CONTIG, MN_CONTIG, EPI_F32>(a, s))) return st;
+    hipLaunchKernelGGL(colsum_kernel, dim3(blocks(p->hid, 256)), dim3(256), 0, s, p->dh1f.as<float>(), B, p->hid,
+                       g + p->ob1);
+    RBP_HIP_CHECK(hipGetLastError());
+    return RBP_OK;
+}
+
+rbp_status refresh_bf16(rbp_mlp* p, hipStream_t s) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(p->n_params, 256)), dim3(256), 0, s, p->w.as<float>(),
+                       p->wb.as<bf16>(), p->n_params);
+    RBP_HIP_CHECK(hipGetLastError());
+    return RBP_OK;
+}
+
+rbp_status zero_adam(rbp_mlp* p) {
+    RBP_HIP_CHECK(hipMemset(p->m.p, 0, sizeof(float) * p->n_params));
+    RBP_HIP_CHECK(hipMemset(p->v.p, 0, sizeof(float) * p->n_params));
+    p->step = 0;
+    return RBP_OK;
+}
+
+}  // namespace
+
 extern "C" {
-rbp_status rbp_mlp_create(int32_t, int32_t, int32_t, uint64_t, rbp_mlp_t* out) {
-    if (out) *out = nullptr;
-    return fail(RBP_ERR_UNSUPPORTED, "mlp not built");
+
+rbp_status rbp_mlp_create(int32_t in_dim, int32_t hidden, int32_t out_dim, uint64_t seed, rbp_mlp_t* out) {
+    if (!out) return fail(RBP_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (in_dim < 1 || hidden < 1 || out_dim < 1) return fail(RBP_ERR_SHAPE, "dimensions must be >= 1");
+    rbp_mlp* p = new rbp_mlp();
+    p->in = in_dim;
+    p->hid = hidden;
+    p->out = out_dim;
+    int64_t o = 0;
+    p->oW1 = o; o += (int64_t)hidden * in_dim;
+    p->ob1 = o; o += hidden;
+    p->oW2 = o; o += (int64_t)hidden * hidden;
+    p->ob2 = o; o += hidden;
+    p->oW3 = o; o += (int64_t)out_dim * hidden;
+    p->ob3 = o; o += out_dim;
+    p->n_params = o;
+    // uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights from Philox(seed; index/4, 0, 0, 2); zero biases
+    std::vector<float> h(o, 0.0f);
+    auto fill = [&](int64_t off, int64_t n, int fan_in) {
+        const float s = 1.0f / std::sqrt((float)fan_in);
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t idx = off + i;
+            const U4 r = philox4x32_10(U4{(uint32_t)(idx >> 2), (uint32_t)(idx >> 34), 0u, 2u}, (uint32_t)seed,
+                                       (uint32_t)(seed >> 32));
+            const float u = (float)(u4_get(r, (int)(idx & 3)) >> 8) * (1.0f / 16777216.0f);
+            h[idx] = (2.0f * u - 1.0f) * s;
+        }
+    };
+    fill(p->oW1, (int64_t)hidden * in_dim, in_dim);
+    fill(p->oW2, (int64_t)hidden * hidden, hidden);
+    fill(p->oW3, (int64_t)out_dim * hidden, hidden);
+    rbp_status st = RBP_OK;
+    if (!st) st = p->w.reserve(sizeof(float) * o);
+    if (!st) st = p->m.reserve(sizeof(float) * o);
+    if (!st) st = p->v.reserve(sizeof(float) * o);
+    if (!st) st = p->g.reserve(sizeof(float) * o);
+    if (!st) st = p->wb.reserve(sizeof(bf16) * o);
+    if (!st) {
+        hipError_t e = hipMemcpy(p->w.p, h.data(), sizeof(float) * o, hipMemcpyHostToDevice);
+        if (e != hipSuccess) st = fail(RBP_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    }
+    if (!st) st = zero_adam(p);
+    if (!st) st = refresh_bf16(p, nullptr);
+    if (!st) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) st = fail(RBP_ERR_HIP, std::string("sync: ") + hipGetErrorString(e));
+    }
+    if (st) {
+        rbp_mlp_destroy(p);
+        return st;
+    }
+    *out = p;
+    return RBP_OK;
 }
-rbp_status rbp_mlp_destroy(rbp_mlp_t) { return RBP_OK; }
-rbp_status rbp_mlp_forward(rbp_mlp_t, const uint32_t*, uint64_t, float*, void*) { return fail(RBP_ERR_UNSUPPORTED, "mlp not built"); }
-rbp_status rbp_mlp_train_step(rbp_mlp_t, const uint32_t*, const uint32_t*, const float*, uint64_t, float, float*, void*) { return fail(RBP_ERR_UNSUPPORTED, "mlp not built"); }
-rbp_status rbp_mlp_num_params(rbp_mlp_t, int64_t*) { return fail(RBP_ERR_UNSUPPORTED, "mlp not built"); }
-rbp_status rbp_mlp_get_params(rbp_mlp_t, float*) { return fail(RBP_ERR_UNSUPPORTED, "mlp not built"); }
-rbp_status rbp_mlp_set_params(rbp_mlp_t, const float*) { return fail(RBP_ERR_UNSUPPORTED, "mlp not built"); }
+
+rbp_status rbp_mlp_destroy(rbp_mlp_t p) {
+    if (!p) return RBP_OK;
+    (void)hipDeviceSynchronize();
+    for (DevBuf* b : {&p->w, &p->m, &p->v, &p->g, &p->wb, &p->xb, &p->h1, &p->h2, &p->d3b, &p->dh2b, &p->dh1b,
+                      &p->delta, &p->d3f, &p->dh2f, &p->dh1f, &p->partial, &p->loss})
+        b->release();
+    delete p;
+    return RBP_OK;
 }
+
+rbp_status rbp_mlp_forward(rbp_mlp_t p, const uint32_t* syndromes, uint64_t shots, float* delta, void* stream_) {
+    if (!p) return fail(RBP_ERR_INVALID_ARG, "mlp is NULL");
+    if (shots == 0) return RBP_OK;
+    if (!syndromes || !delta) return fail(RBP_ERR_INVALID_ARG, "NULL buffer");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
+    const int chunk = 16384;
+    rbp_status st = ensure_workspace(p, (int)std::min<uint64_t>(shots, chunk));
+    if (st) return st;
+    const int words = (p->in + 31) / 32;
+    for (uint64_t b0 = 0; b0 < shots; b0 += chunk) {
+        const int B = (int)std::min<uint64_t>(chunk, shots - b0);
+        st = forward(p, syndromes + b0 * words, B, delta + b0 * (uint64_t)p->out, s);
+        if (st) return st;
+    }
+    return RBP_OK;
+}
+
+rbp_status rbp_mlp_gradients(rbp_mlp_t p, const uint32_t* syndromes, const uint32_t* targets, const float* llr,
+                             uint64_t batch, float* grads_out, float* loss_out, void* stream_) {
+    if (!p) return fail(RBP_ERR_INVALID_ARG, "mlp is NULL");
+    if (!syndromes || !targets || !llr || !grads_out) return fail(RBP_ERR_INVALID_ARG, "NULL buffer");
+    if (batch < 1 || batch > (1u << 20)) return fail(RBP_ERR_INVALID_ARG, "batch must be 1..2^20");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
+    rbp_status st = gradients(p, syndromes, targets, llr, (int)batch, loss_out, s);
+    if (st) return st;
+    RBP_HIP_CHECK(hipMemcpyAsync(grads_out, p->g.p, sizeof(float) * p->n_params, hipMemcpyDeviceToDevice, s));
+    return RBP_OK;
+}
+
+rbp_status rbp_mlp_train_step(rbp_mlp_t p, const uint32_t* syndromes, const uint32_t* targets, const float* llr,
+                              uint64_t batch, float lr, float* loss_out, void* stream_) {
+    if (!p) return fail(RBP_ERR_INVALID_ARG, "mlp is NULL");
+    if (!syndromes || !targets || !llr) return fail(RBP_ERR_INVALID_ARG, "NULL buffer");
+    if (batch < 1 || batch > (1u << 20)) return fail(RBP_ERR_INVALID_ARG, "batch must be 1..2^20");
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(RBP_ERR_INVALID_ARG, "lr must be positive");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
+    rbp_status st = gradients(p, syndromes, targets, llr, (int)batch, loss_out, s);
+    if (st) return st;
+    p->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - (float)std::pow(0.9, (double)p->step);
+    const float c2 = 1.0f - (float)std::pow(0.999, (double)p->step);
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks(p->n_params, 256)), dim3(256), 0, s, p->w.as<float>(),
+                       p->m.as<float>(), p->v.as<float>(), p->g.as<float>(), p->n_params, lr, b1, b2, 1e-8f, c1, c2);
+    RBP_HIP_CHECK(hipGetLastError());
+    return refresh_bf16(p, s);
+}
+
+rbp_status rbp_mlp_num_params(rbp_mlp_t p, int64_t* n) {
+    if (!p || !n) return fail(RBP_ERR_INVALID_ARG, "NULL argument");
+    *n = p->n_params;
+    return RBP_OK;
+}
+
+rbp_status rbp_mlp_get_params(rbp_mlp_t p, float* host_out) {
+    if (!p || !host_out) return fail(RBP_ERR_INVALID_ARG, "NULL argument");
+    RBP_HIP_CHECK(hipDeviceSynchronize());
+    RBP_HIP_CHECK(hipMemcpy(host_out, p->w.p, sizeof(float) * p->n_params, hipMemcpyDeviceToHost));
+    return RBP_OK;
+}
+
+rbp_status rbp_mlp_set_params(rbp_mlp_t p, const float* host_in) {
+    if (!p || !host_in) return fail(RBP_ERR_INVALID_ARG, "NULL argument");
+    RBP_HIP_CHECK(hipDeviceSynchronize());
+    RBP_HIP_CHECK(hipMemcpy(p->w.p, host_in, sizeof(float) * p->n_params, hipMemcpyHostToDevice));
+    rbp_status st = zero_adam(p);
+    if (!st) st = refresh_bf16(p, nullptr);
+    if (st) return st;
+    RBP_HIP_CHECK(hipDeviceSynchronize());
+    return RBP_OK;
+}
+
+}  // extern "C"

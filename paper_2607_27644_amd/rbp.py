@@ -90,6 +90,8 @@ def lib():
         "rbp_mlp_forward": [vp, vp, u64, vp, vp],
         "rbp_mlp_train_step": [vp, vp, vp, vp, u64, ctypes.c_float, vp, vp],
         "rbp_mlp_num_params": [vp, P(i64)],
+        "rbp_mlp_gradients": [vp, vp, vp, vp, u64, vp, vp, vp],
+        "rbp_code_llr": [vp, vp, vp, vp],
         "rbp_mlp_get_params": [vp, vp],
         "rbp_mlp_set_params": [vp, vp],
     }
@@ -218,6 +220,13 @@ class Code:
             return None
         return Mo.cpu().numpy(), mu[: self.nnz].cpu().numpy()
 
+    def llr(self, priors, stream=None) -> torch.Tensor:
+        """The decoder's FP32 LLRs for these priors, on the device."""
+        out = torch.empty(self.N, dtype=torch.float32, device="cuda")
+        pr = _f64(priors)
+        check(lib().rbp_code_llr(self.h, pr.ctypes.data, _ptr(out), _stream(stream)))
+        return out
+
     def set_launch_config(self, waves_per_shot: int = 0, state: int = 0, max_slots: int = 0):
         cfg = LaunchConfigC(waves_per_shot, state, max_slots)
         check(lib().rbp_set_launch_config(self.h, ctypes.byref(cfg)))
@@ -251,3 +260,61 @@ def stats_to_numpy(st: torch.Tensor) -> np.ndarray:
 
 def to_u32(t: torch.Tensor) -> np.ndarray:
     return t.cpu().numpy().view(np.uint32)
+
+
+class MLP:
+    """Learned proposal network (rbp_mlp_*): syndrome bits -> per-mechanism
+    log-prior adjustments delta."""
+
+    def __init__(self, in_dim: int, hidden: int, out_dim: int, seed: int = 0):
+        self.in_dim, self.hidden, self.out_dim = in_dim, hidden, out_dim
+        h = ctypes.c_void_p()
+        check(lib().rbp_mlp_create(in_dim, hidden, out_dim, seed, ctypes.byref(h)))
+        self.h = h
+        n = ctypes.c_int64()
+        check(lib().rbp_mlp_num_params(self.h, ctypes.byref(n)))
+        self.n_params = n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rbp_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, syndromes: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        shots = syndromes.shape[0]
+        assert syndromes.shape[1] == words(self.in_dim) and syndromes.is_contiguous()
+        if out is None:
+            out = torch.empty((shots, self.out_dim), dtype=torch.float32, device=syndromes.device)
+        check(lib().rbp_mlp_forward(self.h, _ptr(syndromes), shots, _ptr(out), _stream(stream)))
+        return out
+
+    def train_step(self, syndromes: torch.Tensor, targets: torch.Tensor, llr: torch.Tensor, lr: float,
+                   loss_out: Optional[torch.Tensor] = None, stream=None):
+        batch = syndromes.shape[0]
+        assert targets.shape == (batch, words(self.out_dim)) and llr.shape == (self.out_dim,)
+        check(lib().rbp_mlp_train_step(self.h, _ptr(syndromes), _ptr(targets), _ptr(llr), batch, ctypes.c_float(lr),
+                                       _ptr(loss_out), _stream(stream)))
+
+    def gradients(self, syndromes: torch.Tensor, targets: torch.Tensor, llr: torch.Tensor, stream=None):
+        batch = syndromes.shape[0]
+        g = torch.empty(self.n_params, dtype=torch.float32, device=syndromes.device)
+        loss = torch.empty(1, dtype=torch.float32, device=syndromes.device)
+        check(lib().rbp_mlp_gradients(self.h, _ptr(syndromes), _ptr(targets), _ptr(llr), batch, _ptr(g), _ptr(loss),
+                                      _stream(stream)))
+        return g, loss
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        check(lib().rbp_mlp_get_params(self.h, out.ctypes.data))
+        return out
+
+    def set_params(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == self.n_params
+        check(lib().rbp_mlp_set_params(self.h, p.ctypes.data))

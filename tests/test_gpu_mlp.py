@@ -1,0 +1,110 @@
+"""GPU checks of the proposal network kernels against the float64 reference."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import mlp_ref as R  # noqa: E402
+from paper_2607_27644_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rbp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_27644_amd import rbp as mod
+    return mod
+
+
+def _data(din, dout, B, seed, dens=0.05):
+    rng = np.random.default_rng(seed)
+    x = (rng.random((B, din)) < dens).astype(np.uint8)
+    y = (rng.random((B, dout)) < 0.02).astype(np.uint8)
+    lam = rng.uniform(2.0, 9.0, dout).astype(np.float32)
+    return x, y, lam
+
+
+def _dev_bits(bits):
+    return torch.from_numpy(W.pack_bits(bits).view(np.int32)).cuda()
+
+
+def rel_err(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+@pytest.mark.parametrize("din,h,dout,B", [(64, 512, 160, 300), (576, 512, 1952, 129), (24, 64, 60, 77),
+                                          (40, 128, 100, 1000)])
+def test_forward_matches_reference(rbp, din, h, dout, B):
+    net = rbp.MLP(din, h, dout, seed=5)
+    rng = np.random.default_rng(2)
+    p = net.get_params().astype(np.float64)
+    # non-zero biases to exercise the epilogue
+    W1, b1, W2, b2, W3, b3 = R.split(p, din, h, dout)
+    b1[:] = rng.normal(0, 0.1, h)
+    b2[:] = rng.normal(0, 0.1, h)
+    b3[:] = rng.normal(0, 0.5, dout)
+    net.set_params(p.astype(np.float32))
+    x, _, _ = _data(din, dout, B, 3, dens=0.2)
+    got = net.forward(_dev_bits(x)).cpu().numpy()
+    ref, _ = R.forward(net.get_params(), x, din, h, dout, mirror=True)
+    # same BF16 roundings on both sides; what remains is FP32 vs FP64 accumulation
+    # and the rare BF16 rounding decision it flips
+    assert rel_err(got, ref) < 5e-3
+    assert np.abs(got - ref).max() < 5e-2 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("din,h,dout,B", [(64, 512, 160, 256), (576, 128, 1952, 200)])
+def test_gradients_match_reference(rbp, din, h, dout, B):
+    net = rbp.MLP(din, h, dout, seed=7)
+    x, y, lam = _data(din, dout, B, 4, dens=0.1)
+    g, loss = net.gradients(_dev_bits(x), _dev_bits(y), torch.from_numpy(lam).cuda())
+    g = g.cpu().numpy()
+    lref, gref = R.loss_and_grads(net.get_params(), x, y, lam, din, h, dout, mirror=True)
+    assert abs(float(loss.item()) - lref) <= 1e-4 * abs(lref)
+    W1, b1, W2, b2, W3, b3 = R.split(g, din, h, dout)
+    V1, c1, V2, c2, V3, c3 = R.split(gref, din, h, dout)
+    for a, b in [(W1, V1), (b1, c1), (W2, V2), (b2, c2), (W3, V3), (b3, c3)]:
+        assert rel_err(a, b) < 1e-2
+
+
+def test_train_step_is_adam_on_the_gradients(rbp):
+    din, h, dout, B = 64, 128, 160, 512
+    net = rbp.MLP(din, h, dout, seed=9)
+    x, y, lam = _data(din, dout, B, 5)
+    xs, ys, ls = _dev_bits(x), _dev_bits(y), torch.from_numpy(lam).cuda()
+    p0 = net.get_params().astype(np.float64)
+    g, _ = net.gradients(xs, ys, ls)
+    net.train_step(xs, ys, ls, lr=1e-3)
+    p1 = net.get_params().astype(np.float64)
+    want, _, _ = R.adam(p0, g.cpu().numpy().astype(np.float64), np.zeros_like(p0), np.zeros_like(p0), 1, 1e-3)
+    assert np.abs(p1 - want).max() < 1e-6
+
+
+def test_training_reduces_loss_on_a_learnable_map(rbp):
+    """Targets are a fixed function of the inputs (y_j = x_{j mod din}); the loss
+    must fall well below its starting value."""
+    din, h, dout, B = 64, 256, 160, 1024
+    net = rbp.MLP(din, h, dout, seed=11)
+    rng = np.random.default_rng(6)
+    lam = np.full(dout, 4.0, np.float32)
+    ls = torch.from_numpy(lam).cuda()
+    loss = torch.zeros(1, device="cuda")
+    losses = []
+    for step in range(150):
+        x = (rng.random((B, din)) < 0.1).astype(np.uint8)
+        y = x[:, np.arange(dout) % din]
+        net.train_step(_dev_bits(x), _dev_bits(y), ls, lr=2e-3, loss_out=loss)
+        losses.append(float(loss.item()))
+    assert losses[-1] < 0.2 * losses[0]
+
+
+def test_forward_chunking_and_empty(rbp):
+    net = rbp.MLP(64, 64, 160, seed=1)
+    x, _, _ = _data(64, 160, 40000, 8)
+    xs = _dev_bits(x)
+    full = net.forward(xs).cpu().numpy()
+    part = net.forward(xs[17000:17100].contiguous()).cpu().numpy()
+    assert np.array_equal(full[17000:17100], part)
+    net.forward(xs[:0])
