@@ -4,8 +4,10 @@
 One step = sample a batch of shots of the phenomenological ZSZ-LP-160 model
 (9 rounds, 576 detectors x 1952 mechanisms, priors 1e-3) on the GPU, decode it
 with Relay-BP (gamma0 0.125, pre_iter 80, max_iterations 60, 100 relay legs,
-stop_nconv 5, gamma in [-0.24, 0.66]), copy the predicted observables and
-per-shot statistics back and count block failures.  Prints one JSON line.
+stop_nconv 5, gamma in [-0.24, 0.66]) and count block failures on the GPU; the
+failure count comes back to the host at the end of the timed steps.  The
+learned path adds the proposal network's forward pass before decoding.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -35,6 +37,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sequential", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-pairs", type=int, default=1_000_000)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (calibrates rocprof byte counters)")
     return ap.parse_args()
 
 
@@ -105,46 +111,65 @@ def main():
     corr = torch.empty((S, rbp.words(dem.N)), dtype=torch.int32, device=dev)
     obsp = torch.empty_like(obs)
     st = torch.empty((S, 32), dtype=torch.uint8, device=dev)
-    h_obs = torch.empty(obs.shape, dtype=torch.int32, pin_memory=True)
-    h_obsp = torch.empty(obs.shape, dtype=torch.int32, pin_memory=True)
-    h_st = torch.empty(st.shape, dtype=torch.uint8, pin_memory=True)
+    fail_count = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    if args.calib_copy_mb:
+        n = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ev = []
+    net = None
+    delta_buf = None
 
-    def step(i: int, record: bool):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)] if record else None
+    def step(i: int, record: bool, path: str = "plain"):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
         if record:
             e[0].record()
         code.sample(dem.priors, S, args.seed + i, out=(syn, obs, None))
         if record:
             e[1].record()
-        code.decode(dem.priors, syn, params, out=(corr, obsp, st))
+        delta = None
+        if path == "learned":
+            delta = net.forward(syn, out=delta_buf)
+        elif path == "proposal_zero":
+            delta = delta_buf
         if record:
             e[2].record()
+        code.decode(dem.priors, syn, params, delta=delta, out=(corr, obsp, st))
+        if record:
+            e[3].record()
             ev.append(e)
-        h_obs.copy_(obs, non_blocking=True)
-        h_obsp.copy_(obsp, non_blocking=True)
-        h_st.copy_(st, non_blocking=True)
-        torch.cuda.current_stream().synchronize()
-        s = h_st.numpy().reshape(-1).view(rbp.SHOT_STATS_DTYPE)
-        fails = stats.block_failures(h_obsp.numpy(), h_obs.numpy(), s["converged"])
-        return int(fails.sum()), s
+        rbp.count_failures(obsp, obs, st, fail_count)
+        return None
 
-    for i in range(args.warmup):
-        step(1000 + i, False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    fail_total, last = 0, None
-    for i in range(args.steps):
-        f, last = step(i, True)
-        fail_total += f
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    def timed(path: str):
+        ev.clear()
+        for i in range(args.warmup):
+            step(1000 + i, False, path)
+        torch.cuda.synchronize()
+        fail_count.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step(i, True, path)
+        fail_total = int(fail_count.item())  # synchronizes: the steps' work is inside the window
+        wall = time.perf_counter() - t0
+        last = rbp.stats_to_numpy(st).copy()
+        ms = lambda a, b: float(np.mean([e[a].elapsed_time(e[b]) for e in ev]))
+        return {"wall": wall, "fails": fail_total, "last": last, "sample_ms": ms(0, 1), "mlp_ms": ms(1, 2),
+                "decode_ms": ms(2, 3)}
+
+    P = timed("plain")
+    wall, fail_total, last = P["wall"], P["fails"], P["last"]
     ms_step = 1e3 * wall / args.steps
     value = S * args.steps / wall
 
-    dec_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
-    smp_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    dec_ms, smp_ms = P["decode_ms"], P["sample_ms"]
     iters = last["iters"].astype(np.int64)
     B_it = 8 * dem.nnz + 8 * dem.N  # algorithmic bytes of one flooding iteration of one shot
     alg_bytes = float(iters.sum()) * B_it
@@ -163,7 +188,7 @@ def main():
                         f"({dem.M} detectors x {dem.N} mechanisms, nnz {dem.nnz}), priors 1e-3, "
                         f"{S} shots per step, Relay-BP gamma0=0.125 pre_iter=80 max_iterations=60 "
                         f"num_sets=100 stop_nconv=5 gamma_dist=[-0.24,0.66], FP32 messages",
-            "shots_per_step": S, "path": "plain Relay-BP",
+            "shots_per_step": S, "path": "plain Relay-BP (value); learned proposal and delta=0 control below",
         },
         "decode_only_shots_per_s": S / (dec_ms * 1e-3),
         "decode_kernel_ms": dec_ms, "sample_kernel_ms": smp_ms,
@@ -177,6 +202,40 @@ def main():
                      "shot_iterations_per_launch": int(iters.sum())},
         "launch": code.launch_config(),
     }
+
+    if not args.no_learned:
+        from paper_2607_27644_amd import learned
+        cfg = learned.TrainConfig(pairs=args.train_pairs)
+        t0 = time.perf_counter()
+        chunks = learned.generate_pairs(code, dem.priors, cfg, params)
+        t1 = time.perf_counter()
+        net = rbp.MLP(dem.M, cfg.hidden, dem.N, seed=cfg.seed)
+        hist = learned.train(net, chunks, cfg)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        del chunks
+        delta_buf = torch.empty((S, dem.N), dtype=torch.float32, device=dev)
+        paths = {}
+        for path in ("learned", "proposal_zero"):
+            if path == "proposal_zero":
+                delta_buf.zero_()
+            R = timed(path)
+            it = R["last"]["iters"].astype(np.float64)
+            sv = (R["last"]["t_end"] - R["last"]["t_start"]).astype(np.float64) * 0.01
+            paths[path] = {
+                "value": S * args.steps / R["wall"], "unit": "shots/s", "ms_per_step": 1e3 * R["wall"] / args.steps,
+                "mlp_ms": R["mlp_ms"], "decode_kernel_ms": R["decode_ms"],
+                "ler": stats.ler_summary(R["fails"], S * args.steps, dem.rounds, dem.k),
+                "mean_iters_per_shot": float(it.mean()),
+                "path_counts": {str(k): int((R["last"]["path"] == k).sum()) for k in range(4)},
+                "latency_us": {"batched_service_time": stats.percentiles(sv)}}
+        paths["learned"]["training"] = {"pairs": cfg.pairs, "p_range": [cfg.p_lo, cfg.p_hi], "epochs": cfg.epochs,
+                                        "batch": cfg.batch, "hidden": cfg.hidden, "params": net.n_params,
+                                        "generate_s": t1 - t0, "train_s": t2 - t1, "final_loss": hist[-1][1]}
+        paths["learned"]["vs_plain"] = paths["learned"]["value"] / value
+        paths["proposal_zero"]["note"] = "control: the same proposal leg with delta = 0 (no network)"
+        out["learned"] = paths["learned"]
+        out["proposal_zero"] = paths["proposal_zero"]
 
     if not args.no_sequential:
         # the paper's latency mode: one shot per decode call, host clock around each

@@ -126,6 +126,14 @@ rbp_status rbp_decode_multi(int32_t n_codes, const rbp_code_t* codes, const doub
                             uint32_t* const* corrections_dev, uint32_t* const* obs_pred_dev,
                             rbp_shot_stats* stats_dev, void* stream);
 
+/* Block failures of a decoded batch (paper Sec. 6.1: a shot fails when any
+ * logical observable is predicted wrong or the decoder did not converge):
+ * *count_dev (uint64, device) += number of shots s with obs_pred_dev[s] !=
+ * obs_dev[s] in any of obs_words words, or stats_dev[s].converged == 0.
+ * Arrays as written by rbp_sample / rbp_decode. */
+rbp_status rbp_count_failures(const uint32_t* obs_pred_dev, const uint32_t* obs_dev, const rbp_shot_stats* stats_dev,
+                              uint64_t shots, int32_t obs_words, unsigned long long* count_dev, void* stream);
+
 /* The LLRs Lambda_j = (float) ln((1-p_j)/p_j) the decoder uses for these
  * priors, written to llr_dev float[N] (device), e.g. as the prior term of the
  * proposal network's loss. */

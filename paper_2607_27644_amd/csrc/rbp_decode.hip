@@ -144,6 +144,19 @@ __global__ void gamma_table_kernel(float* out, int32_t N, int32_t R, float gmin,
     out[idx] = __builtin_fmaf(u, span, gmin);
 }
 
+// one thread per shot; a wave-level ballot count, one atomic per wave
+__global__ void count_failures_kernel(const uint32_t* obsp, const uint32_t* obs, const rbp_shot_stats* st,
+                                      uint64_t shots, int words, unsigned long long* count) {
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool fail = false;
+    if (s < shots) {
+        fail = st[s].converged == 0;
+        for (int w = 0; w < words; ++w) fail |= obsp[s * words + w] != obs[s * words + w];
+    }
+    const unsigned long long b = __ballot(fail);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
+}
+
 __global__ void zero_u64_kernel(unsigned long long* p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
@@ -1232,6 +1245,18 @@ rbp_status rbp_decode_multi(int32_t n_codes, const rbp_code_t* codes, const doub
     a.stats = stats;
     fill_params(a, params);
     return launch_decode(cs.data(), n_codes, a, shots, stream);
+}
+
+rbp_status rbp_count_failures(const uint32_t* obsp, const uint32_t* obs, const rbp_shot_stats* st, uint64_t shots,
+                              int32_t words, unsigned long long* count, void* stream_) {
+    if (!obsp || !obs || !st || !count) return fail(RBP_ERR_INVALID_ARG, "NULL argument");
+    if (words < 0) return fail(RBP_ERR_INVALID_ARG, "obs_words < 0");
+    if (shots == 0) return RBP_OK;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    hipLaunchKernelGGL(count_failures_kernel, dim3((unsigned)ceil_div((int64_t)shots, 256)), dim3(256), 0, stream, obsp,
+                       obs, st, shots, words, count);
+    RBP_HIP_CHECK(hipGetLastError());
+    return RBP_OK;
 }
 
 rbp_status rbp_code_llr(rbp_code_t c, const double* priors, float* llr, void* stream_) {

@@ -85,12 +85,13 @@ def evaluate(code: rbp.Code, net: rbp.MLP, priors: np.ndarray, shots: int, seed:
     syn, obs, _ = code.sample(priors, shots, seed)
     torch.cuda.synchronize()
     res = {}
-    for name in ("plain", "learned"):
+    zero = torch.zeros((shots, code.N), dtype=torch.float32, device="cuda")
+    for name in ("plain", "learned", "proposal_zero"):
         times, mlp_times = [], []
         for _ in range(repeats):
             e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
             e0.record()
-            delta = net.forward(syn) if name == "learned" else None
+            delta = net.forward(syn) if name == "learned" else (zero if name == "proposal_zero" else None)
             e1.record()
             corr, obsp, st = code.decode(priors, syn, params, delta=delta)
             e2.record()
@@ -113,7 +114,7 @@ def evaluate(code: rbp.Code, net: rbp.MLP, priors: np.ndarray, shots: int, seed:
     a, b = res["plain"]["fails_mask"], res["learned"]["fails_mask"]
     res["paired"] = {"plain_only": int((a & ~b).sum()), "learned_only": int((b & ~a).sum()),
                      "both": int((a & b).sum())}
-    for name in ("plain", "learned"):
+    for name in ("plain", "learned", "proposal_zero"):
         del res[name]["fails_mask"]
     return res
 
@@ -129,7 +130,11 @@ def train_and_evaluate(dem, cfg: TrainConfig, eval_priors: np.ndarray, eval_shot
     hist = train(net, chunks, cfg)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    ev = evaluate(code, net, eval_priors, eval_shots, eval_seed, params, dem.rounds, dem.k)
+    if isinstance(eval_priors, dict):
+        ev = {key: evaluate(code, net, pr, eval_shots, eval_seed, params, dem.rounds, dem.k)
+              for key, pr in eval_priors.items()}
+    else:
+        ev = evaluate(code, net, eval_priors, eval_shots, eval_seed, params, dem.rounds, dem.k)
     ev["train"] = {"pairs": cfg.pairs, "gen_s": t1 - t0, "train_s": t2 - t1, "final_loss": hist[-1][1],
                    "steps": hist[-1][0], "params": net.n_params}
     return ev

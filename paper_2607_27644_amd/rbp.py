@@ -92,6 +92,7 @@ def lib():
         "rbp_mlp_num_params": [vp, P(i64)],
         "rbp_mlp_gradients": [vp, vp, vp, vp, u64, vp, vp, vp],
         "rbp_code_llr": [vp, vp, vp, vp],
+        "rbp_count_failures": [vp, vp, vp, u64, i32, vp, vp],
         "rbp_mlp_get_params": [vp, vp],
         "rbp_mlp_set_params": [vp, vp],
     }
@@ -252,6 +253,13 @@ def decode_multi(codes: Sequence[Code], priors: Sequence, shot_code: torch.Tenso
                                  shots, VP(*[s.data_ptr() for s in syndromes]), ctypes.byref(prm),
                                  VP(*[c.data_ptr() for c in corrections]), VP(*[o.data_ptr() for o in obs_pred]),
                                  _ptr(stats), _stream(stream)))
+
+
+def count_failures(obs_pred: torch.Tensor, obs: torch.Tensor, stats: torch.Tensor, count: torch.Tensor,
+                   stream=None):
+    """count (int64[1] on the device) += block failures of the batch (GPU reduction)."""
+    check(lib().rbp_count_failures(_ptr(obs_pred), _ptr(obs), _ptr(stats), obs.shape[0], obs.shape[1], _ptr(count),
+                                   _stream(stream)))
 
 
 def stats_to_numpy(st: torch.Tensor) -> np.ndarray:

@@ -178,6 +178,21 @@ def test_decode_matches_oracle(rbp, name, shots):
     assert a[0] <= b[1] and b[0] <= a[1]
 
 
+def test_gpu_failure_count_matches_host(rbp):
+    dem = dem_of("cc160")
+    code = rbp.Code.from_dem(dem)
+    params = rbp.RelayParams(num_sets=3, pre_iter=3, max_iterations=3)
+    pri = np.full(dem.N, 0.03)
+    syn, obs, _ = code.sample(pri, 5000, seed=2)
+    corr, obsp, st = code.decode(pri, syn, params)
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rbp.count_failures(obsp, obs, st, cnt)
+    rbp.count_failures(obsp, obs, st, cnt)
+    host = ostats.block_failures(u32(obsp), u32(obs), rbp.stats_to_numpy(st)["converged"]).sum()
+    assert host > 0
+    assert int(cnt.item()) == 2 * host
+
+
 def test_decode_random_priors_and_dense_syndromes(rbp):
     """Non-uniform priors and random (mostly unsatisfiable-looking) syndromes
     exercise long legs, relay legs and non-convergence."""
