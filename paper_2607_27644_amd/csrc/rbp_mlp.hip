@@ -209,13 +209,46 @@ __global__ void sum_partials_kernel(const float* partial, int n, float scale, fl
     if (threadIdx.x == 0) *out = red[0] * scale;
 }
 
-// out[n] = sum_b in[b][n]  (one thread per column, rows in order: deterministic)
-__global__ void colsum_kernel(const float* in, int B, int N, float* out) {
+// Column sums out[n] = sum_b in[b][n] in two deterministic stages: chunks of
+// 256 rows per block (64 columns x 4 row groups, fixed order), then the chunk
+// partials in order.
+constexpr int CS_ROWS = 256;
+__global__ void colsum_partial_kernel(const float* in, int B, int N, float* part) {
+    __shared__ float red[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
+    const int r0 = blockIdx.y * CS_ROWS;
+    float s = 0.0f;
+    if (c < N)
+        for (int r = r0 + g; r < min(B, r0 + CS_ROWS); r += 4) s += in[(int64_t)r * N + c];
+    red[g][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (g == 0 && c < N)
+        part[(int64_t)blockIdx.y * N + c] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
+                                           red[3][threadIdx.x];
+}
+
+__global__ void colsum_final_kernel(const float* part, int chunks, int N, float* out) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     float s = 0.0f;
-    for (int b = 0; b < B; ++b) s += in[(int64_t)b * N + n];
+    for (int k = 0; k < chunks; ++k) s += part[(int64_t)k * N + n];
     out[n] = s;
+}
+
+// out[c][r] = in[r][c] for a rows x cols BF16 matrix (64 x 64 tiles through LDS)
+__global__ void transpose_bf16_kernel(const bf16* in, int rows, int cols, bf16* out) {
+    __shared__ bf16 t[64][65];
+    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int gr = r0 + r, gc = c0 + tx;
+        t[r][tx] = (gr < rows && gc < cols) ? in[(int64_t)gr * cols + gc] : (bf16)0.0f;
+    }
+    __syncthreads();
+    for (int c = ty; c < 64; c += 4) {
+        const int gc = c0 + c, gr = r0 + tx;
+        if (gc < cols && gr < rows) out[(int64_t)gc * rows + gr] = t[tx][c];
+    }
 }
 
 __global__ void adam_kernel(float* w, float* mo, float* ve, const float* g, int64_t n, float lr, float b1, float b2,
@@ -246,21 +279,28 @@ struct rbp_mlp {
     int64_t n_params = 0;
     int64_t oW1, ob1, oW2, ob2, oW3, ob3;  // offsets in the parameter array
     DevBuf w, m, v, g, wb;                 // FP32 masters, Adam moments, gradients, BF16 copies
+    DevBuf w2t, w3t;                       // BF16 W2^T [hid][hid] and W3^T [hid][out] for the backward pass
     int64_t step = 0;
-    int cap = 0;                           // batch capacity of the workspace
+    int cap = 0;                           // batch capacity of the training workspace
+    int fcap = 0;                          // batch capacity of the forward workspace
     DevBuf xb, h1, h2, d3b, dh2b, dh1b;    // BF16 activations / gradients
     DevBuf delta, d3f, dh2f, dh1f, partial, loss;
+    DevBuf tA, tB, csum;                   // transposed operands of the weight gradients, column-sum partials
 };
 
 namespace {
 
-rbp_status ensure_workspace(rbp_mlp* p, int B) {
-    if (B <= p->cap) return RBP_OK;
+// forward needs x, h1, h2; training also the gradient buffers
+rbp_status ensure_workspace(rbp_mlp* p, int B, bool training) {
+    if (B <= (training ? p->cap : p->fcap)) return RBP_OK;
     const int64_t Bi = B;
     rbp_status st = RBP_OK;
     if (!st) st = p->xb.reserve(sizeof(bf16) * Bi * p->in);
     if (!st) st = p->h1.reserve(sizeof(bf16) * Bi * p->hid);
     if (!st) st = p->h2.reserve(sizeof(bf16) * Bi * p->hid);
+    if (st) return st;
+    p->fcap = std::max(p->fcap, B);
+    if (!training) return RBP_OK;
     if (!st) st = p->d3b.reserve(sizeof(bf16) * Bi * p->out);
     if (!st) st = p->dh2b.reserve(sizeof(bf16) * Bi * p->hid);
     if (!st) st = p->dh1b.reserve(sizeof(bf16) * Bi * p->hid);
@@ -270,6 +310,10 @@ rbp_status ensure_workspace(rbp_mlp* p, int B) {
     if (!st) st = p->dh1f.reserve(sizeof(float) * Bi * p->hid);
     if (!st) st = p->partial.reserve(sizeof(float) * (Bi * std::max(p->out, p->hid) / 256 + 2));
     if (!st) st = p->loss.reserve(sizeof(float) * 4);
+    const int64_t wide = std::max<int64_t>(std::max(p->out, p->hid), p->in);
+    if (!st) st = p->tA.reserve(sizeof(bf16) * Bi * wide);
+    if (!st) st = p->tB.reserve(sizeof(bf16) * Bi * wide);
+    if (!st) st = p->csum.reserve(sizeof(float) * ((Bi + CS_ROWS - 1) / CS_ROWS) * wide);
     if (st) return st;
     p->cap = B;
     return RBP_OK;
@@ -298,6 +342,23 @@ GemmArgs ga(int M, int N, int K, const bf16* A, int lda, const bf16* B, int ldb,
 }
 
 int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+rbp_status transpose(const bf16* in, int rows, int cols, bf16* out, hipStream_t s) {
+    hipLaunchKernelGGL(transpose_bf16_kernel, dim3(blocks(cols, 64), blocks(rows, 64)), dim3(256), 0, s, in, rows, cols,
+                       out);
+    RBP_HIP_CHECK(hipGetLastError());
+    return RBP_OK;
+}
+
+rbp_status colsum(rbp_mlp* p, const float* in, int B, int N, float* out, hipStream_t s) {
+    const int chunks = blocks(B, CS_ROWS);
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3(blocks(N, 64), chunks), dim3(256), 0, s, in, B, N,
+                       p->csum.as<float>());
+    RBP_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(colsum_final_kernel, dim3(blocks(N, 256)), dim3(256), 0, s, p->csum.as<float>(), chunks, N, out);
+    RBP_HIP_CHECK(hipGetLastError());
+    return RBP_OK;
+}
 
 // forward of B rows: x from syndromes, h1, h2 (workspace), delta into `dout`
 rbp_status forward(rbp_mlp* p, const uint32_t* syn, int B, float* dout, hipStream_t s) {
@@ -329,7 +390,7 @@ rbp_status forward(rbp_mlp* p, const uint32_t* syn, int B, float* dout, hipStrea
 // forward + backward of one batch into p->g (gradients of the mean loss)
 rbp_status gradients(rbp_mlp* p, const uint32_t* syn, const uint32_t* tgt, const float* llr, int B, float* loss_out,
                      hipStream_t s) {
-    rbp_status st = ensure_workspace(p, B);
+    rbp_status st = ensure_workspace(p, B, true);
     if (st) return st;
     float* delta = p->delta.as<float>();
     st = forward(p, syn, B, delta, s);
@@ -344,46 +405,50 @@ rbp_status gradients(rbp_mlp* p, const uint32_t* syn, const uint32_t* tgt, const
                        loss_out ? loss_out : p->loss.as<float>());
     RBP_HIP_CHECK(hipGetLastError());
     float* g = p->g.as<float>();
-    const bf16* wb = p->wb.as<bf16>();
+    bf16* tA = p->tA.as<bf16>();
+    bf16* tB = p->tB.as<bf16>();
+    // Weight gradients dW = dY^T X are NT products of the transposed operands
+    // (both K = batch contiguous); dX = dY W uses the transposed weight copies.
     // dW3 = d3^T h2 ; db3 = colsum d3 ; dh2 = (d3 W3) * [h2 > 0]
-    GemmArgs a = ga(p->out, p->hid, B, p->d3b.as<bf16>(), p->out, p->h2.as<bf16>(), p->hid, p->hid);
+    if ((st = transpose(p->d3b.as<bf16>(), B, p->out, tA, s))) return st;
+    if ((st = transpose(p->h2.as<bf16>(), B, p->hid, tB, s))) return st;
+    GemmArgs a = ga(p->out, p->hid, B, tA, B, tB, B, p->hid);
     a.out_f32 = g + p->oW3;
-    if ((st = gemm<MN_CONTIG, MN_CONTIG, EPI_F32>(a, s))) return st;
-    hipLaunchKernelGGL(colsum_kernel, dim3(blocks(p->out, 256)), dim3(256), 0, s, p->d3f.as<float>(), B, p->out,
-                       g + p->ob3);
-    RBP_HIP_CHECK(hipGetLastError());
-    a = ga(B, p->hid, p->out, p->d3b.as<bf16>(), p->out, wb + p->oW3, p->hid, p->hid);
+    if ((st = gemm<K_CONTIG, K_CONTIG, EPI_F32>(a, s))) return st;
+    if ((st = colsum(p, p->d3f.as<float>(), B, p->out, g + p->ob3, s))) return st;
+    a = ga(B, p->hid, p->out, p->d3b.as<bf16>(), p->out, p->w3t.as<bf16>(), p->out, p->hid);
     a.mask = p->h2.as<bf16>();
     a.out_bf16 = p->dh2b.as<bf16>();
     a.out_f32 = p->dh2f.as<float>();
-    if ((st = gemm<K_CONTIG, MN_CONTIG, EPI_MASK_BF16_F32>(a, s))) return st;
+    if ((st = gemm<K_CONTIG, K_CONTIG, EPI_MASK_BF16_F32>(a, s))) return st;
     // dW2 = dh2^T h1 ; db2 ; dh1 = (dh2 W2) * [h1 > 0]
-    a = ga(p->hid, p->hid, B, p->dh2b.as<bf16>(), p->hid, p->h1.as<bf16>(), p->hid, p->hid);
+    if ((st = transpose(p->dh2b.as<bf16>(), B, p->hid, tA, s))) return st;
+    if ((st = transpose(p->h1.as<bf16>(), B, p->hid, tB, s))) return st;
+    a = ga(p->hid, p->hid, B, tA, B, tB, B, p->hid);
     a.out_f32 = g + p->oW2;
-    if ((st = gemm<MN_CONTIG, MN_CONTIG, EPI_F32>(a, s))) return st;
-    hipLaunchKernelGGL(colsum_kernel, dim3(blocks(p->hid, 256)), dim3(256), 0, s, p->dh2f.as<float>(), B, p->hid,
-                       g + p->ob2);
-    RBP_HIP_CHECK(hipGetLastError());
-    a = ga(B, p->hid, p->hid, p->dh2b.as<bf16>(), p->hid, wb + p->oW2, p->hid, p->hid);
+    if ((st = gemm<K_CONTIG, K_CONTIG, EPI_F32>(a, s))) return st;
+    if ((st = colsum(p, p->dh2f.as<float>(), B, p->hid, g + p->ob2, s))) return st;
+    a = ga(B, p->hid, p->hid, p->dh2b.as<bf16>(), p->hid, p->w2t.as<bf16>(), p->hid, p->hid);
     a.mask = p->h1.as<bf16>();
     a.out_bf16 = p->dh1b.as<bf16>();
     a.out_f32 = p->dh1f.as<float>();
-    if ((st = gemm<K_CONTIG, MN_CONTIG, EPI_MASK_BF16_F32>(a, s))) return st;
+    if ((st = gemm<K_CONTIG, K_CONTIG, EPI_MASK_BF16_F32>(a, s))) return st;
     // dW1 = dh1^T x ; db1
-    a = ga(p->hid, p->in, B, p->dh1b.as<bf16>(), p->hid, p->xb.as<bf16>(), p->in, p->in);
+    if ((st = transpose(p->dh1b.as<bf16>(), B, p->hid, tA, s))) return st;
+    if ((st = transpose(p->xb.as<bf16>(), B, p->in, tB, s))) return st;
+    a = ga(p->hid, p->in, B, tA, B, tB, B, p->in);
     a.out_f32 = g + p->oW1;
-    if ((st = gemm<MN_CONTIG, MN_CONTIG, EPI_F32>(a, s))) return st;
-    hipLaunchKernelGGL(colsum_kernel, dim3(blocks(p->hid, 256)), dim3(256), 0, s, p->dh1f.as<float>(), B, p->hid,
-                       g + p->ob1);
-    RBP_HIP_CHECK(hipGetLastError());
-    return RBP_OK;
+    if ((st = gemm<K_CONTIG, K_CONTIG, EPI_F32>(a, s))) return st;
+    return colsum(p, p->dh1f.as<float>(), B, p->hid, g + p->ob1, s);
 }
 
 rbp_status refresh_bf16(rbp_mlp* p, hipStream_t s) {
     hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(p->n_params, 256)), dim3(256), 0, s, p->w.as<float>(),
                        p->wb.as<bf16>(), p->n_params);
     RBP_HIP_CHECK(hipGetLastError());
-    return RBP_OK;
+    rbp_status st = transpose(p->wb.as<bf16>() + p->oW2, p->hid, p->hid, p->w2t.as<bf16>(), s);
+    if (st) return st;
+    return transpose(p->wb.as<bf16>() + p->oW3, p->out, p->hid, p->w3t.as<bf16>(), s);
 }
 
 rbp_status zero_adam(rbp_mlp* p) {
@@ -434,6 +499,8 @@ rbp_status rbp_mlp_create(int32_t in_dim, int32_t hidden, int32_t out_dim, uint6
     if (!st) st = p->v.reserve(sizeof(float) * o);
     if (!st) st = p->g.reserve(sizeof(float) * o);
     if (!st) st = p->wb.reserve(sizeof(bf16) * o);
+    if (!st) st = p->w2t.reserve(sizeof(bf16) * (int64_t)hidden * hidden);
+    if (!st) st = p->w3t.reserve(sizeof(bf16) * (int64_t)hidden * out_dim);
     if (!st) {
         hipError_t e = hipMemcpy(p->w.p, h.data(), sizeof(float) * o, hipMemcpyHostToDevice);
         if (e != hipSuccess) st = fail(RBP_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
@@ -455,8 +522,9 @@ rbp_status rbp_mlp_create(int32_t in_dim, int32_t hidden, int32_t out_dim, uint6
 rbp_status rbp_mlp_destroy(rbp_mlp_t p) {
     if (!p) return RBP_OK;
     (void)hipDeviceSynchronize();
-    for (DevBuf* b : {&p->w, &p->m, &p->v, &p->g, &p->wb, &p->xb, &p->h1, &p->h2, &p->d3b, &p->dh2b, &p->dh1b,
-                      &p->delta, &p->d3f, &p->dh2f, &p->dh1f, &p->partial, &p->loss})
+    for (DevBuf* b : {&p->w, &p->m, &p->v, &p->g, &p->wb, &p->w2t, &p->w3t, &p->xb, &p->h1, &p->h2, &p->d3b,
+                      &p->dh2b, &p->dh1b, &p->delta, &p->d3f, &p->dh2f, &p->dh1f, &p->partial, &p->loss, &p->tA,
+                      &p->tB, &p->csum})
         b->release();
     delete p;
     return RBP_OK;
@@ -467,8 +535,8 @@ rbp_status rbp_mlp_forward(rbp_mlp_t p, const uint32_t* syndromes, uint64_t shot
     if (shots == 0) return RBP_OK;
     if (!syndromes || !delta) return fail(RBP_ERR_INVALID_ARG, "NULL buffer");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
-    const int chunk = 16384;
-    rbp_status st = ensure_workspace(p, (int)std::min<uint64_t>(shots, chunk));
+    const int chunk = 65536;
+    rbp_status st = ensure_workspace(p, (int)std::min<uint64_t>(shots, chunk), false);
     if (st) return st;
     const int words = (p->in + 31) / 32;
     for (uint64_t b0 = 0; b0 < shots; b0 += chunk) {

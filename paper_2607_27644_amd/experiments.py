@@ -1,0 +1,172 @@
+"""Measurements of the decoding path on its workload configurations.
+
+    python -m paper_2607_27644_amd.experiments <name> [options]   -> one JSON object
+
+names:
+  multi      batched uneven decode: one persistent launch over several models
+             with shots interleaved (shot i -> model i mod n), against one
+             tuned launch per model
+  large      a large model (phenomenological [[840,168]] code, 12 rounds, or the
+             seeded hypergraph-product code with n1 = 56): throughput, per-shot
+             service time, LER
+  latency    sequential single-shot latency (one decode call per shot, host
+             clock) and the all-legs worst case (stopping_criterion = 1)
+  learned    train the proposal network on decoder-generated pairs and compare
+             plain Relay-BP, the proposal and the delta = 0 control
+All inputs are seeded and synthetic (see workloads.py).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import autotune, learned, rbp, stats, workloads
+
+
+def _timed(fn, repeats: int = 3):
+    best, out = float("inf"), None
+    for _ in range(repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best, out
+
+
+def _summary(dem, obs, obsp, st, shots, ms):
+    s = rbp.stats_to_numpy(st)
+    fails = stats.block_failures(rbp.to_u32(obsp), rbp.to_u32(obs), s["converged"])
+    svc = (s["t_end"] - s["t_start"]).astype(np.float64) * 0.01
+    return {"shots": shots, "ms": ms, "shots_per_s": shots / (ms * 1e-3),
+            "ler": stats.ler_summary(int(fails.sum()), shots, dem.rounds, dem.k),
+            "mean_iters": float(s["iters"].mean()), "max_iters": int(s["iters"].max()),
+            "service_us": stats.percentiles(svc)}
+
+
+def multi(names, shots_each: int, seed: int = 11, params: rbp.RelayParams | None = None) -> dict:
+    params = params or rbp.RelayParams()
+    dems = [workloads.workload(n) for n in names]
+    codes = [rbp.Code.from_dem(d) for d in dems]
+    n = len(dems)
+    syns, obss = [], []
+    for i, (d, c) in enumerate(zip(dems, codes)):
+        syn, obs, _ = c.sample(d.priors, shots_each, seed + i)
+        syns.append(syn)
+        obss.append(obs)
+    total = n * shots_each
+    idx = torch.arange(total, device="cuda")
+    shot_code = (idx % n).to(torch.uint8)
+    shot_index = (idx // n).to(torch.int32)
+    corrs = [torch.empty((shots_each, rbp.words(d.N)), dtype=torch.int32, device="cuda") for d in dems]
+    obsps = [torch.empty((shots_each, max(rbp.words(d.k), 1)), dtype=torch.int32, device="cuda") for d in dems]
+    st = torch.empty((total, 32), dtype=torch.uint8, device="cuda")
+    res = {"models": [{"name": nm, "M": d.M, "N": d.N, "nnz": d.nnz, "k": d.k} for nm, d in zip(names, dems)],
+           "shots_each": shots_each, "one_launch": {}, "per_model_launches": {}}
+    # one launch, every launch shape
+    for waves in (4, 8, 16):
+        for state in (1, 2):
+            try:
+                codes[0].set_launch_config(waves, state, 0)
+                ms, _ = _timed(lambda: rbp.decode_multi(codes, [d.priors for d in dems], shot_code, shot_index,
+                                                        syns, params, corrs, obsps, st))
+                res["one_launch"][f"waves{waves}_state{state}"] = {"ms": ms, "shots_per_s": total / (ms * 1e-3)}
+            except rbp.RbpError as ex:
+                res["one_launch"][f"waves{waves}_state{state}"] = {"error": str(ex)}
+    best = min((v for v in res["one_launch"].values() if "ms" in v), key=lambda v: v["ms"])
+    res["one_launch_best"] = best
+    codes[0].set_launch_config(0, 0, 0)
+    # per model, each tuned
+    tot_ms = 0.0
+    for nm, d, c, syn in zip(names, dems, codes, syns):
+        tr = autotune.tune(c, d.H, d.priors, params, use_cache=False)
+        ms, _ = _timed(lambda: c.decode(d.priors, syn, params))
+        tot_ms += ms
+        res["per_model_launches"][nm] = {"ms": ms, "shots_per_s": shots_each / (ms * 1e-3),
+                                         "waves": tr["waves_per_shot"], "state": tr["state"]}
+    res["per_model_total"] = {"ms": tot_ms, "shots_per_s": total / (tot_ms * 1e-3)}
+    return res
+
+
+def large(name: str, shots: int, seed: int = 21, params: rbp.RelayParams | None = None, tune: bool = True) -> dict:
+    params = params or rbp.RelayParams()
+    t0 = time.perf_counter()
+    dem = workloads.workload(name)
+    t1 = time.perf_counter()
+    code = rbp.Code.from_dem(dem)
+    tr = autotune.tune(code, dem.H, dem.priors, params, shots=min(shots, 4000), use_cache=False) if tune else None
+    syn, obs, _ = code.sample(dem.priors, shots, seed)
+    ms, out = _timed(lambda: code.decode(dem.priors, syn, params), repeats=2)
+    r = _summary(dem, obs, out[1], out[2], shots, ms)
+    r.update({"model": {"name": name, "M": dem.M, "N": dem.N, "nnz": dem.nnz, "k": dem.k, "rounds": dem.rounds},
+              "build_s": t1 - t0, "tuned": tr, "launch": code.launch_config(),
+              "algorithmic_bytes_per_shot_iteration": 8 * dem.nnz + 8 * dem.N})
+    it = rbp.stats_to_numpy(out[2])["iters"].astype(np.float64).sum()
+    r["algorithmic_GBps"] = it * (8 * dem.nnz + 8 * dem.N) / (ms * 1e-3) / 1e9
+    return r
+
+
+def latency(name: str, shots: int = 300, all_shots: int = 100, seed: int = 31) -> dict:
+    params = rbp.RelayParams()
+    dem = workloads.workload(name)
+    code = rbp.Code.from_dem(dem)
+    syn, _, _ = code.sample(dem.priors, shots, seed)
+    out = code.decode(dem.priors, syn[:1], params)
+    torch.cuda.synchronize()
+    lat = []
+    for i in range(shots):
+        t0 = time.perf_counter()
+        code.decode(dem.priors, syn[i:i + 1], params, out=out)
+        torch.cuda.synchronize()
+        lat.append(1e6 * (time.perf_counter() - t0))
+    allp = rbp.RelayParams(stopping_criterion=1)
+    lat_all = []
+    for i in range(all_shots):
+        t0 = time.perf_counter()
+        code.decode(dem.priors, syn[i:i + 1], allp, out=out)
+        torch.cuda.synchronize()
+        lat_all.append(1e6 * (time.perf_counter() - t0))
+    return {"model": {"name": name, "M": dem.M, "N": dem.N, "nnz": dem.nnz},
+            "sequential_us": stats.percentiles(np.array(lat)),
+            "all_legs_us": stats.percentiles(np.array(lat_all)), "launch": code.launch_config()}
+
+
+def learned_exp(name: str, pairs: int, eval_shots: int, p_eval, p_lo: float, p_hi: float) -> dict:
+    dem = workloads.workload(name)
+    cfg = learned.TrainConfig(pairs=pairs, p_lo=p_lo, p_hi=p_hi)
+    evals = {f"{p:g}": np.full(dem.N, p) for p in p_eval}
+    return learned.train_and_evaluate(dem, cfg, evals, eval_shots, 777)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what")
+    ap.add_argument("--models", default="phen160,phen320,phen550,phen775")
+    ap.add_argument("--model", default="phen840")
+    ap.add_argument("--shots", type=int, default=100000)
+    ap.add_argument("--pairs", type=int, default=1000000)
+    ap.add_argument("--p-eval", default="1e-3")
+    ap.add_argument("--p-range", default="5e-4,2e-3")
+    a = ap.parse_args()
+    torch.cuda.set_device(0)
+    if a.what == "multi":
+        r = multi(a.models.split(","), a.shots)
+    elif a.what == "large":
+        r = large(a.model, a.shots)
+    elif a.what == "latency":
+        r = latency(a.model, a.shots)
+    elif a.what == "learned":
+        lo, hi = (float(x) for x in a.p_range.split(","))
+        r = learned_exp(a.model, a.pairs, a.shots, [float(x) for x in a.p_eval.split(",")], lo, hi)
+    else:
+        raise SystemExit(__doc__)
+    print(json.dumps(r, default=float), flush=True)
+
+
+if __name__ == "__main__":
+    main()
