@@ -74,25 +74,33 @@ struct rbp_code {
     int32_t max_row_deg = 0, max_col_deg = 0;
     int device = 0;
     int num_cus = 0;
+    // wave-group layout of the decoder (64 rows or variables per group)
+    int32_t S = 0;                      // edge slots (>= E)
+    int32_t GR = 0, GV = 0, Np = 0;     // row groups, variable groups, 64 GV
+    int32_t RB = 0;                     // length of the row position table
+    int32_t max_stored_row_deg = 0;     // largest stored row degree (<= 12, 16, 24 or 32)
+    std::vector<int32_t> h_vord;        // host copy of vord
     // device copies
-    int32_t P = 12;                         // row stride of the padded tables (12 or 32)
-    rbp::DevBuf row_ptr, col_idx;           // CSR of H: row_ptr[M+1], col_idx[E]
-    rbp::DevBuf rpos;                       // [M][P] CSC slot of each edge of a row, -1 padded
-    rbp::DevBuf col_ptr, csc_row;           // CSC of H: col_ptr[N+1], csc_row[E]
-    rbp::DevBuf orow_ptr, ocol_idx;    // CSR of O: orow_ptr[k+1], ocol_idx[nnzO]
-    rbp::DevBuf ocol_ptr, orow_idx;    // CSC of O (sampler)
+    rbp::DevBuf row_ptr, col_idx;       // CSR of H: row_ptr[M+1], col_idx[E]
+    rbp::DevBuf col_ptr, csc_row;       // CSC of H: col_ptr[N+1], csc_row[E]
+    rbp::DevBuf rgrp, rposp, rposw;     // row groups {offset, degree, mixed, 0}; slot byte offsets (read, write)
+    rbp::DevBuf rord;                   // check at each row position
+    rbp::DevBuf vgrp, vord, vdeg, pinv; // variable groups {first slot, degree, mixed, 0}, order, degrees, inverse
+    rbp::DevBuf scheck, scsc;           // check and CSC edge of each slot
+    rbp::DevBuf orow_ptr, ocol_idx;     // CSR of O: orow_ptr[k+1], ocol_idx[nnzO]
+    rbp::DevBuf ocol_ptr, orow_idx;     // CSC of O (sampler)
     // per-call data (cached by content)
-    rbp::DevBuf thr;                   // uint32[N] sampling thresholds
+    rbp::DevBuf thr;                    // uint32[N] sampling thresholds
     std::vector<double> thr_key;
-    rbp::DevBuf lam;                   // float[N] LLRs
-    rbp::DevBuf m1;                    // float[M][P] first-iteration message magnitudes (row layout)
+    rbp::DevBuf lam, lamp;              // float LLRs by variable [N] and by position [Np]
+    rbp::DevBuf m1;                     // float[RB] first-iteration message magnitudes (layout of rposp)
     std::vector<double> lam_key;
-    rbp::DevBuf gtab;                  // float[R][N] relay-leg memory strengths
+    rbp::DevBuf gtab;                   // float[max(R,1)][Np] relay-leg memory strengths by position
     uint64_t gtab_seed = 0;
     float gtab_lo = 0.f, gtab_hi = 0.f;
     int32_t gtab_R = -1;
-    rbp::DevBuf queue;                 // work counters of the persistent decoder
-    rbp::DevBuf gstate;                // per-slot state when it does not fit in LDS
+    rbp::DevBuf queue;                  // work counter of the persistent decoder
+    rbp::DevBuf gstate;                 // per-slot state when it does not fit in LDS
     rbp::DevBuf trace_hit;
     rbp::LaunchCfg cfg;
 };

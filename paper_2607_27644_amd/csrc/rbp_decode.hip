@@ -131,13 +131,21 @@ __global__ void __launch_bounds__(64 * kSampleWaves) sample_kernel(const SampleA
 }
 
 // ---------------------------------------------------------------------------
-// Relay-leg memory strengths gamma_j^(r), r = 1..R: table[(r-1)*N + j]
+// Relay-leg memory strengths gamma_j^(r), r = 1..R, drawn per variable j from
+// Philox (key = gamma seed, counter = (j/4, r, 0, 1), word j%4) and stored by
+// variable position (see the layout below): table[(r-1)*Np + pos].
 // ---------------------------------------------------------------------------
-__global__ void gamma_table_kernel(float* out, int32_t N, int32_t R, float gmin, float gmax, uint64_t seed) {
+__global__ void gamma_table_kernel(float* out, const int32_t* vord, int32_t Np, int32_t R, float gmin, float gmax,
+                                   uint64_t seed) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)N * R;
+    const int64_t total = (int64_t)Np * R;
     if (idx >= total) return;
-    const int32_t r = (int32_t)(idx / N) + 1, j = (int32_t)(idx % N);
+    const int32_t r = (int32_t)(idx / Np) + 1, pos = (int32_t)(idx % Np);
+    const int32_t j = vord[pos];
+    if (j < 0) {
+        out[idx] = 0.0f;
+        return;
+    }
     const U4 o = philox4x32_10(U4{(uint32_t)(j >> 2), (uint32_t)r, 0u, 1u}, (uint32_t)seed, (uint32_t)(seed >> 32));
     const float u = (float)(u4_get(o, j & 3) >> 8) * (1.0f / 16777216.0f);
     const float span = gmax - gmin;
@@ -164,28 +172,54 @@ __global__ void zero_u64_kernel(unsigned long long* p, int n) {
 // ---------------------------------------------------------------------------
 // Persistent Relay-BP
 //
-// State of a shot slot: one float per Tanner-graph edge, X[E], in CSC order
-// (the edges of a variable are contiguous, checks ascending).  The check sweep
-// reads nu_{j->i} from X and overwrites it with mu_{i->j}; the variable sweep
-// reads mu, forms the marginal M_j and overwrites X with nu_{j->i} = M_j - mu.
-// So the two sweeps work in place on a single array, and the marginals live in
-// the registers of the thread that owns the variable (or in Mg[N] when the
-// index lists are not cached in registers).  The first iteration of a plain
-// leg reads no state: nu(0) = Lambda, so mu(1) = (-1)^sigma_i * (min of the
-// other Lambda of the row), a per-model table m1[E] computed once per priors.
+// A shot slot's state is one float per Tanner-graph edge slot, X[S], plus the
+// marginals Mg[Np].  The check sweep reads nu_{j->i} from X and overwrites it
+// in place with mu_{i->j}; the variable sweep reads mu, forms the marginal M_j
+// and overwrites X with nu_{j->i} = M_j - mu_{i->j}.
+//
+// Layout, chosen for 64-lane wavefronts:
+//  * Variables are sorted by degree (descending, stable) and cut into groups
+//    of 64.  Lane l of group g owns the variable at position 64 g + l, and the
+//    q-th edge of that variable (q-th check in ascending order) lives in slot
+//    vbase_g + 64 q + l.  A wave's loads and stores of X in the variable sweep
+//    are unit-stride (no LDS bank conflicts) with the slot step folded into the
+//    instruction's offset, and Mg is kept by position.
+//  * Checks are sorted and grouped the same way.  Lane l of row group g owns
+//    the check at row position 64 g + l; the byte offsets of its edge slots
+//    sit at rposp[rbase_g + 64 p + l] (columns ascending), one unit-stride load
+//    per p for the whole wave.
+//  * Every member of a group has the group's degree, except in the few groups
+//    that straddle a degree boundary or are partial ("mixed").  Loops over a
+//    member's edges therefore have a wave-uniform trip count and are unrolled
+//    per degree; mixed row groups pad their rows with the offset of X[S], a
+//    read-only +inf cell (neutral for both minima and the sign product), and
+//    redirect those writes to X[S+1]; mixed variable groups mask their sums.
+// The first iteration of a plain leg reads no state: nu(0) = Lambda, so
+// mu(1) = (-1)^sigma_i * (least |Lambda| of the other variables of the row),
+// a per-model table (layout of rposp) computed once per priors.
 // ---------------------------------------------------------------------------
 constexpr int kMaxModels = 8;
+constexpr int kShotRun = 4;  // shots taken per queue atomic while many remain
 
 struct DecodeModel {
-    int32_t M, N, E, k, WM, WN, WK, P;  // P: row stride of rpos/m1p (<= RD of the kernel)
-    const int32_t* rpos;      // [M][P] CSC slot of each edge of a row (columns ascending), -1 padded
-    const int32_t* col_ptr;   // [N+1]
-    const int32_t* csc_row;   // [E] check of each CSC slot
+    int32_t M, N, E, k, WM, WN, WK;
+    int32_t S;             // edge slots; X[S] = +inf (read-only padding cell), X[S+1] write-only cell
+    int32_t GR, GV, Np;    // row groups, variable groups, Np = 64 GV variable positions
+    const int4* rgrp;      // [GR] {offset in rposp, stored degree, mixed, 0}
+    const int32_t* rposp;  // byte offsets 4 x slot of the edges of each row, 4 S for padding
+    const int32_t* rposw;  // the same for writes, 4 (S + 1) for padding
+    const float* m1pp;     // first-iteration magnitudes, layout of rposp
+    const int32_t* rord;   // [64 GR] check at each row position, -1 for padding
+    const int4* vgrp;      // [GV] {first slot, degree, mixed, 0}
+    const int32_t* vord;   // [Np] variable at each position, -1 for padding
+    const int32_t* vdeg;   // [Np] degree at each position (0 for padding)
+    const int32_t* pinv;   // [N] position of each variable
+    const int32_t* scheck; // [S] check of each slot (-1 unused)
+    const int32_t* scsc;   // [S] CSC edge index of each slot (-1 unused)
+    const float* lamp;     // [Np] Lambda by position (0 for padding)
+    const float* gtabp;    // [max(R,1)][Np] relay-leg memory strengths by position
     const int32_t* ocol_ptr;  // [N+1] observables, CSC
     const int32_t* orow_idx;
-    const float* lam;         // [N] Lambda
-    const float* m1p;         // [M][P] first-iteration message magnitudes, row layout
-    const float* gtab;        // [R][N] relay-leg memory strengths
     const uint32_t* syn;
     uint32_t* corr;
     uint32_t* obsp;
@@ -202,8 +236,9 @@ struct DecodeLaunch {
     unsigned long long* queue;
     float* gstate;
     int64_t gstate_stride;
-    int32_t Emax;
-    int32_t off_sig, off_par, off_best, off_obs;  // byte offsets in dynamic LDS
+    int32_t Smax;  // device-memory state: marginals at X + Smax + 4
+    // byte offsets in dynamic LDS (X itself starts at 0 when it lives there)
+    int32_t off_M, off_sig, off_sigp, off_par, off_bestp, off_best, off_obs, off_misc;
     float gamma0;
     int32_t T0, Tr, R, S, crit;
     int32_t trace_on, trace_phase, trace_leg, trace_t;
@@ -212,12 +247,25 @@ struct DecodeLaunch {
     int32_t* trace_hit;
 };
 
-// first-iteration magnitudes in the padded row layout:
-// m1p[i*P + p] = min over the other variables j' of row i of Lambda_j'
-__global__ void first_message_kernel(const int32_t* row_ptr, const int32_t* col_idx, const float* lam, float* m1p,
-                                     int32_t M, int32_t P) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M) return;
+// Per-slot scalars, in dynamic LDS (the kernel has no static LDS, so that X
+// can start at address 0 and a slot's byte offset is its LDS address).
+struct SlotMisc {
+    unsigned long long shot;
+    double W;
+    int32_t count;
+    int32_t pad;
+    int32_t red[16];
+};
+
+// mu(1) magnitudes of a plain leg in the layout of rposp:
+// m1pp[rbase_g + 64 p + l] = least |Lambda_j'| over the other variables j' of the row
+__global__ void first_message_kernel(const int32_t* row_ptr, const int32_t* col_idx, const int32_t* rord,
+                                     const int4* rgrp, const float* lam, float* m1pp, int32_t npos) {
+    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= npos) return;
+    const int i = rord[pos];
+    if (i < 0) return;
+    float* out = m1pp + rgrp[pos >> 6].x + (pos & 63);
     const int rs = row_ptr[i], re = row_ptr[i + 1];
     float min1 = INFINITY, min2 = INFINITY;
     for (int e = rs; e < re; ++e) {
@@ -227,7 +275,7 @@ __global__ void first_message_kernel(const int32_t* row_ptr, const int32_t* col_
     }
     for (int e = rs; e < re; ++e) {
         const float av = fabsf(lam[col_idx[e]]);
-        m1p[(int64_t)i * P + (e - rs)] = (av == min1) ? min2 : min1;
+        out[64 * (e - rs)] = (av == min1) ? min2 : min1;
     }
 }
 
@@ -244,146 +292,225 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
     return s;
 }
 
-// One check row of the min-sum update, in place on X.  pos[p] is the CSC slot
-// of the row's p-th edge; slots past the row's degree hold E, the index of a
-// read-only +inf cell (neutral for both minima and for the sign product), and
-// their results go to the write-only cell E + 1.  nu -> mu with
-//   mu_p = (-1)^sigma * prod_{q != p} s(nu_q) * min_{q != p} |nu_q|.
-// The sign product is the XOR of the IEEE sign bits (nu is never -0: it is a
-// difference of floats or a positive prior, and x - x = +0); |nu| is compared as
-// an unsigned integer, which orders non-negative floats exactly as the floats;
-// the minimum over the others is the second minimum exactly when |nu_p| is the
-// first (with a tie both are equal).
-template <int RD>
-__device__ __forceinline__ void check_row(float* X, const int (&pos)[RD], int E, uint32_t sbit, bool first,
-                                          const float (&m1v)[RD]) {
-    const int wdummy = E + 1;
+// median of three unsigned values: the new second minimum, given min1 <= min2
+__device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+typedef __attribute__((address_space(3))) float lds_float;
+
+// Access to a slot's state by byte offset.  In LDS the state starts at LDS
+// address 0 (the kernel declares no static LDS, so its dynamic LDS begins
+// there) and a byte offset is the address itself; in device memory it is
+// added to the slot's base pointer.
+template <bool LDS>
+struct State {
+    float* g;
+    __device__ __forceinline__ float ld(uint32_t off) const {
+        if constexpr (LDS)
+            return *reinterpret_cast<const lds_float*>((size_t)off);
+        else
+            return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(g) + (uint64_t)off);
+    }
+    __device__ __forceinline__ void st(uint32_t off, float v) const {
+        if constexpr (LDS)
+            *reinterpret_cast<lds_float*>((size_t)off) = v;
+        else
+            *reinterpret_cast<float*>(reinterpret_cast<char*>(g) + (uint64_t)off) = v;
+    }
+};
+
+// element i of a read-only table, addressed as base + 32-bit byte offset
+template <class T>
+__device__ __forceinline__ T ldg(const T* base, uint32_t i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint64_t)(i * (uint32_t)sizeof(T)));
+}
+
+// One check row of the min-sum update with D edge slots, in place on X.  The
+// magnitudes compare as unsigned integers (|nu| bit patterns order like the
+// floats); the outgoing sign is sigma_i times the signs of the other nu.  On the
+// first iteration of a plain leg the messages come from the m1 table.  rp, wp
+// and mp point at the lane's first entry of the read-offset, write-offset and
+// m1 tables (stride 64); rows of a mixed group read padding from the +inf cell
+// and write it to the write-only cell.
+template <int D, bool MIXED, bool LDS>
+__device__ __forceinline__ void check_row(const State<LDS> X, const int32_t* rp, const int32_t* wp, const float* mp,
+                                          uint32_t sbit, bool first) {
+    uint32_t pos[D], wpos[D];
+#pragma unroll
+    for (int p = 0; p < D; ++p) pos[p] = (uint32_t)rp[64 * p];
+#pragma unroll
+    for (int p = 0; p < D; ++p) wpos[p] = MIXED ? (uint32_t)wp[64 * p] : pos[p];
     if (first) {
 #pragma unroll
-        for (int p = 0; p < RD; ++p) {
-            const int w = pos[p] == E ? wdummy : pos[p];
-            X[w] = __uint_as_float(__float_as_uint(m1v[p]) | sbit);
-        }
+        for (int p = 0; p < D; ++p) X.st(wpos[p], __uint_as_float(__float_as_uint(mp[64 * p]) | sbit));
         return;
     }
-    uint32_t nu[RD];
-    uint32_t sgn = sbit;
-    uint32_t min1 = 0x7f800000u, min2 = 0x7f800000u;
+    uint32_t nu[D], av[D];
 #pragma unroll
-    for (int p = 0; p < RD; ++p) {
-        const uint32_t v = __float_as_uint(X[pos[p]]);
-        nu[p] = v;
-        sgn ^= v;
-        const uint32_t av = v & 0x7fffffffu;
-        const uint32_t lo2 = min2 < av ? min2 : av;
-        min2 = min1 > lo2 ? min1 : lo2;  // median of (min1, min2, av) given min1 <= min2
-        min1 = min1 < av ? min1 : av;
+    for (int p = 0; p < D; ++p) nu[p] = __float_as_uint(X.ld(pos[p]));
+    uint32_t min1 = 0x7f800000u, min2 = 0x7f800000u, sgn = sbit;
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+        av[p] = nu[p] & 0x7fffffffu;
+        sgn ^= nu[p];
+        min2 = umed3(min1, min2, av[p]);
+        min1 = min1 < av[p] ? min1 : av[p];
     }
 #pragma unroll
-    for (int p = 0; p < RD; ++p) {
-        const uint32_t av = nu[p] & 0x7fffffffu;
-        const uint32_t mag = (av == min1) ? min2 : min1;
-        const int w = pos[p] == E ? wdummy : pos[p];
-        X[w] = __uint_as_float(mag | ((sgn ^ nu[p]) & 0x80000000u));
+    for (int p = 0; p < D; ++p) {
+        const uint32_t mag = (av[p] == min1) ? min2 : min1;
+        X.st(wpos[p], __uint_as_float(mag | ((sgn ^ nu[p]) & 0x80000000u)));
     }
 }
 
-// A variable whose hard decision flips toggles the parity of its checks and
-// moves the solution weight by +-Lambda_j (double; sums of FP32 values of
-// this range are exact, so the order of the atomics does not matter).
-__device__ __forceinline__ void flip_variable(const int32_t* csc_row, int s0, int d, bool now_neg, float lamj,
-                                              uint32_t* par, int& dcount, double& dW) {
-    for (int e = s0; e < s0 + d; ++e) {
-        const int i = csc_row[e];
+template <int D, bool LDS>
+__device__ __forceinline__ void check_row_d(const State<LDS> X, const int32_t* rp, const int32_t* wp,
+                                            const float* mp, bool mixed, uint32_t sbit, bool first) {
+    if (mixed)
+        check_row<D, true>(X, rp, wp, mp, sbit, first);
+    else
+        check_row<D, false>(X, rp, wp, mp, sbit, first);
+}
+
+// stored row degrees: 2..12 exactly, larger rows padded to 16, 24 or 32 slots
+template <int RD, bool LDS>
+__device__ __forceinline__ void check_dispatch(const State<LDS> X, const int32_t* rp, const int32_t* wp,
+                                               const float* mp, int dg, bool mixed, uint32_t sbit, bool first) {
+    switch (dg) {
+#define RBP_ROW(D) \
+    case D: check_row_d<D>(X, rp, wp, mp, mixed, sbit, first); break;
+        RBP_ROW(2) RBP_ROW(3) RBP_ROW(4) RBP_ROW(5) RBP_ROW(6) RBP_ROW(7)
+        RBP_ROW(8) RBP_ROW(9) RBP_ROW(10) RBP_ROW(11) RBP_ROW(12)
+        default:
+            if constexpr (RD > 12) {
+                switch (dg) {
+                    RBP_ROW(16) RBP_ROW(24) RBP_ROW(32)
+                    default: break;
+                }
+            }
+            break;
+#undef RBP_ROW
+    }
+}
+
+// One variable with D edge slots (byte offsets sb + 256 q): M = Lambda~ +
+// sum_q mu_q (checks ascending), then nu_q = M - mu_q.  In a mixed group only
+// the member's own vd edges enter the sum (its remaining slots are unused by
+// any check).
+template <int D, bool MIXED, bool LDS>
+__device__ __forceinline__ float var_member(const State<LDS> X, uint32_t sb, int vd, float acc) {
+    float mu[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) mu[q] = X.ld(sb + 256u * q);
+#pragma unroll
+    for (int q = 0; q < D; ++q) acc = (!MIXED || q < vd) ? acc + mu[q] : acc;
+#pragma unroll
+    for (int q = 0; q < D; ++q) X.st(sb + 256u * q, acc - mu[q]);
+    return acc;
+}
+
+// rolled form for large degrees and traced iterations
+template <bool LDS>
+__device__ __forceinline__ float var_member_rolled(const State<LDS> X, uint32_t sb, int vd, float acc, float* trace_mu,
+                                                const int32_t* scsc) {
+    for (int q = 0; q < vd; ++q) acc = acc + X.ld(sb + 256u * q);
+    for (int q = 0; q < vd; ++q) {
+        const uint32_t o = sb + 256u * q;
+        const float mu = X.ld(o);
+        if (trace_mu) trace_mu[scsc[o >> 2]] = mu;
+        X.st(o, acc - mu);
+    }
+    return acc;
+}
+
+template <int D, bool LDS>
+__device__ __forceinline__ float var_member_d(const State<LDS> X, uint32_t sb, bool mixed, int vd, float acc) {
+    return mixed ? var_member<D, true>(X, sb, vd, acc) : var_member<D, false>(X, sb, vd, acc);
+}
+
+template <bool LDS>
+__device__ __forceinline__ float var_dispatch(const State<LDS> X, uint32_t sb, int dg, bool mixed, int vd, float acc) {
+    switch (dg) {
+        case 0: return acc;
+        case 1: return var_member_d<1>(X, sb, mixed, vd, acc);
+        case 2: return var_member_d<2>(X, sb, mixed, vd, acc);
+        case 3: return var_member_d<3>(X, sb, mixed, vd, acc);
+        case 4: return var_member_d<4>(X, sb, mixed, vd, acc);
+        case 5: return var_member_d<5>(X, sb, mixed, vd, acc);
+        case 6: return var_member_d<6>(X, sb, mixed, vd, acc);
+        case 7: return var_member_d<7>(X, sb, mixed, vd, acc);
+        case 8: return var_member_d<8>(X, sb, mixed, vd, acc);
+        default: return var_member_rolled(X, sb, vd, acc, nullptr, nullptr);
+    }
+}
+
+// A variable whose hard decision flips toggles the parity bits of its checks
+// (LDS atomics); the caller moves the solution weight by +-Lambda_j.
+__device__ __forceinline__ void flip_slots(const int32_t* scheck, uint32_t sb, int vd, uint32_t* par, int& dcount) {
+    for (int q = 0; q < vd; ++q) {
+        const int i = ldg(scheck, (sb >> 2) + 64u * q);
         const uint32_t bit = 1u << (i & 31);
         const uint32_t old = atomicXor(par + (i >> 5), bit);
         dcount += (old & bit) ? -1 : 1;
     }
-    dW += now_neg ? (double)lamj : -(double)lamj;
 }
 
-// Hides a register value from loop-invariant code motion: address arithmetic on
-// the cached index lists is then redone per sweep (one add) instead of being
-// hoisted out of the persistent loop as one 64-bit address per edge.
-__device__ __forceinline__ void opaque(int& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-template <int RD, int CD, int CPT, int VPT, bool LDS_STATE, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES, (WAVES >= 4 ? 4 : WAVES)) relay_bp_kernel(const DecodeLaunch a) {
-    constexpr bool CACHED = CPT > 0;
-    constexpr int CP = CACHED ? CPT : 1;
-    constexpr int VP = CACHED ? VPT : 1;
+template <int RD, bool LDS_STATE>
+__global__ void __launch_bounds__(1024, 4) relay_bp_kernel(const DecodeLaunch a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ unsigned long long sh_shot;
-    __shared__ int sh_count;
-    __shared__ double sh_W;
-    __shared__ int sh_red_i[16];
-
-    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wid = tid >> 6;
-    float* X;
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63;
+    const int wid = uniform(tid >> 6), nw = nth >> 6;
+    State<LDS_STATE> X;
+    float* Mg;
     if constexpr (LDS_STATE) {
-        X = reinterpret_cast<float*>(smem);
+        X.g = nullptr;
+        Mg = reinterpret_cast<float*>(smem + a.off_M);
     } else {
-        X = a.gstate + (int64_t)blockIdx.x * a.gstate_stride;
+        X.g = a.gstate + (int64_t)blockIdx.x * a.gstate_stride;
+        Mg = X.g + a.Smax + 4;
     }
-    float* Mg = X + a.Emax + 4;  // marginals of the uncached variant (after the two dummy cells)
     uint32_t* sig = reinterpret_cast<uint32_t*>(smem + a.off_sig);
+    uint32_t* sigp = reinterpret_cast<uint32_t*>(smem + a.off_sigp);
     uint32_t* par = reinterpret_cast<uint32_t*>(smem + a.off_par);
+    uint32_t* bestp = reinterpret_cast<uint32_t*>(smem + a.off_bestp);
     uint32_t* best = reinterpret_cast<uint32_t*>(smem + a.off_best);
     uint32_t* obw = reinterpret_cast<uint32_t*>(smem + a.off_obs);
+    SlotMisc* ms = reinterpret_cast<SlotMisc*>(smem + a.off_misc);
 
-    // Register caches of the persistent thread: its checks tid + c*nth and its
-    // variables tid + v*nth never change, so their index lists are loaded once.
-    int cpos[CP][RD];
-    int cdeg[CP];
-    int vstart[VP], vdeg[VP];
-    float vlam[VP], Mreg[VP], greg[VP];
-    if constexpr (CACHED) {
-        const DecodeModel m0 = a.m[0];
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const int i = tid + c * nth;
-            cdeg[c] = 0;
-#pragma unroll
-            for (int p = 0; p < RD; ++p) cpos[c][p] = (i < m0.M && p < m0.P) ? m0.rpos[(int64_t)i * m0.P + p] : m0.E;
-        }
-#pragma unroll
-        for (int v = 0; v < VPT; ++v) {
-            const int j = tid + v * nth;
-            int s0 = 0, d = 0;
-            float l = 0.f;
-            if (j < m0.N) {
-                s0 = m0.col_ptr[j];
-                d = m0.col_ptr[j + 1] - s0;
-                l = m0.lam[j];
-            }
-            vstart[v] = s0;
-            vdeg[v] = d;
-            vlam[v] = l;
-            Mreg[v] = 0.f;
-            greg[v] = 0.f;
-        }
-    }
-
+    // Shots come from a device-wide ticket counter in runs of kShotRun (one
+    // atomic per run) while many shots remain, one at a time near the end.
+    unsigned long long run_next = 0, run_end = 0, last_ticket = 0;
     for (;;) {
         if (tid == 0) {
-            sh_shot = atomicAdd(a.queue, 1ull);
-            sh_count = 0;
-            sh_W = 0.0;
+            if (run_next == run_end) {
+                const unsigned long long k =
+                    last_ticket + 8ull * kShotRun * gridDim.x < a.shots ? (unsigned long long)kShotRun : 1ull;
+                run_next = atomicAdd(a.queue, k);
+                run_end = run_next + k;
+                last_ticket = run_next;
+            }
+            ms->shot = run_next++;
+            ms->count = 0;
+            ms->W = 0.0;
         }
         __syncthreads();
         // the shot, its model and its row are uniform over the workgroup: keep them scalar
-        const unsigned long long s = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(sh_shot >> 32)) << 32) |
-                                     __builtin_amdgcn_readfirstlane((uint32_t)sh_shot);
+        const unsigned long long s = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(ms->shot >> 32))
+                                      << 32) |
+                                     __builtin_amdgcn_readfirstlane((uint32_t)ms->shot);
         if (s >= a.shots) break;
         const uint64_t t_start = wall_clock64();
-        const int mi = (CACHED || !a.shot_code) ? 0 : __builtin_amdgcn_readfirstlane((int)a.shot_code[s]);
+        const int mi = a.shot_code ? uniform((int)a.shot_code[s]) : 0;
         const DecodeModel m = a.m[mi];
-        const uint64_t row = a.shot_index ? (uint64_t)__builtin_amdgcn_readfirstlane(a.shot_index[s]) : (uint64_t)s;
-        const int M = m.M, N = m.N, WM = m.WM, WN = m.WN;
-        const float* lam = m.lam;
+        const uint64_t row = a.shot_index ? (uint64_t)uniform((int)a.shot_index[s]) : (uint64_t)s;
+        const int N = m.N, WM = m.WM, WN = m.WN;
         const float* dlt = a.delta ? a.delta + row * (uint64_t)N : nullptr;
-
-        if (tid == 0) X[m.E] = INFINITY;  // read-only cell of the padded row slots
+        if (tid == 0) X.st(4u * (uint32_t)m.S, INFINITY);  // read-only padding cell
         int pc = 0;
         for (int w = tid; w < WM; w += nth) {
             const uint32_t v = m.syn[row * WM + w];
@@ -391,7 +518,7 @@ __global__ void __launch_bounds__(64 * WAVES, (WAVES >= 4 ? 4 : WAVES)) relay_bp
             par[w] = v;
             pc += __popc(v);
         }
-        const int base = block_sum<int>(pc, sh_red_i);
+        const int base = block_sum<int>(pc, ms->red);
 
         int nconv = 0, legs = 0, iters = 0, path = 0;
         bool have_best = false;
@@ -404,6 +531,16 @@ __global__ void __launch_bounds__(64 * WAVES, (WAVES >= 4 ? 4 : WAVES)) relay_bp
             for (int w = tid; w < WN; w += nth) best[w] = 0u;
             __syncthreads();
         } else {
+            // syndrome bits in row-position order, one ballot per row group
+            for (int g = wid; g < m.GR; g += nw) {
+                const int i = m.rord[g * 64 + lane];
+                const bool b = i >= 0 && ((sig[i >> 5] >> (i & 31)) & 1u);
+                const unsigned long long bb = __ballot(b);
+                if (lane == 0) {
+                    sigp[2 * g] = (uint32_t)bb;
+                    sigp[2 * g + 1] = (uint32_t)(bb >> 32);
+                }
+            }
             const int first_phase = dlt ? 1 : 0;
             for (int phase = first_phase; phase >= 0; --phase) {
                 const bool prop = phase == 1;
@@ -411,8 +548,8 @@ __global__ void __launch_bounds__(64 * WAVES, (WAVES >= 4 ? 4 : WAVES)) relay_bp
                     // plain Relay-BP from scratch after a failed proposal
                     __syncthreads();
                     if (tid == 0) {
-                        sh_count = 0;
-                        sh_W = 0.0;
+                        ms->count = 0;
+                        ms->W = 0.0;
                     }
                     for (int w = tid; w < WM; w += nth) par[w] = sig[w];
                     __syncthreads();
@@ -421,31 +558,24 @@ __global__ void __launch_bounds__(64 * WAVES, (WAVES >= 4 ? 4 : WAVES)) relay_bp
                 {
                     int dc = 0;
                     double dW = 0.0;
-                    if constexpr (CACHED) {
-#pragma unroll
-                        for (int v = 0; v < VPT; ++v) {
-                            const int j = tid + v * nth;
-                            if (j < N) {
-                                const float x = prop ? vlam[v] + dlt[j] : vlam[v];
-                                Mreg[v] = x;
-                                if (prop)
-                                    for (int e = vstart[v]; e < vstart[v] + vdeg[v]; ++e) X[e] = x;
-                                if (x < 0.0f) flip_variable(m.csc_row, vstart[v], vdeg[v], true, vlam[v], par, dc, dW);
+                    for (int pp = tid; pp < m.Np; pp += nth) {
+                        const float l = ldg(m.lamp, pp);
+                        float x = l;
+                        if (prop) {
+                            const int j = ldg(m.vord, pp);
+                            x = j >= 0 ? l + dlt[j] : 0.0f;
+                            const int vd = ldg(m.vdeg, pp);
+                            const uint32_t sb = 4u * ((uint32_t)ldg(m.vgrp, pp >> 6).x + (uint32_t)(pp & 63));
+                            for (int q = 0; q < vd; ++q) X.st(sb + 256u * q, x);
+                            if (x < 0.0f) {
+                                flip_slots(m.scheck, sb, vd, par, dc);
+                                dW += (double)l;
                             }
                         }
-                    } else {
-                        for (int j = tid; j < N; j += nth) {
-                            const float x = prop ? lam[j] + dlt[j] : lam[j];
-                            Mg[j] = x;
-                            if (prop) {
-                                const int s0 = m.col_ptr[j], d = m.col_ptr[j + 1] - s0;
-                                for (int e = s0; e < s0 + d; ++e) X[e] = x;
-                                if (x < 0.0f) flip_variable(m.csc_row, s0, d, true, lam[j], par, dc, dW);
-                            }
-                        }
+                        Mg[pp] = x;
                     }
-                    if (dc) atomicAdd(&sh_count, dc);
-                    if (dW != 0.0) atomicAdd(&sh_W, dW);
+                    if (dc) atomicAdd(&ms->count, dc);
+                    if (dW != 0.0) atomicAdd(&ms->W, dW);
                     __syncthreads();
                 }
 
@@ -454,152 +584,55 @@ __global__ void __launch_bounds__(64 * WAVES, (WAVES >= 4 ? 4 : WAVES)) relay_bp
                     const bool leg0 = leg == 0;
                     const bool lp = prop && leg0;  // priors of this leg are Lambda + delta
                     const int T = leg0 ? a.T0 : a.Tr;
-                    const float* gam = leg0 ? nullptr : m.gtab + (int64_t)(leg - 1) * N;
+                    const float* gt = m.gtabp + (int64_t)(leg0 ? 0 : leg - 1) * m.Np;
                     bool conv = false;
                     ++legs;
-                    if constexpr (CACHED) {
-#pragma unroll
-                        for (int v = 0; v < VPT; ++v) {
-                            const int j = tid + v * nth;
-                            greg[v] = (leg0 || j >= N) ? a.gamma0 : gam[j];
-                        }
-                    }
                     for (int t = 1; t <= T; ++t) {
                         const bool first_plain = t == 1 && !lp;
-                        // ---- check sweep
-                        if constexpr (CACHED) {
-#pragma unroll
-                            for (int c = 0; c < CPT; ++c) {
-#pragma unroll
-                                for (int p = 0; p < RD; ++p) opaque(cpos[c][p]);
-                                const int i = tid + c * nth;
-                                if (i < M) {
-                                    float m1v[RD];
-#pragma unroll
-                                    for (int p = 0; p < RD; ++p)
-                                        m1v[p] = (first_plain && p < m.P) ? m.m1p[(int64_t)i * m.P + p] : 0.f;
-                                    check_row<RD>(X, cpos[c], m.E, ((sig[i >> 5] >> (i & 31)) & 1u) << 31, first_plain, m1v);
-                                }
-                                __builtin_amdgcn_sched_barrier(0);
-                            }
-                        } else {
-                            // rounds of CR rows per thread: the position lists of all
-                            // rounds are loaded before any row is processed
-                            constexpr int CR = RD <= 12 ? 2 : 1;
-                            static_assert(RD % 4 == 0, "row stride must be a multiple of 4");
-                            for (int i0 = tid; i0 < M; i0 += CR * nth) {
-                                int pos[CR][RD];
-                                float m1v[CR][RD];
-#pragma unroll
-                                for (int r = 0; r < CR; ++r) {
-                                    const int i = i0 + r * nth;
-                                    const uint32_t b = (uint32_t)(i < M ? i : 0) * (uint32_t)RD;
-                                    const int4* pp = reinterpret_cast<const int4*>(m.rpos + b);
-                                    const float4* mp = reinterpret_cast<const float4*>(m.m1p + b);
-#pragma unroll
-                                    for (int q = 0; q < RD / 4; ++q) {
-                                        const int4 v = pp[q];
-                                        pos[r][4 * q] = v.x;
-                                        pos[r][4 * q + 1] = v.y;
-                                        pos[r][4 * q + 2] = v.z;
-                                        pos[r][4 * q + 3] = v.w;
-                                        if (first_plain) {
-                                            const float4 f = mp[q];
-                                            m1v[r][4 * q] = f.x;
-                                            m1v[r][4 * q + 1] = f.y;
-                                            m1v[r][4 * q + 2] = f.z;
-                                            m1v[r][4 * q + 3] = f.w;
-                                        } else {
-                                            m1v[r][4 * q] = m1v[r][4 * q + 1] = m1v[r][4 * q + 2] = m1v[r][4 * q + 3] = 0.f;
-                                        }
-                                    }
-                                }
-#pragma unroll
-                                for (int r = 0; r < CR; ++r) {
-                                    const int i = i0 + r * nth;
-                                    if (i < M)
-                                        check_row<RD>(X, pos[r], m.E, ((sig[i >> 5] >> (i & 31)) & 1u) << 31, first_plain,
-                                                      m1v[r]);
-                                }
-                            }
+                        // ---- check sweep: one row group per wave at a time
+                        for (int g = wid; g < m.GR; g += nw) {
+                            const int4 gi = m.rgrp[g];
+                            const uint32_t off = (uint32_t)uniform(gi.x) + (uint32_t)lane;
+                            const uint32_t sbit = ((sigp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u) << 31;
+                            check_dispatch<RD>(X, m.rposp + off, m.rposw + off, m.m1pp + off, uniform(gi.y),
+                                               uniform(gi.z) != 0, sbit, first_plain);
                         }
                         __syncthreads();
-                        // ---- variable sweep
+                        // ---- variable sweep: one variable group per wave at a time
                         const bool tr = a.trace_on && phase == a.trace_phase && leg == a.trace_leg && t == a.trace_t;
                         int dcount = 0;
                         double dW = 0.0;
-                        if constexpr (CACHED) {
-#pragma unroll
-                            for (int v = 0; v < VPT; ++v) {
-                                opaque(vstart[v]);
-                                opaque(vdeg[v]);
-                                const int j = tid + v * nth;
-                                if (j < N) {
-                                    const float lt = lp ? vlam[v] + dlt[j] : vlam[v];
-                                    const float mo = Mreg[v];
-                                    float acc = __builtin_fmaf(greg[v], mo - lt, lt);
-                                    const int s0 = vstart[v], d = vdeg[v];
-                                    float mu[CD];
-#pragma unroll
-                                    for (int e = 0; e < CD; ++e)
-                                        if (e < d) mu[e] = X[s0 + e];
-#pragma unroll
-                                    for (int e = 0; e < CD; ++e)
-                                        if (e < d) acc = acc + mu[e];
-#pragma unroll
-                                    for (int e = 0; e < CD; ++e)
-                                        if (e < d) X[s0 + e] = acc - mu[e];
-                                    if (tr) {
-                                        a.trace_M[j] = acc;
-#pragma unroll
-                                        for (int e = 0; e < CD; ++e)
-                                            if (e < d) a.trace_mu[s0 + e] = mu[e];
-                                    }
-                                    Mreg[v] = acc;
-                                    if ((acc < 0.0f) != (mo < 0.0f))
-                                        flip_variable(m.csc_row, s0, d, acc < 0.0f, vlam[v], par, dcount, dW);
-                                }
-                                __builtin_amdgcn_sched_barrier(0);
+                        for (int g = wid; g < m.GV; g += nw) {
+                            const int4 gi = m.vgrp[g];
+                            const int dg = uniform(gi.y);
+                            const bool mixed = uniform(gi.z) != 0;
+                            const uint32_t pp = (uint32_t)(g * 64 + lane);
+                            const float l = ldg(m.lamp, pp), gv = ldg(gt, pp);
+                            float lt = l;
+                            if (lp) {
+                                const int j = ldg(m.vord, pp);
+                                if (j >= 0) lt = l + dlt[j];
                             }
-                        } else {
-                            // rounds of VR variables per thread, scalars of all rounds loaded first
-                            constexpr int VR = 4;
-                            for (int j0 = tid; j0 < N; j0 += VR * nth) {
-                                int s0[VR], dg[VR];
-                                float lt[VR], g[VR], mo[VR];
-#pragma unroll
-                                for (int r = 0; r < VR; ++r) {
-                                    const int j = j0 + r * nth;
-                                    const uint32_t jj = j < N ? (uint32_t)j : 0u;
-                                    s0[r] = m.col_ptr[jj];
-                                    dg[r] = j < N ? m.col_ptr[jj + 1u] - s0[r] : 0;
-                                    lt[r] = lp ? lam[jj] + dlt[jj] : lam[jj];
-                                    g[r] = leg0 ? a.gamma0 : gam[jj];
-                                    mo[r] = Mg[jj];
-                                }
-#pragma unroll
-                                for (int r = 0; r < VR; ++r) {
-                                    const int j = j0 + r * nth;
-                                    if (j < N) {
-                                        float acc = __builtin_fmaf(g[r], mo[r] - lt[r], lt[r]);
-                                        const uint32_t b = (uint32_t)s0[r];
-                                        const int d = dg[r];
-                                        for (uint32_t e = b; e < b + d; ++e) acc = acc + X[e];
-                                        for (uint32_t e = b; e < b + d; ++e) {
-                                            const float mu = X[e];
-                                            if (tr) a.trace_mu[e] = mu;
-                                            X[e] = acc - mu;
-                                        }
-                                        if (tr) a.trace_M[j] = acc;
-                                        Mg[j] = acc;
-                                        if ((acc < 0.0f) != (mo[r] < 0.0f))
-                                            flip_variable(m.csc_row, b, d, acc < 0.0f, lam[j], par, dcount, dW);
-                                    }
-                                }
+                            const float gm = leg0 ? a.gamma0 : gv;
+                            const float mo = Mg[pp];
+                            float acc = __builtin_fmaf(gm, mo - lt, lt);
+                            const uint32_t sb = 4u * ((uint32_t)uniform(gi.x) + (uint32_t)lane);
+                            const int vd = mixed ? ldg(m.vdeg, pp) : dg;
+                            if (!tr) {
+                                acc = var_dispatch(X, sb, dg, mixed, vd, acc);
+                            } else {
+                                acc = var_member_rolled(X, sb, vd, acc, a.trace_mu, m.scsc);
+                                const int j = ldg(m.vord, pp);
+                                if (j >= 0) a.trace_M[j] = acc;
+                            }
+                            Mg[pp] = acc;
+                            if ((acc < 0.0f) != (mo < 0.0f)) {
+                                flip_slots(m.scheck, sb, vd, par, dcount);
+                                dW += acc < 0.0f ? (double)l : -(double)l;
                             }
                         }
-                        if (dcount) atomicAdd(&sh_count, dcount);
-                        if (dW != 0.0) atomicAdd(&sh_W, dW);
+                        if (dcount) atomicAdd(&ms->count, dcount);
+                        if (dW != 0.0) atomicAdd(&ms->W, dW);
                         __syncthreads();
                         ++iters;
                         if (tr) {
@@ -607,38 +640,23 @@ __global__ void __launch_bounds__(64 * WAVES, (WAVES >= 4 ? 4 : WAVES)) relay_bp
                             traced = true;
                             break;
                         }
-                        if (base + sh_count == 0) {
+                        if (base + ms->count == 0) {
                             conv = true;
                             break;
                         }
                     }
                     if (traced) break;
                     if (conv) {
-                        const double W = sh_W;
+                        const double W = ms->W;
                         if (!have_best || W < bestW) {
                             bestW = W;
                             have_best = true;
-                            // best := current hard decision (one ballot per 64 variables)
-                            if constexpr (CACHED) {
-#pragma unroll
-                                for (int v = 0; v < VPT; ++v) {
-                                    const int jb = wid * 64 + v * nth;
-                                    if (jb < N) {
-                                        const unsigned long long b = __ballot(jb + lane < N && Mreg[v] < 0.0f);
-                                        if (lane == 0) {
-                                            best[jb >> 5] = (uint32_t)b;
-                                            if ((jb >> 5) + 1 < WN) best[(jb >> 5) + 1] = (uint32_t)(b >> 32);
-                                        }
-                                    }
-                                }
-                            } else {
-                                for (int jb = wid * 64; jb < N; jb += nth) {
-                                    const int j = jb + lane;
-                                    const unsigned long long b = __ballot(j < N && Mg[j] < 0.0f);
-                                    if (lane == 0) {
-                                        best[jb >> 5] = (uint32_t)b;
-                                        if ((jb >> 5) + 1 < WN) best[(jb >> 5) + 1] = (uint32_t)(b >> 32);
-                                    }
+                            // best := current hard decision, by position (one ballot per group)
+                            for (int g = wid; g < m.GV; g += nw) {
+                                const unsigned long long b = __ballot(Mg[g * 64 + lane] < 0.0f);
+                                if (lane == 0) {
+                                    bestp[2 * g] = (uint32_t)b;
+                                    bestp[2 * g + 1] = (uint32_t)(b >> 32);
                                 }
                             }
                         }
@@ -657,27 +675,27 @@ __global__ void __launch_bounds__(64 * WAVES, (WAVES >= 4 ? 4 : WAVES)) relay_bp
             }
             if (!have_best) {
                 // no solution: report the last hard decision
-                if constexpr (CACHED) {
-#pragma unroll
-                    for (int v = 0; v < VPT; ++v) {
-                        const int jb = wid * 64 + v * nth;
-                        if (jb < N) {
-                            const unsigned long long b = __ballot(jb + lane < N && Mreg[v] < 0.0f);
-                            if (lane == 0) {
-                                best[jb >> 5] = (uint32_t)b;
-                                if ((jb >> 5) + 1 < WN) best[(jb >> 5) + 1] = (uint32_t)(b >> 32);
-                            }
-                        }
+                for (int g = wid; g < m.GV; g += nw) {
+                    const unsigned long long b = __ballot(Mg[g * 64 + lane] < 0.0f);
+                    if (lane == 0) {
+                        bestp[2 * g] = (uint32_t)b;
+                        bestp[2 * g + 1] = (uint32_t)(b >> 32);
                     }
-                } else {
-                    for (int jb = wid * 64; jb < N; jb += nth) {
-                        const int j = jb + lane;
-                        const unsigned long long b = __ballot(j < N && Mg[j] < 0.0f);
-                        if (lane == 0) {
-                            best[jb >> 5] = (uint32_t)b;
-                            if ((jb >> 5) + 1 < WN) best[(jb >> 5) + 1] = (uint32_t)(b >> 32);
-                        }
-                    }
+                }
+            }
+            __syncthreads();
+            // positions -> variable order
+            for (int jb = wid * 64; jb < N; jb += nth) {
+                const int j = jb + lane;
+                bool bit = false;
+                if (j < N) {
+                    const int pp = m.pinv[j];
+                    bit = (bestp[pp >> 5] >> (pp & 31)) & 1u;
+                }
+                const unsigned long long b = __ballot(bit);
+                if (lane == 0) {
+                    best[jb >> 5] = (uint32_t)b;
+                    if ((jb >> 5) + 1 < WN) best[(jb >> 5) + 1] = (uint32_t)(b >> 32);
                 }
             }
             __syncthreads();
@@ -742,21 +760,25 @@ static rbp_status check_priors(const double* priors, int N) {
     return RBP_OK;
 }
 
-// LLRs Lambda_j = (float) ln((1-p)/p) in double, uploaded when the priors change.
+// LLRs Lambda_j = (float) ln((1-p)/p) in double, uploaded (by variable and by
+// position) when the priors change, and the first-iteration message table.
 static rbp_status ensure_llr(rbp_code* c, const double* priors, hipStream_t stream) {
     if (c->lam.p && c->lam_key.size() == (size_t)c->N &&
         std::memcmp(c->lam_key.data(), priors, sizeof(double) * c->N) == 0)
         return RBP_OK;
-    std::vector<float> lam(c->N);
+    std::vector<float> lam(c->N), lamp(c->Np, 0.0f);
     for (int j = 0; j < c->N; ++j) lam[j] = (float)std::log((1.0 - priors[j]) / priors[j]);
-    rbp_status st = c->lam.reserve(sizeof(float) * std::max(c->N, 1));
-    if (st) return st;
-    st = c->m1.reserve(sizeof(float) * std::max<int64_t>((int64_t)c->M * c->P, 1));
-    if (st) return st;
+    for (int p = 0; p < c->Np; ++p)
+        if (c->h_vord[p] >= 0) lamp[p] = lam[c->h_vord[p]];
     RBP_HIP_CHECK(hipStreamSynchronize(stream));
-    RBP_HIP_CHECK(hipMemcpy(c->lam.p, lam.data(), sizeof(float) * c->N, hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(first_message_kernel, dim3(ceil_div(c->M, 256)), dim3(256), 0, stream, c->row_ptr.as<int32_t>(),
-                       c->col_idx.as<int32_t>(), c->lam.as<float>(), c->m1.as<float>(), c->M, c->P);
+    rbp_status st = upload(c->lam, lam);
+    if (!st) st = upload(c->lamp, lamp);
+    if (!st) st = c->m1.reserve(sizeof(float) * std::max<int64_t>(c->RB, 1));
+    if (st) return st;
+    const int npos = 64 * c->GR;
+    hipLaunchKernelGGL(first_message_kernel, dim3(ceil_div(npos, 256)), dim3(256), 0, stream, c->row_ptr.as<int32_t>(),
+                       c->col_idx.as<int32_t>(), c->rord.as<int32_t>(), c->rgrp.as<int4>(), c->lam.as<float>(),
+                       c->m1.as<float>(), npos);
     RBP_HIP_CHECK(hipGetLastError());
     c->lam_key.assign(priors, priors + c->N);
     return RBP_OK;
@@ -784,13 +806,14 @@ static rbp_status ensure_gamma(rbp_code* c, const rbp_relay_params* p, hipStream
     if (c->gtab.p && c->gtab_R == R && c->gtab_seed == p->gamma_seed && c->gtab_lo == p->gamma_min &&
         c->gtab_hi == p->gamma_max)
         return RBP_OK;
-    const int64_t total = (int64_t)c->N * std::max(R, 0);
+    const int64_t total = (int64_t)c->Np * std::max(R, 0);
     RBP_HIP_CHECK(hipStreamSynchronize(stream));
-    rbp_status st = c->gtab.reserve(sizeof(float) * std::max<int64_t>(total, 1));
+    // at least one row: the first leg reads (and discards) row 0
+    rbp_status st = c->gtab.reserve(sizeof(float) * std::max<int64_t>(total, c->Np));
     if (st) return st;
     if (total > 0) {
-        hipLaunchKernelGGL(gamma_table_kernel, dim3(ceil_div(total, 256)), dim3(256), 0, stream,
-                           c->gtab.as<float>(), c->N, R, p->gamma_min, p->gamma_max, p->gamma_seed);
+        hipLaunchKernelGGL(gamma_table_kernel, dim3(ceil_div(total, 256)), dim3(256), 0, stream, c->gtab.as<float>(),
+                           c->vord.as<int32_t>(), c->Np, R, p->gamma_min, p->gamma_max, p->gamma_seed);
         RBP_HIP_CHECK(hipGetLastError());
     }
     c->gtab_R = R;
@@ -820,15 +843,25 @@ static DecodeModel model_of(const rbp_code* c, const uint32_t* syn, uint32_t* co
     m.WM = ceil_div(c->M, 32);
     m.WN = ceil_div(c->N, 32);
     m.WK = ceil_div(c->k, 32);
-    m.P = c->P;
-    m.rpos = c->rpos.as<int32_t>();
-    m.col_ptr = c->col_ptr.as<int32_t>();
-    m.csc_row = c->csc_row.as<int32_t>();
-    m.m1p = c->m1.as<float>();
+    m.S = c->S;
+    m.GR = c->GR;
+    m.GV = c->GV;
+    m.Np = c->Np;
+    m.rgrp = c->rgrp.as<int4>();
+    m.rposp = c->rposp.as<int32_t>();
+    m.rposw = c->rposw.as<int32_t>();
+    m.m1pp = c->m1.as<float>();
+    m.rord = c->rord.as<int32_t>();
+    m.vgrp = c->vgrp.as<int4>();
+    m.vord = c->vord.as<int32_t>();
+    m.vdeg = c->vdeg.as<int32_t>();
+    m.pinv = c->pinv.as<int32_t>();
+    m.scheck = c->scheck.as<int32_t>();
+    m.scsc = c->scsc.as<int32_t>();
+    m.lamp = c->lamp.as<float>();
+    m.gtabp = c->gtab.as<float>();
     m.ocol_ptr = c->ocol_ptr.as<int32_t>();
     m.orow_idx = c->orow_idx.as<int32_t>();
-    m.lam = c->lam.as<float>();
-    m.gtab = c->gtab.as<float>();
     m.syn = syn;
     m.corr = corr;
     m.obsp = c->k > 0 ? obsp : nullptr;
@@ -837,23 +870,9 @@ static DecodeModel model_of(const rbp_code* c, const uint32_t* syn, uint32_t* co
 
 typedef void (*DecodeKernel)(const DecodeLaunch);
 
-// Variants whose per-thread index lists live in registers: a thread owns at
-// most CPT checks and VPT variables (rows <= 12, columns <= 8 edges).
-struct CachedVariant {
-    int waves, cpt, vpt;
-    DecodeKernel k;
-};
-#define RBP_CACHED(W, C, V) {W, C, V, relay_bp_kernel<12, 8, C, V, true, W>}
-// Register-cached variants are compiled on demand; none is enabled by default
-// (their control state does not fit the register budget without spilling).
-static const CachedVariant kCached[] = {
-    {0, 0, 0, nullptr},
-};
-#undef RBP_CACHED
-
-static DecodeKernel generic_kernel(int maxdeg, bool lds) {
-    if (maxdeg <= 12) return lds ? relay_bp_kernel<12, 8, 0, 0, true, 16> : relay_bp_kernel<12, 8, 0, 0, false, 16>;
-    return lds ? relay_bp_kernel<32, 8, 0, 0, true, 16> : relay_bp_kernel<32, 8, 0, 0, false, 16>;
+static DecodeKernel decode_kernel(int max_stored_row_deg, bool lds) {
+    if (max_stored_row_deg <= 12) return lds ? relay_bp_kernel<12, true> : relay_bp_kernel<12, false>;
+    return lds ? relay_bp_kernel<32, true> : relay_bp_kernel<32, false>;
 }
 
 static constexpr int kMaxLds = 160 * 1024;
@@ -861,97 +880,72 @@ static constexpr int kMaxLds = 160 * 1024;
 struct LaunchShape {
     int waves = 1;
     bool lds_state = true;
-    bool cached = false;
-    int cpt = 0, vpt = 0;
     DecodeKernel kernel = nullptr;
     int lds_bytes = 0;
     int slots = 1;
     int64_t gstride = 0;
-    int Emax = 0;
-    int off_sig = 0, off_par = 0, off_best = 0, off_obs = 0;
+    int Smax = 0;
+    int off_M = 0, off_sig = 0, off_sigp = 0, off_par = 0, off_bestp = 0, off_best = 0, off_obs = 0, off_misc = 0;
 };
 
-static const CachedVariant* find_cached(int M, int N, int waves) {
-    const int nth = 64 * waves;
-    const int cpt = ceil_div(M, nth), vpt = ceil_div(N, nth);
-    const CachedVariant* bestv = nullptr;
-    for (const CachedVariant& v : kCached)
-        if (v.k && v.waves == waves && cpt <= v.cpt && vpt <= v.vpt &&
-            (!bestv || v.cpt * 12 + v.vpt * 5 < bestv->cpt * 12 + bestv->vpt * 5))
-            bestv = &v;
-    return bestv;
-}
+static int align16(int64_t x) { return (int)((x + 15) & ~(int64_t)15); }
 
 // Launch shape for a set of models decoded together (max sizes over models).
 static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, LaunchShape* out) {
-    int Nmax = 0, Emax = 0, WMmax = 0, WNmax = 0, WKmax = 1, maxdeg = 0, maxcol = 0, Mmax = 0;
+    int Smax = 0, Npmax = 0, GRmax = 0, WMmax = 0, WNmax = 0, WKmax = 1, rdmax = 0;
     for (int i = 0; i < n; ++i) {
-        Mmax = std::max(Mmax, cs[i]->M);
-        Nmax = std::max(Nmax, cs[i]->N);
-        Emax = std::max(Emax, cs[i]->E);
+        Smax = std::max(Smax, cs[i]->S);
+        Npmax = std::max(Npmax, cs[i]->Np);
+        GRmax = std::max(GRmax, cs[i]->GR);
         WMmax = std::max(WMmax, ceil_div(cs[i]->M, 32));
         WNmax = std::max(WNmax, ceil_div(cs[i]->N, 32));
         WKmax = std::max(WKmax, ceil_div(cs[i]->k, 32));
-        maxdeg = std::max(maxdeg, cs[i]->max_row_deg);
-        maxcol = std::max(maxcol, cs[i]->max_col_deg);
+        rdmax = std::max(rdmax, cs[i]->max_stored_row_deg);
     }
-    for (int i = 1; i < n; ++i)
-        if (cs[i]->P != cs[0]->P)
-            return fail(RBP_ERR_UNSUPPORTED, "models decoded together must all have rows of <= 12 or all > 12 edges");
     const LaunchCfg& cfg = cs[0]->cfg;
-    const int small = 4 * (2 * WMmax + WNmax + WKmax) + 512;  // + static shared variables
-    const bool cached_possible = n == 1 && maxdeg <= 12 && maxcol <= 8 && cfg.state != 2 &&
-                                 4 * (Emax + 4) + small <= kMaxLds;
-    LaunchShape L;
     int waves = cfg.waves_per_shot;
-    const CachedVariant* cv = nullptr;
     if (waves <= 0) {
-        if (cached_possible)
-            for (int w : {1, 2, 3, 4, 6, 8, 12, 16})
-                if ((cv = find_cached(Mmax, Nmax, w))) {
-                    waves = w;
-                    break;
-                }
-        if (waves <= 0) {
-            const int want = ceil_div(Nmax, 512);
-            waves = 1;
-            while (waves < want && waves < 8) waves <<= 1;
-        }
-    } else if (cached_possible) {
-        cv = find_cached(Mmax, Nmax, waves);
+        const int want = ceil_div(Npmax, 512);
+        waves = 1;
+        while (waves < want && waves < 8) waves <<= 1;
     }
     waves = std::min(std::max(waves, 1), 16);
-    int state_bytes;
-    bool lds;
-    if (cv) {
-        L.cached = true;
-        L.cpt = cv->cpt;
-        L.vpt = cv->vpt;
-        L.kernel = cv->k;
-        lds = true;
-        state_bytes = 4 * (Emax + 4);
-    } else {
-        state_bytes = 4 * (Emax + 4 + Nmax);
-        lds = state_bytes + small <= kMaxLds;
-        if (cfg.state == 1 && !lds) return fail(RBP_ERR_UNSUPPORTED, "per-shot state does not fit in LDS");
-        if (cfg.state == 2) lds = false;
-        L.kernel = generic_kernel(maxdeg, lds);
-    }
+    // small per-slot arrays (always LDS)
+    const int small = align16(4 * (int64_t)WMmax) + align16(8 * (int64_t)GRmax) + align16(4 * (int64_t)WMmax) +
+                      align16(4 * (int64_t)(Npmax / 32)) + align16(4 * (int64_t)WNmax) + align16(4 * (int64_t)WKmax) +
+                      align16(sizeof(SlotMisc));
+    const int64_t state_bytes = align16(4 * ((int64_t)Smax + 2)) + align16(4 * (int64_t)Npmax);
+    bool lds = state_bytes + small <= kMaxLds;
+    if (cfg.state == 1 && !lds) return fail(RBP_ERR_UNSUPPORTED, "per-shot state does not fit in LDS");
+    if (cfg.state == 2) lds = false;
+    LaunchShape L;
+    L.kernel = decode_kernel(rdmax, lds);
     L.waves = waves;
     L.lds_state = lds;
-    L.Emax = Emax;
-    int off = lds ? state_bytes : 0;
-    off = (off + 15) & ~15;
-    L.off_sig = off;
-    off += 4 * WMmax;
-    L.off_par = off;
-    off += 4 * WMmax;
-    L.off_best = off;
-    off += 4 * WNmax;
-    L.off_obs = off;
-    off += 4 * WKmax;
-    L.lds_bytes = (off + 15) & ~15;
-    L.gstride = lds ? 0 : ((int64_t)Nmax + Emax + 4 + 63) / 64 * 64;
+    L.Smax = Smax;
+    int64_t off = 0;
+    if (lds) {
+        off = align16(4 * ((int64_t)Smax + 2));
+        L.off_M = (int)off;
+        off += align16(4 * (int64_t)Npmax);
+    }
+    L.off_sig = (int)off;
+    off += align16(4 * (int64_t)WMmax);
+    L.off_sigp = (int)off;
+    off += align16(8 * (int64_t)GRmax);
+    L.off_par = (int)off;
+    off += align16(4 * (int64_t)WMmax);
+    L.off_bestp = (int)off;
+    off += align16(4 * (int64_t)(Npmax / 32));
+    L.off_best = (int)off;
+    off += align16(4 * (int64_t)WNmax);
+    L.off_obs = (int)off;
+    off += align16(4 * (int64_t)WKmax);
+    L.off_misc = (int)off;
+    off += align16(sizeof(SlotMisc));
+    if (off > kMaxLds) return fail(RBP_ERR_UNSUPPORTED, "per-shot bit arrays do not fit in LDS");
+    L.lds_bytes = (int)off;
+    L.gstride = lds ? 0 : ((int64_t)Smax + 4 + Npmax + 63) / 64 * 64;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(L.kernel),
                                                                 64 * waves, L.lds_bytes);
@@ -979,11 +973,15 @@ static rbp_status launch_decode(rbp_code* const* cs, int n, DecodeLaunch& a, uin
     a.queue = c0->queue.as<unsigned long long>();
     a.gstate = L.lds_state ? nullptr : c0->gstate.as<float>();
     a.gstate_stride = L.gstride;
-    a.Emax = L.Emax;
+    a.Smax = L.Smax;
+    a.off_M = L.off_M;
     a.off_sig = L.off_sig;
+    a.off_sigp = L.off_sigp;
     a.off_par = L.off_par;
+    a.off_bestp = L.off_bestp;
     a.off_best = L.off_best;
     a.off_obs = L.off_obs;
+    a.off_misc = L.off_misc;
     a.shots = shots;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, stream, a.queue, 1);
     RBP_HIP_CHECK(hipGetLastError());
@@ -1054,16 +1052,87 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
         }
         nnzO = obs_col_ptr[N];
     }
-    // CSR of H (columns ascending within a row) and the CSC -> CSR edge map
-    const int P = maxrow <= 12 ? 12 : 32;  // row stride of the padded position table
-    std::vector<int32_t> rp(M + 1, 0), ci(std::max(E, 1)), rpos((size_t)M * P, E), fillc(M, 0);
+    // CSR of H (columns ascending within a row)
+    std::vector<int32_t> rp(M + 1, 0), ci(std::max(E, 1)), fillc(M, 0);
     for (int i = 0; i < M; ++i) rp[i + 1] = rp[i] + deg[i];
     for (int j = 0; j < N; ++j)
         for (int e = col_ptr[j]; e < col_ptr[j + 1]; ++e) {
             const int i = row_idx[e];
-            const int pos = rp[i] + fillc[i]++;
-            ci[pos] = j;
-            rpos[(size_t)i * P + (pos - rp[i])] = e;
+            ci[rp[i] + fillc[i]++] = j;
+        }
+    // Variable groups: positions sorted by degree (descending, stable), 64 per
+    // group; the q-th edge of the variable at position 64 g + l sits in slot
+    // vbase_g + 64 q + l.
+    const int GV = ceil_div(N, 64), Np = 64 * GV;
+    std::vector<int32_t> cdeg(N), vperm(N);
+    for (int j = 0; j < N; ++j) {
+        cdeg[j] = col_ptr[j + 1] - col_ptr[j];
+        vperm[j] = j;
+    }
+    std::stable_sort(vperm.begin(), vperm.end(), [&](int x, int y) { return cdeg[x] > cdeg[y]; });
+    std::vector<int32_t> vord(Np, -1), vdeg(Np, 0), pinv(N), vgrp(4 * (size_t)GV, 0);
+    for (int p = 0; p < N; ++p) {
+        vord[p] = vperm[p];
+        vdeg[p] = cdeg[vperm[p]];
+        pinv[vperm[p]] = p;
+    }
+    int64_t S = 0;
+    for (int g = 0; g < GV; ++g) {
+        const int dg = vdeg[64 * g];
+        bool mixed = false;
+        for (int l = 0; l < 64; ++l) mixed |= vord[64 * g + l] < 0 || vdeg[64 * g + l] != dg;
+        vgrp[4 * g] = (int32_t)S;
+        vgrp[4 * g + 1] = dg;
+        vgrp[4 * g + 2] = mixed ? 1 : 0;
+        S += 64 * (int64_t)dg;
+    }
+    if (S + 2 > (int64_t)(INT32_MAX / 4)) return fail(RBP_ERR_UNSUPPORTED, "too many edges");
+    std::vector<int32_t> slot_of(std::max(E, 1)), scheck(std::max<int64_t>(S, 1), -1), scsc(std::max<int64_t>(S, 1), -1);
+    for (int p = 0; p < N; ++p) {
+        const int j = vord[p], g = p >> 6, l = p & 63;
+        for (int q = 0; q < cdeg[j]; ++q) {
+            const int e = col_ptr[j] + q;
+            const int slot = vgrp[4 * g] + 64 * q + l;
+            slot_of[e] = slot;
+            scheck[slot] = row_idx[e];
+            scsc[slot] = e;
+        }
+    }
+    // Row groups: checks sorted the same way; rows of up to 12 edges are stored
+    // at their group's degree, larger ones padded to 16, 24 or 32 slots.
+    const int GR = ceil_div(M, 64);
+    std::vector<int32_t> rperm(M), rord(64 * (size_t)GR, -1), rinv(M), rgrp(4 * (size_t)GR, 0);
+    for (int i = 0; i < M; ++i) rperm[i] = i;
+    std::stable_sort(rperm.begin(), rperm.end(), [&](int x, int y) { return deg[x] > deg[y]; });
+    for (int p = 0; p < M; ++p) {
+        rord[p] = rperm[p];
+        rinv[rperm[p]] = p;
+    }
+    int64_t RB = 0;
+    int maxstored = 0;
+    for (int g = 0; g < GR; ++g) {
+        const int dmax = deg[rord[64 * g]];
+        const int dst = dmax <= 12 ? dmax : dmax <= 16 ? 16 : dmax <= 24 ? 24 : 32;
+        bool mixed = false;
+        for (int l = 0; l < 64; ++l) {
+            const int i = rord[64 * g + l];
+            mixed |= i < 0 || deg[i] != dst;
+        }
+        rgrp[4 * g] = (int32_t)RB;
+        rgrp[4 * g + 1] = dst;
+        rgrp[4 * g + 2] = mixed ? 1 : 0;
+        RB += 64 * (int64_t)dst;
+        maxstored = std::max(maxstored, dst);
+    }
+    if (RB > (int64_t)INT32_MAX) return fail(RBP_ERR_UNSUPPORTED, "too many edges");
+    std::vector<int32_t> rposp(std::max<int64_t>(RB, 1), (int32_t)(4 * S)),
+        rposw(std::max<int64_t>(RB, 1), (int32_t)(4 * (S + 1))), rfill(M, 0);
+    for (int j = 0; j < N; ++j)
+        for (int e = col_ptr[j]; e < col_ptr[j + 1]; ++e) {
+            const int i = row_idx[e], p = rfill[i]++, pos = rinv[i];
+            const size_t at = (size_t)rgrp[4 * (pos >> 6)] + 64 * p + (pos & 63);
+            rposp[at] = 4 * slot_of[e];
+            rposw[at] = 4 * slot_of[e];
         }
     // CSR of O
     std::vector<int32_t> orp(k + 1, 0), oci(std::max(nnzO, 1)), ofill(std::max(k, 1), 0);
@@ -1083,8 +1152,14 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
     c->k = k;
     c->nnzO = nnzO;
     c->max_row_deg = maxrow;
-    c->P = P;
     c->max_col_deg = maxcol;
+    c->S = (int32_t)S;
+    c->GR = GR;
+    c->GV = GV;
+    c->Np = Np;
+    c->RB = (int32_t)RB;
+    c->max_stored_row_deg = maxstored;
+    c->h_vord = vord;
     hipError_t he = hipGetDevice(&c->device);
     if (he == hipSuccess) he = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device);
     if (he != hipSuccess) {
@@ -1103,7 +1178,16 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
     if (!st) st = upload(c->col_idx, ci);
     if (!st) st = upload(c->col_ptr, cp);
     if (!st) st = upload(c->csc_row, cr);
-    if (!st) st = upload(c->rpos, rpos);
+    if (!st) st = upload(c->rgrp, rgrp);
+    if (!st) st = upload(c->rposp, rposp);
+    if (!st) st = upload(c->rposw, rposw);
+    if (!st) st = upload(c->rord, rord);
+    if (!st) st = upload(c->vgrp, vgrp);
+    if (!st) st = upload(c->vord, vord);
+    if (!st) st = upload(c->vdeg, vdeg);
+    if (!st) st = upload(c->pinv, pinv);
+    if (!st) st = upload(c->scheck, scheck);
+    if (!st) st = upload(c->scsc, scsc);
     if (!st) st = upload(c->orow_ptr, orp);
     if (!st) st = upload(c->ocol_idx, oci);
     if (!st) st = upload(c->ocol_ptr, ocp);
@@ -1119,8 +1203,10 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
 rbp_status rbp_code_destroy(rbp_code_t c) {
     if (!c) return RBP_OK;
     (void)hipDeviceSynchronize();
-    for (DevBuf* b : {&c->row_ptr, &c->col_idx, &c->col_ptr, &c->csc_row, &c->rpos, &c->orow_ptr, &c->ocol_idx,
-                      &c->ocol_ptr, &c->orow_idx, &c->thr, &c->lam, &c->m1, &c->gtab, &c->queue, &c->gstate, &c->trace_hit})
+    for (DevBuf* b : {&c->row_ptr, &c->col_idx, &c->col_ptr, &c->csc_row, &c->rgrp, &c->rposp, &c->rposw, &c->rord, &c->vgrp,
+                      &c->vord, &c->vdeg, &c->pinv, &c->scheck, &c->scsc, &c->orow_ptr, &c->ocol_idx, &c->ocol_ptr,
+                      &c->orow_idx, &c->thr, &c->lam, &c->lamp, &c->m1, &c->gtab, &c->queue, &c->gstate,
+                      &c->trace_hit})
         b->release();
     delete c;
     return RBP_OK;
@@ -1289,7 +1375,7 @@ rbp_status rbp_get_launch_config(rbp_code_t c, rbp_launch_config* cfg, int32_t* 
     if (st) return st;
     if (cfg) {
         cfg->waves_per_shot = L.waves;
-        cfg->state = (L.lds_state ? 1 : 2) + (L.cached ? 8 : 0);
+        cfg->state = L.lds_state ? 1 : 2;
         cfg->max_slots = c->cfg.max_slots;
     }
     if (slots) *slots = L.slots;

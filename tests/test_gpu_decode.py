@@ -368,3 +368,29 @@ def test_full_size_decode_sampled(rbp):
     assert same.mean() >= 0.999
     s = rbp.stats_to_numpy(st)
     assert (s["converged"] == 1).mean() > 0.999
+
+
+# ----------------------------------------------------------------- largest models, sampled check
+@pytest.mark.parametrize("name,shots,checked", [("phen840", 20000, 300), ("hgp56", 4000, 60)])
+def test_largest_models_sampled(rbp, name, shots, checked):
+    """Full-size launches on the largest models (per-slot state in device
+    memory); the oracle decodes a spread sample of the same shots."""
+    dem = dem_of(name)
+    code = rbp.Code.from_dem(dem)
+    params = rbp.RelayParams()
+    syn, obs, _ = code.sample(dem.priors, shots, seed=4242)
+    corr, obsp, st = code.decode(dem.priors, syn, params)
+    torch.cuda.synchronize()
+    assert code.launch_config()["state"] == 2
+    idx = np.linspace(0, shots - 1, checked).astype(int)
+    syn_np = u32(syn)[idx]
+    ref = oracle.decode(oracle.Graph(dem.H, dem.O), dem.priors, syn_np, oparams(params), nthreads=16)
+    same = (u32(corr)[idx] == ref["corrections"]).all(axis=1)
+    assert same.mean() >= 0.99, same.mean()
+    s = rbp.stats_to_numpy(st)
+    assert np.array_equal(s["iters"][idx][same], ref["iters"][same])
+    # converged corrections reproduce their syndromes (checked on the sample)
+    e = W.unpack_bits(u32(corr)[idx], dem.N)
+    conv = s["converged"][idx] == 1
+    resyn = (e.astype(np.int64) @ dem.H.T.astype(np.int64)) % 2
+    assert np.array_equal(resyn[conv], W.unpack_bits(syn_np, dem.M)[conv])
