@@ -96,6 +96,11 @@ struct rbp_code {
     rbp::DevBuf m1;                     // float[RB] first-iteration message magnitudes (layout of rposp)
     std::vector<double> lam_key;
     rbp::DevBuf gtab;                   // float[max(R,1)][Np] relay-leg memory strengths by position
+    rbp::DevBuf lg;                     // float2[R+1][Np] {Lambda, gamma} by leg and position
+    uint64_t lam_gen = 0, gtab_gen = 0; // bumped when lam / gtab are rewritten
+    uint64_t lg_lam_gen = ~0ull, lg_gtab_gen = ~0ull;
+    float lg_gamma0 = 0.f;
+    int32_t lg_R = -1;
     uint64_t gtab_seed = 0;
     float gtab_lo = 0.f, gtab_hi = 0.f;
     int32_t gtab_R = -1;

@@ -11,10 +11,10 @@
 //                      from a device queue until none are left, so a shot that
 //                      converges early frees its slot at once.  The slot's state
 //                      is one float per edge, in place (see below), in LDS when
-//                      it fits, else in a per-slot device buffer; the threads'
-//                      index lists and the marginals of their variables stay in
-//                      registers for the life of the kernel.  The syndrome of the
-//                      hard decision and the weight of the current solution are
+//                      it fits, else in a per-slot device buffer; variables and
+//                      checks are processed in degree-sorted groups of 64, one
+//                      group per wavefront step.  The syndrome of the hard
+//                      decision and the weight of the current solution are
 //                      tracked incrementally: a variable whose decision flips XORs
 //                      its checks' parity bits with LDS atomics and moves the
 //                      weight, so convergence and solution weights cost no extra
@@ -152,6 +152,17 @@ __global__ void gamma_table_kernel(float* out, const int32_t* vord, int32_t Np, 
     out[idx] = __builtin_fmaf(u, span, gmin);
 }
 
+// {Lambda, gamma} by leg and position, read by the variable sweep with one
+// 8-byte load: row 0 holds gamma0 (first leg), row r the gamma of relay leg r.
+__global__ void lam_gamma_kernel(float2* out, const float* lamp, const float* gtab, int32_t Np, int32_t R,
+                                 float gamma0) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)Np * (R + 1);
+    if (idx >= total) return;
+    const int32_t r = (int32_t)(idx / Np), pos = (int32_t)(idx % Np);
+    out[idx] = make_float2(lamp[pos], r == 0 ? gamma0 : gtab[(int64_t)(r - 1) * Np + pos]);
+}
+
 // one thread per shot; a wave-level ballot count, one atomic per wave
 __global__ void count_failures_kernel(const uint32_t* obsp, const uint32_t* obs, const rbp_shot_stats* st,
                                       uint64_t shots, int words, unsigned long long* count) {
@@ -186,17 +197,22 @@ __global__ void zero_u64_kernel(unsigned long long* p, int n) {
 //    instruction's offset, and Mg is kept by position.
 //  * Checks are sorted and grouped the same way.  Lane l of row group g owns
 //    the check at row position 64 g + l; the byte offsets of its edge slots
-//    sit at rposp[rbase_g + 64 p + l] (columns ascending), one unit-stride load
-//    per p for the whole wave.
+//    (columns ascending) sit contiguously at rposp[rbase_g + st_g l + p], read
+//    with 16-byte loads (st_g: the group's degree rounded up to 4).
 //  * Every member of a group has the group's degree, except in the few groups
 //    that straddle a degree boundary or are partial ("mixed").  Loops over a
 //    member's edges therefore have a wave-uniform trip count and are unrolled
 //    per degree; mixed row groups pad their rows with the offset of X[S], a
 //    read-only +inf cell (neutral for both minima and the sign product), and
 //    redirect those writes to X[S+1]; mixed variable groups mask their sums.
+//  * Lambda_j and the leg's gamma_j are read together, one 8-byte load per
+//    lane and group, from a {Lambda, gamma} table with one row per leg.
 // The first iteration of a plain leg reads no state: nu(0) = Lambda, so
 // mu(1) = (-1)^sigma_i * (least |Lambda| of the other variables of the row),
 // a per-model table (layout of rposp) computed once per priors.
+// Waves of a slot spend most of their time waiting on table loads, so the
+// launch aims at about 8 waves per SIMD: the kernel is also built for a
+// 64-VGPR budget, used when that fits more slots per CU.
 // ---------------------------------------------------------------------------
 constexpr int kMaxModels = 8;
 constexpr int kShotRun = 4;  // shots taken per queue atomic while many remain
@@ -205,8 +221,8 @@ struct DecodeModel {
     int32_t M, N, E, k, WM, WN, WK;
     int32_t S;             // edge slots; X[S] = +inf (read-only padding cell), X[S+1] write-only cell
     int32_t GR, GV, Np;    // row groups, variable groups, Np = 64 GV variable positions
-    const int4* rgrp;      // [GR] {offset in rposp, stored degree, mixed, 0}
-    const int32_t* rposp;  // byte offsets 4 x slot of the edges of each row, 4 S for padding
+    const int4* rgrp;      // [GR] {offset in rposp, stored degree, mixed, lane stride}
+    const int32_t* rposp;  // byte offsets 4 x slot of the edges of each row (lane-major per group), 4 S padding
     const int32_t* rposw;  // the same for writes, 4 (S + 1) for padding
     const float* m1pp;     // first-iteration magnitudes, layout of rposp
     const int32_t* rord;   // [64 GR] check at each row position, -1 for padding
@@ -218,6 +234,7 @@ struct DecodeModel {
     const int32_t* scsc;   // [S] CSC edge index of each slot (-1 unused)
     const float* lamp;     // [Np] Lambda by position (0 for padding)
     const float* gtabp;    // [max(R,1)][Np] relay-leg memory strengths by position
+    const float2* lg;      // [R+1][Np] {Lambda, gamma} by leg and position
     const int32_t* ocol_ptr;  // [N+1] observables, CSC
     const int32_t* orow_idx;
     const uint32_t* syn;
@@ -258,14 +275,15 @@ struct SlotMisc {
 };
 
 // mu(1) magnitudes of a plain leg in the layout of rposp:
-// m1pp[rbase_g + 64 p + l] = least |Lambda_j'| over the other variables j' of the row
+// m1pp[rbase_g + l st_g + p] = least |Lambda_j'| over the other variables j' of the row
 __global__ void first_message_kernel(const int32_t* row_ptr, const int32_t* col_idx, const int32_t* rord,
                                      const int4* rgrp, const float* lam, float* m1pp, int32_t npos) {
     const int pos = blockIdx.x * blockDim.x + threadIdx.x;
     if (pos >= npos) return;
     const int i = rord[pos];
     if (i < 0) return;
-    float* out = m1pp + rgrp[pos >> 6].x + (pos & 63);
+    const int4 gi = rgrp[pos >> 6];
+    float* out = m1pp + gi.x + (pos & 63) * gi.w;
     const int rs = row_ptr[i], re = row_ptr[i + 1];
     float min1 = INFINITY, min2 = INFINITY;
     for (int e = rs; e < re; ++e) {
@@ -275,7 +293,7 @@ __global__ void first_message_kernel(const int32_t* row_ptr, const int32_t* col_
     }
     for (int e = rs; e < re; ++e) {
         const float av = fabsf(lam[col_idx[e]]);
-        out[64 * (e - rs)] = (av == min1) ? min2 : min1;
+        out[e - rs] = (av == min1) ? min2 : min1;
     }
 }
 
@@ -331,21 +349,49 @@ __device__ __forceinline__ T ldg(const T* base, uint32_t i) {
 // One check row of the min-sum update with D edge slots, in place on X.  The
 // magnitudes compare as unsigned integers (|nu| bit patterns order like the
 // floats); the outgoing sign is sigma_i times the signs of the other nu.  On the
-// first iteration of a plain leg the messages come from the m1 table.  rp, wp
-// and mp point at the lane's first entry of the read-offset, write-offset and
-// m1 tables (stride 64); rows of a mixed group read padding from the +inf cell
-// and write it to the write-only cell.
+// first iteration of a plain leg the messages come from the m1 table.  The
+// row's entries of the read-offset, write-offset and m1 tables are contiguous
+// (lane-major, stride (D + 3) & ~3), so each is read with 16-byte loads; rows
+// of a mixed group read padding from the +inf cell and write it to the
+// write-only cell.
 template <int D, bool MIXED, bool LDS>
 __device__ __forceinline__ void check_row(const State<LDS> X, const int32_t* rp, const int32_t* wp, const float* mp,
                                           uint32_t sbit, bool first) {
-    uint32_t pos[D], wpos[D];
+    constexpr int Q = (D + 3) / 4;
+    uint32_t pos[4 * Q], wpos[4 * Q];
 #pragma unroll
-    for (int p = 0; p < D; ++p) pos[p] = (uint32_t)rp[64 * p];
+    for (int k = 0; k < Q; ++k) {
+        const int4 v = reinterpret_cast<const int4*>(rp)[k];
+        pos[4 * k] = (uint32_t)v.x;
+        pos[4 * k + 1] = (uint32_t)v.y;
+        pos[4 * k + 2] = (uint32_t)v.z;
+        pos[4 * k + 3] = (uint32_t)v.w;
+    }
 #pragma unroll
-    for (int p = 0; p < D; ++p) wpos[p] = MIXED ? (uint32_t)wp[64 * p] : pos[p];
+    for (int k = 0; k < Q; ++k) {
+        if (MIXED) {
+            const int4 v = reinterpret_cast<const int4*>(wp)[k];
+            wpos[4 * k] = (uint32_t)v.x;
+            wpos[4 * k + 1] = (uint32_t)v.y;
+            wpos[4 * k + 2] = (uint32_t)v.z;
+            wpos[4 * k + 3] = (uint32_t)v.w;
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) wpos[4 * k + r] = pos[4 * k + r];
+        }
+    }
     if (first) {
+        float m1v[4 * Q];
 #pragma unroll
-        for (int p = 0; p < D; ++p) X.st(wpos[p], __uint_as_float(__float_as_uint(mp[64 * p]) | sbit));
+        for (int k = 0; k < Q; ++k) {
+            const float4 v = reinterpret_cast<const float4*>(mp)[k];
+            m1v[4 * k] = v.x;
+            m1v[4 * k + 1] = v.y;
+            m1v[4 * k + 2] = v.z;
+            m1v[4 * k + 3] = v.w;
+        }
+#pragma unroll
+        for (int p = 0; p < D; ++p) X.st(wpos[p], __uint_as_float(__float_as_uint(m1v[p]) | sbit));
         return;
     }
     uint32_t nu[D], av[D];
@@ -366,22 +412,27 @@ __device__ __forceinline__ void check_row(const State<LDS> X, const int32_t* rp,
     }
 }
 
+// rp, wp, mp: the group's blocks of the three tables; lane l's entries start at
+// l * ((D + 3) & ~3)
 template <int D, bool LDS>
-__device__ __forceinline__ void check_row_d(const State<LDS> X, const int32_t* rp, const int32_t* wp,
-                                            const float* mp, bool mixed, uint32_t sbit, bool first) {
+__device__ __forceinline__ void check_row_d(const State<LDS> X, const int32_t* rp, const int32_t* wp, const float* mp,
+                                            int lane, bool mixed, uint32_t sbit, bool first) {
+    constexpr int ST = (D + 3) & ~3;
+    const uint32_t o = (uint32_t)lane * ST;
     if (mixed)
-        check_row<D, true>(X, rp, wp, mp, sbit, first);
+        check_row<D, true>(X, rp + o, wp + o, mp + o, sbit, first);
     else
-        check_row<D, false>(X, rp, wp, mp, sbit, first);
+        check_row<D, false>(X, rp + o, wp + o, mp + o, sbit, first);
 }
 
 // stored row degrees: 2..12 exactly, larger rows padded to 16, 24 or 32 slots
 template <int RD, bool LDS>
 __device__ __forceinline__ void check_dispatch(const State<LDS> X, const int32_t* rp, const int32_t* wp,
-                                               const float* mp, int dg, bool mixed, uint32_t sbit, bool first) {
+                                               const float* mp, int lane, int dg, bool mixed, uint32_t sbit,
+                                               bool first) {
     switch (dg) {
 #define RBP_ROW(D) \
-    case D: check_row_d<D>(X, rp, wp, mp, mixed, sbit, first); break;
+    case D: check_row_d<D>(X, rp, wp, mp, lane, mixed, sbit, first); break;
         RBP_ROW(2) RBP_ROW(3) RBP_ROW(4) RBP_ROW(5) RBP_ROW(6) RBP_ROW(7)
         RBP_ROW(8) RBP_ROW(9) RBP_ROW(10) RBP_ROW(11) RBP_ROW(12)
         default:
@@ -460,8 +511,10 @@ __device__ __forceinline__ void flip_slots(const int32_t* scheck, uint32_t sb, i
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-template <int RD, bool LDS_STATE>
-__global__ void __launch_bounds__(1024, 4) relay_bp_kernel(const DecodeLaunch a) {
+// MINW: waves per SIMD the register allocation must allow (4: up to 128
+// VGPRs; 8: up to 64, for launch shapes whose LDS permits 8 waves per SIMD).
+template <int RD, bool LDS_STATE, int MINW>
+__global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63;
     const int wid = uniform(tid >> 6), nw = nth >> 6;
@@ -584,7 +637,7 @@ __global__ void __launch_bounds__(1024, 4) relay_bp_kernel(const DecodeLaunch a)
                     const bool leg0 = leg == 0;
                     const bool lp = prop && leg0;  // priors of this leg are Lambda + delta
                     const int T = leg0 ? a.T0 : a.Tr;
-                    const float* gt = m.gtabp + (int64_t)(leg0 ? 0 : leg - 1) * m.Np;
+                    const float2* lgl = m.lg + (int64_t)leg * m.Np;  // {Lambda, gamma} of this leg
                     bool conv = false;
                     ++legs;
                     for (int t = 1; t <= T; ++t) {
@@ -592,9 +645,9 @@ __global__ void __launch_bounds__(1024, 4) relay_bp_kernel(const DecodeLaunch a)
                         // ---- check sweep: one row group per wave at a time
                         for (int g = wid; g < m.GR; g += nw) {
                             const int4 gi = m.rgrp[g];
-                            const uint32_t off = (uint32_t)uniform(gi.x) + (uint32_t)lane;
+                            const uint32_t off = (uint32_t)uniform(gi.x);
                             const uint32_t sbit = ((sigp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u) << 31;
-                            check_dispatch<RD>(X, m.rposp + off, m.rposw + off, m.m1pp + off, uniform(gi.y),
+                            check_dispatch<RD>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane, uniform(gi.y),
                                                uniform(gi.z) != 0, sbit, first_plain);
                         }
                         __syncthreads();
@@ -607,13 +660,13 @@ __global__ void __launch_bounds__(1024, 4) relay_bp_kernel(const DecodeLaunch a)
                             const int dg = uniform(gi.y);
                             const bool mixed = uniform(gi.z) != 0;
                             const uint32_t pp = (uint32_t)(g * 64 + lane);
-                            const float l = ldg(m.lamp, pp), gv = ldg(gt, pp);
+                            const float2 lgv = ldg(lgl, pp);
+                            const float l = lgv.x, gm = lgv.y;
                             float lt = l;
                             if (lp) {
                                 const int j = ldg(m.vord, pp);
                                 if (j >= 0) lt = l + dlt[j];
                             }
-                            const float gm = leg0 ? a.gamma0 : gv;
                             const float mo = Mg[pp];
                             float acc = __builtin_fmaf(gm, mo - lt, lt);
                             const uint32_t sb = 4u * ((uint32_t)uniform(gi.x) + (uint32_t)lane);
@@ -781,6 +834,7 @@ static rbp_status ensure_llr(rbp_code* c, const double* priors, hipStream_t stre
                        c->m1.as<float>(), npos);
     RBP_HIP_CHECK(hipGetLastError());
     c->lam_key.assign(priors, priors + c->N);
+    ++c->lam_gen;
     return RBP_OK;
 }
 
@@ -817,9 +871,30 @@ static rbp_status ensure_gamma(rbp_code* c, const rbp_relay_params* p, hipStream
         RBP_HIP_CHECK(hipGetLastError());
     }
     c->gtab_R = R;
+    ++c->gtab_gen;
     c->gtab_seed = p->gamma_seed;
     c->gtab_lo = p->gamma_min;
     c->gtab_hi = p->gamma_max;
+    return RBP_OK;
+}
+
+// the {Lambda, gamma} table, rebuilt when the priors, the gamma table or gamma0 change
+static rbp_status ensure_lam_gamma(rbp_code* c, const rbp_relay_params* p, hipStream_t stream) {
+    const int R = p->num_sets;
+    if (c->lg.p && c->lg_lam_gen == c->lam_gen && c->lg_gtab_gen == c->gtab_gen && c->lg_gamma0 == p->gamma0 &&
+        c->lg_R == R)
+        return RBP_OK;
+    const int64_t total = (int64_t)c->Np * (R + 1);
+    RBP_HIP_CHECK(hipStreamSynchronize(stream));
+    rbp_status st = c->lg.reserve(sizeof(float2) * total);
+    if (st) return st;
+    hipLaunchKernelGGL(lam_gamma_kernel, dim3(ceil_div(total, 256)), dim3(256), 0, stream, c->lg.as<float2>(),
+                       c->lamp.as<float>(), c->gtab.as<float>(), c->Np, R, p->gamma0);
+    RBP_HIP_CHECK(hipGetLastError());
+    c->lg_lam_gen = c->lam_gen;
+    c->lg_gtab_gen = c->gtab_gen;
+    c->lg_gamma0 = p->gamma0;
+    c->lg_R = R;
     return RBP_OK;
 }
 
@@ -860,6 +935,7 @@ static DecodeModel model_of(const rbp_code* c, const uint32_t* syn, uint32_t* co
     m.scsc = c->scsc.as<int32_t>();
     m.lamp = c->lamp.as<float>();
     m.gtabp = c->gtab.as<float>();
+    m.lg = c->lg.as<float2>();
     m.ocol_ptr = c->ocol_ptr.as<int32_t>();
     m.orow_idx = c->orow_idx.as<int32_t>();
     m.syn = syn;
@@ -870,9 +946,13 @@ static DecodeModel model_of(const rbp_code* c, const uint32_t* syn, uint32_t* co
 
 typedef void (*DecodeKernel)(const DecodeLaunch);
 
-static DecodeKernel decode_kernel(int max_stored_row_deg, bool lds) {
-    if (max_stored_row_deg <= 12) return lds ? relay_bp_kernel<12, true> : relay_bp_kernel<12, false>;
-    return lds ? relay_bp_kernel<32, true> : relay_bp_kernel<32, false>;
+static DecodeKernel decode_kernel(int max_stored_row_deg, bool lds, int minw) {
+    if (max_stored_row_deg <= 12) {
+        if (minw >= 8) return lds ? relay_bp_kernel<12, true, 8> : relay_bp_kernel<12, false, 8>;
+        return lds ? relay_bp_kernel<12, true, 4> : relay_bp_kernel<12, false, 4>;
+    }
+    if (minw >= 8) return lds ? relay_bp_kernel<32, true, 8> : relay_bp_kernel<32, false, 8>;
+    return lds ? relay_bp_kernel<32, true, 4> : relay_bp_kernel<32, false, 4>;
 }
 
 static constexpr int kMaxLds = 160 * 1024;
@@ -903,13 +983,6 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
         rdmax = std::max(rdmax, cs[i]->max_stored_row_deg);
     }
     const LaunchCfg& cfg = cs[0]->cfg;
-    int waves = cfg.waves_per_shot;
-    if (waves <= 0) {
-        const int want = ceil_div(Npmax, 512);
-        waves = 1;
-        while (waves < want && waves < 8) waves <<= 1;
-    }
-    waves = std::min(std::max(waves, 1), 16);
     // small per-slot arrays (always LDS)
     const int small = align16(4 * (int64_t)WMmax) + align16(8 * (int64_t)GRmax) + align16(4 * (int64_t)WMmax) +
                       align16(4 * (int64_t)(Npmax / 32)) + align16(4 * (int64_t)WNmax) + align16(4 * (int64_t)WKmax) +
@@ -918,8 +991,25 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
     bool lds = state_bytes + small <= kMaxLds;
     if (cfg.state == 1 && !lds) return fail(RBP_ERR_UNSUPPORTED, "per-shot state does not fit in LDS");
     if (cfg.state == 2) lds = false;
+    int waves = cfg.waves_per_shot;
+    if (waves <= 0) {
+        if (lds) {
+            // about 8 waves per SIMD (32 per CU) over the slots that fit in LDS, and
+            // at least min(4, groups) waves so that a slow shot is not left to one wave
+            const int per_cu_lds = (int)std::max<int64_t>(kMaxLds / (state_bytes + small), 1);
+            int groups = 0;
+            for (int i = 0; i < n; ++i) groups = std::max(groups, std::max(cs[i]->GR, cs[i]->GV));
+            waves = 1;
+            while (waves * 2 * per_cu_lds <= 32 && waves < 16) waves <<= 1;
+            while (waves < 4 && waves < groups) waves <<= 1;
+        } else {
+            const int want = ceil_div(Npmax, 512);
+            waves = 1;
+            while (waves < want && waves < 16) waves <<= 1;
+        }
+    }
+    waves = std::min(std::max(waves, 1), 16);
     LaunchShape L;
-    L.kernel = decode_kernel(rdmax, lds);
     L.waves = waves;
     L.lds_state = lds;
     L.Smax = Smax;
@@ -946,10 +1036,20 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
     if (off > kMaxLds) return fail(RBP_ERR_UNSUPPORTED, "per-shot bit arrays do not fit in LDS");
     L.lds_bytes = (int)off;
     L.gstride = lds ? 0 : ((int64_t)Smax + 4 + Npmax + 63) / 64 * 64;
+    // the register budget (128 or 64 VGPRs) that fits more slots per CU; on a
+    // tie the larger budget (no spills)
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(L.kernel),
-                                                                64 * waves, L.lds_bytes);
-    if (e != hipSuccess) return fail(RBP_ERR_HIP, std::string("occupancy query: ") + hipGetErrorString(e));
+    for (int minw : {4, 8}) {
+        DecodeKernel k = decode_kernel(rdmax, lds, minw);
+        int pc = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, reinterpret_cast<const void*>(k), 64 * waves,
+                                                                    L.lds_bytes);
+        if (e != hipSuccess) return fail(RBP_ERR_HIP, std::string("occupancy query: ") + hipGetErrorString(e));
+        if (!L.kernel || pc > per_cu) {
+            L.kernel = k;
+            per_cu = pc;
+        }
+    }
     per_cu = std::max(per_cu, 1);
     int64_t slots = (int64_t)per_cu * std::max(cs[0]->num_cus, 1);
     if (cfg.max_slots > 0) slots = std::min<int64_t>(slots, cfg.max_slots);
@@ -1118,10 +1218,12 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
             const int i = rord[64 * g + l];
             mixed |= i < 0 || deg[i] != dst;
         }
+        const int st = (dst + 3) & ~3;  // entries per lane, 16-byte aligned
         rgrp[4 * g] = (int32_t)RB;
         rgrp[4 * g + 1] = dst;
         rgrp[4 * g + 2] = mixed ? 1 : 0;
-        RB += 64 * (int64_t)dst;
+        rgrp[4 * g + 3] = st;
+        RB += 64 * (int64_t)st;
         maxstored = std::max(maxstored, dst);
     }
     if (RB > (int64_t)INT32_MAX) return fail(RBP_ERR_UNSUPPORTED, "too many edges");
@@ -1130,7 +1232,7 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
     for (int j = 0; j < N; ++j)
         for (int e = col_ptr[j]; e < col_ptr[j + 1]; ++e) {
             const int i = row_idx[e], p = rfill[i]++, pos = rinv[i];
-            const size_t at = (size_t)rgrp[4 * (pos >> 6)] + 64 * p + (pos & 63);
+            const size_t at = (size_t)rgrp[4 * (pos >> 6)] + (size_t)(pos & 63) * rgrp[4 * (pos >> 6) + 3] + p;
             rposp[at] = 4 * slot_of[e];
             rposw[at] = 4 * slot_of[e];
         }
@@ -1205,7 +1307,7 @@ rbp_status rbp_code_destroy(rbp_code_t c) {
     (void)hipDeviceSynchronize();
     for (DevBuf* b : {&c->row_ptr, &c->col_idx, &c->col_ptr, &c->csc_row, &c->rgrp, &c->rposp, &c->rposw, &c->rord, &c->vgrp,
                       &c->vord, &c->vdeg, &c->pinv, &c->scheck, &c->scsc, &c->orow_ptr, &c->ocol_idx, &c->ocol_ptr,
-                      &c->orow_idx, &c->thr, &c->lam, &c->lamp, &c->m1, &c->gtab, &c->queue, &c->gstate,
+                      &c->orow_idx, &c->thr, &c->lam, &c->lamp, &c->m1, &c->gtab, &c->lg, &c->queue, &c->gstate,
                       &c->trace_hit})
         b->release();
     delete c;
@@ -1284,6 +1386,7 @@ rbp_status rbp_decode(rbp_code_t c, const double* priors, const uint32_t* syndro
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
     st = ensure_llr(c, priors, stream);
     if (!st) st = ensure_gamma(c, params, stream);
+    if (!st) st = ensure_lam_gamma(c, params, stream);
     if (st) return st;
     DecodeLaunch a;
     std::memset(&a, 0, sizeof(a));
@@ -1321,6 +1424,7 @@ rbp_status rbp_decode_multi(int32_t n_codes, const rbp_code_t* codes, const doub
         st = check_priors(priors[i], c->N);
         if (!st) st = ensure_llr(c, priors[i], stream);
         if (!st) st = ensure_gamma(c, params, stream);
+        if (!st) st = ensure_lam_gamma(c, params, stream);
         if (st) return st;
         cs[i] = c;
         a.m[i] = model_of(c, syndromes[i], corrections[i], obs_pred ? obs_pred[i] : nullptr);
@@ -1394,6 +1498,7 @@ rbp_status rbp_trace(rbp_code_t c, const double* priors, const uint32_t* syndrom
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
     st = ensure_llr(c, priors, stream);
     if (!st) st = ensure_gamma(c, params, stream);
+    if (!st) st = ensure_lam_gamma(c, params, stream);
     if (!st) st = c->trace_hit.reserve(16);
     if (st) return st;
     RBP_HIP_CHECK(hipMemsetAsync(c->trace_hit.p, 0, 16, stream));
