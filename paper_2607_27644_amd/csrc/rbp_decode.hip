@@ -229,7 +229,6 @@ struct DecodeModel {
     const int4* vgrp;      // [GV] {first slot, degree, mixed, 0}
     const int32_t* vord;   // [Np] variable at each position, -1 for padding
     const int32_t* vdeg;   // [Np] degree at each position (0 for padding)
-    const int32_t* pinv;   // [N] position of each variable
     const int32_t* scheck; // [S] check of each slot (-1 unused)
     const int32_t* scsc;   // [S] CSC edge index of each slot (-1 unused)
     const float* lamp;     // [Np] Lambda by position (0 for padding)
@@ -571,6 +570,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
             par[w] = v;
             pc += __popc(v);
         }
+        for (int w = tid; w < m.WK; w += nth) obw[w] = 0u;
         const int base = block_sum<int>(pc, ms->red);
 
         int nconv = 0, legs = 0, iters = 0, path = 0;
@@ -736,27 +736,20 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                     }
                 }
             }
+            for (int w = tid; w < WN; w += nth) best[w] = 0u;
             __syncthreads();
-            // positions -> variable order
-            for (int jb = wid * 64; jb < N; jb += nth) {
-                const int j = jb + lane;
-                bool bit = false;
-                if (j < N) {
-                    const int pp = m.pinv[j];
-                    bit = (bestp[pp >> 5] >> (pp & 31)) & 1u;
-                }
-                const unsigned long long b = __ballot(bit);
-                if (lane == 0) {
-                    best[jb >> 5] = (uint32_t)b;
-                    if ((jb >> 5) + 1 < WN) best[(jb >> 5) + 1] = (uint32_t)(b >> 32);
+            // positions -> variable order: scatter the (few) set bits
+            for (int g = wid; g < m.GV; g += nw) {
+                if ((bestp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u) {
+                    const int j = ldg(m.vord, (uint32_t)(g * 64 + lane));
+                    atomicOr(best + (j >> 5), 1u << (j & 31));
                 }
             }
             __syncthreads();
         }
         if (!a.trace_on) {
             // corrections out; O * correction from the columns of O at its set bits
-            for (int w = tid; w < m.WK; w += nth) obw[w] = 0u;
-            __syncthreads();
+            // (obw was cleared with the shot's setup)
             for (int w = tid; w < WN; w += nth) {
                 const uint32_t bits = best[w];
                 m.corr[row * WN + w] = bits;
@@ -930,7 +923,6 @@ static DecodeModel model_of(const rbp_code* c, const uint32_t* syn, uint32_t* co
     m.vgrp = c->vgrp.as<int4>();
     m.vord = c->vord.as<int32_t>();
     m.vdeg = c->vdeg.as<int32_t>();
-    m.pinv = c->pinv.as<int32_t>();
     m.scheck = c->scheck.as<int32_t>();
     m.scsc = c->scsc.as<int32_t>();
     m.lamp = c->lamp.as<float>();
@@ -1170,11 +1162,10 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
         vperm[j] = j;
     }
     std::stable_sort(vperm.begin(), vperm.end(), [&](int x, int y) { return cdeg[x] > cdeg[y]; });
-    std::vector<int32_t> vord(Np, -1), vdeg(Np, 0), pinv(N), vgrp(4 * (size_t)GV, 0);
+    std::vector<int32_t> vord(Np, -1), vdeg(Np, 0), vgrp(4 * (size_t)GV, 0);
     for (int p = 0; p < N; ++p) {
         vord[p] = vperm[p];
         vdeg[p] = cdeg[vperm[p]];
-        pinv[vperm[p]] = p;
     }
     int64_t S = 0;
     for (int g = 0; g < GV; ++g) {
@@ -1287,7 +1278,6 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
     if (!st) st = upload(c->vgrp, vgrp);
     if (!st) st = upload(c->vord, vord);
     if (!st) st = upload(c->vdeg, vdeg);
-    if (!st) st = upload(c->pinv, pinv);
     if (!st) st = upload(c->scheck, scheck);
     if (!st) st = upload(c->scsc, scsc);
     if (!st) st = upload(c->orow_ptr, orp);
@@ -1306,7 +1296,7 @@ rbp_status rbp_code_destroy(rbp_code_t c) {
     if (!c) return RBP_OK;
     (void)hipDeviceSynchronize();
     for (DevBuf* b : {&c->row_ptr, &c->col_idx, &c->col_ptr, &c->csc_row, &c->rgrp, &c->rposp, &c->rposw, &c->rord, &c->vgrp,
-                      &c->vord, &c->vdeg, &c->pinv, &c->scheck, &c->scsc, &c->orow_ptr, &c->ocol_idx, &c->ocol_ptr,
+                      &c->vord, &c->vdeg, &c->scheck, &c->scsc, &c->orow_ptr, &c->ocol_idx, &c->ocol_ptr,
                       &c->orow_idx, &c->thr, &c->lam, &c->lamp, &c->m1, &c->gtab, &c->lg, &c->queue, &c->gstate,
                       &c->trace_hit})
         b->release();
