@@ -78,11 +78,12 @@ def cpu_baseline(dem, shots_total: int, seed: int, params, target_s: float):
         return time.perf_counter() - t0, r
 
     dt, _ = run(2000)
-    n = int(min(shots_total, max(2000, 2000 * target_s / max(dt, 1e-3))))
+    # about target_s of work, at most 10 steps' worth of shots
+    n = int(min(10 * shots_total, max(2000, 2000 * target_s / max(dt, 1e-3))))
     dt, r = run(n)
     return {"value": n / dt, "unit": "shots/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} of the {shots_total} shots (same seed): oracle sampling + Relay-BP decode "
-                      f"on {threads} threads, {dt:.1f} s",
+            "sample": f"{n} shots of the same model and seed (the first {min(n, shots_total)} are the first "
+                      f"timed step's shots): oracle sampling + Relay-BP decode on {threads} threads, {dt:.1f} s",
             "mean_iters_per_shot": float(np.mean(r["iters"]))}
 
 
@@ -211,6 +212,7 @@ def main():
         t1 = time.perf_counter()
         net = rbp.MLP(dem.M, cfg.hidden, dem.N, seed=cfg.seed)
         hist = learned.train(net, chunks, cfg)
+        learned.scale_output(net, cfg.delta_scale)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         del chunks
@@ -231,6 +233,7 @@ def main():
                 "latency_us": {"batched_service_time": stats.percentiles(sv)}}
         paths["learned"]["training"] = {"pairs": cfg.pairs, "p_range": [cfg.p_lo, cfg.p_hi], "epochs": cfg.epochs,
                                         "batch": cfg.batch, "hidden": cfg.hidden, "params": net.n_params,
+                                        "delta_scale": cfg.delta_scale,
                                         "generate_s": t1 - t0, "train_s": t2 - t1, "final_loss": hist[-1][1]}
         paths["learned"]["vs_plain"] = paths["learned"]["value"] / value
         paths["proposal_zero"]["note"] = "control: the same proposal leg with delta = 0 (no network)"
