@@ -447,53 +447,79 @@ __device__ __forceinline__ void check_dispatch(const State<LDS> X, const int32_t
 }
 
 // One variable with D edge slots (byte offsets sb + 256 q): M = Lambda~ +
-// sum_q mu_q (checks ascending), then nu_q = M - mu_q.  In a mixed group only
-// the member's own vd edges enter the sum (its remaining slots are unused by
-// any check).
-template <int D, bool MIXED, bool LDS>
+// sum_q mu_q (checks ascending), then nu_q = M - mu_q written back (WRITE), or
+// mu left in place (see the first iteration of a plain leg in the kernel).  In
+// a mixed group only the member's own vd edges enter the sum (its remaining
+// slots are unused by any check).
+template <int D, bool MIXED, bool WRITE, bool LDS>
 __device__ __forceinline__ float var_member(const State<LDS> X, uint32_t sb, int vd, float acc) {
     float mu[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) mu[q] = X.ld(sb + 256u * q);
 #pragma unroll
     for (int q = 0; q < D; ++q) acc = (!MIXED || q < vd) ? acc + mu[q] : acc;
+    if (WRITE) {
 #pragma unroll
-    for (int q = 0; q < D; ++q) X.st(sb + 256u * q, acc - mu[q]);
+        for (int q = 0; q < D; ++q) X.st(sb + 256u * q, acc - mu[q]);
+    }
     return acc;
 }
 
 // rolled form for large degrees and traced iterations
 template <bool LDS>
-__device__ __forceinline__ float var_member_rolled(const State<LDS> X, uint32_t sb, int vd, float acc, float* trace_mu,
-                                                const int32_t* scsc) {
+__device__ __forceinline__ float var_member_rolled(const State<LDS> X, bool write, uint32_t sb, int vd, float acc,
+                                                   float* trace_mu, const int32_t* scsc) {
     for (int q = 0; q < vd; ++q) acc = acc + X.ld(sb + 256u * q);
     for (int q = 0; q < vd; ++q) {
         const uint32_t o = sb + 256u * q;
         const float mu = X.ld(o);
         if (trace_mu) trace_mu[scsc[o >> 2]] = mu;
-        X.st(o, acc - mu);
+        if (write) X.st(o, acc - mu);
     }
     return acc;
 }
 
-template <int D, bool LDS>
+template <int D, bool WRITE, bool LDS>
 __device__ __forceinline__ float var_member_d(const State<LDS> X, uint32_t sb, bool mixed, int vd, float acc) {
-    return mixed ? var_member<D, true>(X, sb, vd, acc) : var_member<D, false>(X, sb, vd, acc);
+    return mixed ? var_member<D, true, WRITE>(X, sb, vd, acc) : var_member<D, false, WRITE>(X, sb, vd, acc);
 }
 
-template <bool LDS>
+template <bool WRITE, bool LDS>
 __device__ __forceinline__ float var_dispatch(const State<LDS> X, uint32_t sb, int dg, bool mixed, int vd, float acc) {
     switch (dg) {
         case 0: return acc;
-        case 1: return var_member_d<1>(X, sb, mixed, vd, acc);
-        case 2: return var_member_d<2>(X, sb, mixed, vd, acc);
-        case 3: return var_member_d<3>(X, sb, mixed, vd, acc);
-        case 4: return var_member_d<4>(X, sb, mixed, vd, acc);
-        case 5: return var_member_d<5>(X, sb, mixed, vd, acc);
-        case 6: return var_member_d<6>(X, sb, mixed, vd, acc);
-        case 7: return var_member_d<7>(X, sb, mixed, vd, acc);
-        case 8: return var_member_d<8>(X, sb, mixed, vd, acc);
-        default: return var_member_rolled(X, sb, vd, acc, nullptr, nullptr);
+#define RBP_VAR(D) \
+    case D: return var_member_d<D, WRITE>(X, sb, mixed, vd, acc);
+        RBP_VAR(1) RBP_VAR(2) RBP_VAR(3) RBP_VAR(4) RBP_VAR(5) RBP_VAR(6) RBP_VAR(7) RBP_VAR(8)
+#undef RBP_VAR
+        default: return var_member_rolled(X, WRITE, sb, vd, acc, nullptr, nullptr);
+    }
+}
+
+// nu_q = M - mu_q for one variable whose mu were left in X (same operands as
+// the variable sweep's own write-back)
+template <int D, bool LDS>
+__device__ __forceinline__ void extrinsic_d(const State<LDS> X, uint32_t sb, float M) {
+    float mu[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) mu[q] = X.ld(sb + 256u * q);
+#pragma unroll
+    for (int q = 0; q < D; ++q) X.st(sb + 256u * q, M - mu[q]);
+}
+
+template <bool LDS>
+__device__ __forceinline__ void extrinsic_dispatch(const State<LDS> X, uint32_t sb, int dg, float M) {
+    switch (dg) {
+        case 0: return;
+#define RBP_EXT(D) \
+    case D: extrinsic_d<D>(X, sb, M); return;
+        RBP_EXT(1) RBP_EXT(2) RBP_EXT(3) RBP_EXT(4) RBP_EXT(5) RBP_EXT(6) RBP_EXT(7) RBP_EXT(8)
+#undef RBP_EXT
+        default:
+            for (int q = 0; q < dg; ++q) {
+                const uint32_t o = sb + 256u * q;
+                X.st(o, M - X.ld(o));
+            }
     }
 }
 
@@ -574,6 +600,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
         const int base = block_sum<int>(pc, ms->red);
 
         int nconv = 0, legs = 0, iters = 0, path = 0;
+        bool x_mu1 = false;  // X holds mu(1) of a plain leg
         bool have_best = false;
         double bestW = 0.0;
         bool traced = false;
@@ -608,6 +635,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                     __syncthreads();
                 }
                 // M(0) = Lambda (or Lambda + delta; then also nu(0) = Lambda + delta on every edge)
+                x_mu1 = false;
                 {
                     int dc = 0;
                     double dW = 0.0;
@@ -641,16 +669,28 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                     bool conv = false;
                     ++legs;
                     for (int t = 1; t <= T; ++t) {
+                        // The first iteration of a plain leg starts from nu(0) = Lambda, so its
+                        // check messages mu(1) are the same for every plain leg of the shot.  Its
+                        // variable sweep leaves mu(1) in X; if the leg converges there, the next
+                        // leg finds mu(1) in place and skips that check sweep, otherwise nu(1) is
+                        // formed from the marginals before the second check sweep.
                         const bool first_plain = t == 1 && !lp;
-                        // ---- check sweep: one row group per wave at a time
-                        for (int g = wid; g < m.GR; g += nw) {
-                            const int4 gi = m.rgrp[g];
-                            const uint32_t off = (uint32_t)uniform(gi.x);
-                            const uint32_t sbit = ((sigp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u) << 31;
-                            check_dispatch<RD>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane, uniform(gi.y),
-                                               uniform(gi.z) != 0, sbit, first_plain);
+                        if (!(first_plain && x_mu1)) {
+                            // ---- check sweep: one row group per wave at a time
+                            for (int g = wid; g < m.GR; g += nw) {
+                                const int4 gi = m.rgrp[g];
+                                const uint32_t off = (uint32_t)uniform(gi.x);
+                                const uint32_t sbit = ((sigp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u) << 31;
+                                check_dispatch<RD>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane, uniform(gi.y),
+                                                   uniform(gi.z) != 0, sbit, first_plain);
+                            }
+                            __syncthreads();
+                            x_mu1 = first_plain;
+                        } else {
+                            // every thread has read the count and weight of the previous leg
+                            // before this sweep's atomics change them
+                            __syncthreads();
                         }
-                        __syncthreads();
                         // ---- variable sweep: one variable group per wave at a time
                         const bool tr = a.trace_on && phase == a.trace_phase && leg == a.trace_leg && t == a.trace_t;
                         int dcount = 0;
@@ -672,9 +712,10 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                             const uint32_t sb = 4u * ((uint32_t)uniform(gi.x) + (uint32_t)lane);
                             const int vd = mixed ? ldg(m.vdeg, pp) : dg;
                             if (!tr) {
-                                acc = var_dispatch(X, sb, dg, mixed, vd, acc);
+                                acc = first_plain ? var_dispatch<false>(X, sb, dg, mixed, vd, acc)
+                                                  : var_dispatch<true>(X, sb, dg, mixed, vd, acc);
                             } else {
-                                acc = var_member_rolled(X, sb, vd, acc, a.trace_mu, m.scsc);
+                                acc = var_member_rolled(X, !first_plain, sb, vd, acc, a.trace_mu, m.scsc);
                                 const int j = ldg(m.vord, pp);
                                 if (j >= 0) a.trace_M[j] = acc;
                             }
@@ -696,6 +737,17 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                         if (base + ms->count == 0) {
                             conv = true;
                             break;
+                        }
+                        if (first_plain) {
+                            // not converged on mu(1): nu(1) = M - mu(1) for the second check sweep
+                            for (int g = wid; g < m.GV; g += nw) {
+                                const int4 gi = m.vgrp[g];
+                                const uint32_t pp = (uint32_t)(g * 64 + lane);
+                                extrinsic_dispatch(X, 4u * ((uint32_t)uniform(gi.x) + (uint32_t)lane), uniform(gi.y),
+                                                   Mg[pp]);
+                            }
+                            __syncthreads();
+                            x_mu1 = false;
                         }
                     }
                     if (traced) break;
