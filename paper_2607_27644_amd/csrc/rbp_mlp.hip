@@ -12,9 +12,10 @@
 //
 // All products are one tiled GEMM kernel: C[MxN] = opA(A)[MxK] . opB(B)[KxN]
 // with a 128x128 output tile per workgroup of 4 wavefronts, each computing a
-// 64x64 block with v_mfma_f32_32x32x16_bf16, operands staged through LDS in a
-// K-contiguous layout (operands stored M- or N-contiguous are transposed while
-// staging).  Epilogues fuse the bias, ReLU, the ReLU mask of the backward pass
+// 64x64 block with v_mfma_f32_32x32x16_bf16, operands staged through two LDS
+// buffers in a K-contiguous layout (operands stored M- or N-contiguous are
+// transposed while staging; the next K step's tiles are loaded while the
+// current ones are multiplied).  Epilogues fuse the bias, ReLU, the ReLU mask of the backward pass
 // and the BF16/FP32 stores.
 #include <algorithm>
 #include <cmath>
@@ -34,7 +35,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int BM = 128, BN = 128, BK = 32;
 constexpr int LDSK = BK + 8;  // padded row of the staged tiles (bank spread)
 
-enum Layout { K_CONTIG = 0, MN_CONTIG = 1 };
+enum Layout { K_CONTIG = 0, MN_CONTIG = 1, BITS = 2 };  // BITS: A is packed 0/1 bits, 32 per word, rows of lda words
 enum Epi {
     EPI_BIAS_RELU_BF16 = 0,  // out_bf16 = bf16(relu(acc + bias[n]))
     EPI_BIAS_F32 = 1,        // out_f32 = acc + bias[n]
@@ -55,54 +56,90 @@ struct GemmArgs {
     int ldc;
 };
 
-// Stages a BM x BK (or BN x BK) tile of an operand into LDS as tile[row][k].
+// A BM x BK (or BN x BK) tile of an operand in flight from device memory to
+// LDS: each thread holds VPT vectors of 8 BF16 between the load (issued one K
+// step ahead) and the store into tile[row][k].
+constexpr int VPT = BM * BK / 8 / 256;
+static_assert(BM == BN && VPT * 256 * 8 == BM * BK, "tile shape");
+
+struct TileRegs {
+    bf16x8 x[VPT];
+};
+
 template <int LAYOUT>
-__device__ __forceinline__ void stage(bf16 (*tile)[LDSK], const bf16* src, int ld, int rows, int K, int r0, int k0) {
+__device__ __forceinline__ TileRegs load_tile(const bf16* src, int ld, int rows, int K, int r0, int k0) {
     const int t = threadIdx.x;
+    TileRegs v;
+    if constexpr (LAYOUT == BITS) {
+        // rows x BK k as vectors of 8 bits, each inside one 32-bit word (k0 and
+        // the vector offsets are multiples of 8): expanded to BF16 0/1 in registers
+        const uint32_t* w = reinterpret_cast<const uint32_t*>(src);
+#pragma unroll
+        for (int pass = 0; pass < VPT; ++pass) {
+            const int q = t + pass * 256;
+            const int r = q / (BK / 8), kk = (q % (BK / 8)) * 8;
+            const int gr = r0 + r, gk = k0 + kk;
+            const uint32_t bits = gr < rows && gk < K ? (w[(int64_t)gr * ld + (gk >> 5)] >> (gk & 31)) : 0u;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v.x[pass][i] = ((bits >> i) & 1u) && gk + i < K ? (bf16)1.0f : (bf16)0.0f;
+        }
+        return v;
+    }
     // 16-byte vector loads need a 16-byte aligned base and a leading dimension of 8k
     const bool vec = ((reinterpret_cast<uintptr_t>(src) & 15) == 0) && ((ld & 7) == 0);
-    if constexpr (LAYOUT == K_CONTIG) {
-        // 128 rows x 32 k = 512 vectors of 8; 2 per thread
 #pragma unroll
-        for (int pass = 0; pass < 2; ++pass) {
-            const int v = t + pass * 256;
-            const int r = v >> 2, kk = (v & 3) * 8;
+    for (int pass = 0; pass < VPT; ++pass) {
+        const int q = t + pass * 256;
+        if constexpr (LAYOUT == K_CONTIG) {
+            // rows x BK k as vectors of 8 k
+            const int r = q / (BK / 8), kk = (q % (BK / 8)) * 8;
             const int gr = r0 + r, gk = k0 + kk;
-            bf16x8 x;
             if (vec && gr < rows && gk + 7 < K) {
-                x = *reinterpret_cast<const bf16x8*>(src + (int64_t)gr * ld + gk);
+                v.x[pass] = *reinterpret_cast<const bf16x8*>(src + (int64_t)gr * ld + gk);
             } else {
 #pragma unroll
                 for (int i = 0; i < 8; ++i)
-                    x[i] = (gr < rows && gk + i < K) ? src[(int64_t)gr * ld + gk + i] : (bf16)0.0f;
+                    v.x[pass][i] = (gr < rows && gk + i < K) ? src[(int64_t)gr * ld + gk + i] : (bf16)0.0f;
             }
-            *reinterpret_cast<bf16x8*>(&tile[r][kk]) = x;
-        }
-    } else {
-        // 32 k x 128 rows, rows contiguous in memory: vectors of 8 rows
-#pragma unroll
-        for (int pass = 0; pass < 2; ++pass) {
-            const int v = t + pass * 256;
-            const int kk = v >> 4, r = (v & 15) * 8;
+        } else {
+            // BK k x rows, rows contiguous in memory: vectors of 8 rows
+            const int kk = q / (BM / 8), r = (q % (BM / 8)) * 8;
             const int gr = r0 + r, gk = k0 + kk;
-            bf16x8 x;
             if (vec && gk < K && gr + 7 < rows) {
-                x = *reinterpret_cast<const bf16x8*>(src + (int64_t)gk * ld + gr);
+                v.x[pass] = *reinterpret_cast<const bf16x8*>(src + (int64_t)gk * ld + gr);
             } else {
 #pragma unroll
                 for (int i = 0; i < 8; ++i)
-                    x[i] = (gk < K && gr + i < rows) ? src[(int64_t)gk * ld + gr + i] : (bf16)0.0f;
+                    v.x[pass][i] = (gk < K && gr + i < rows) ? src[(int64_t)gk * ld + gr + i] : (bf16)0.0f;
             }
+        }
+    }
+    return v;
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void store_tile(bf16 (*tile)[LDSK], const TileRegs& v) {
+    const int t = threadIdx.x;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) tile[r + i][kk] = x[i];
+    for (int pass = 0; pass < VPT; ++pass) {
+        const int q = t + pass * 256;
+        if constexpr (LAYOUT == K_CONTIG || LAYOUT == BITS) {
+            const int r = q / (BK / 8), kk = (q % (BK / 8)) * 8;
+            *reinterpret_cast<bf16x8*>(&tile[r][kk]) = v.x[pass];
+        } else {
+            const int kk = q / (BM / 8), r = (q % (BM / 8)) * 8;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) tile[r + i][kk] = v.x[pass][i];
         }
     }
 }
 
 template <int LA, int LB, int EPI>
 __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs g) {
-    __shared__ __align__(16) bf16 As[BM][LDSK];
-    __shared__ __align__(16) bf16 Bs[BN][LDSK];
+    // two LDS stages: the tiles of step k are read by the matrix cores while
+    // those of step k + 1 arrive in registers
+    __shared__ __align__(16) bf16 As[2][BM][LDSK];
+    __shared__ __align__(16) bf16 Bs[2][BN][LDSK];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int wm = (wid >> 1) * 64, wn = (wid & 1) * 64;  // this wave's 64x64 block
@@ -112,10 +149,21 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{};
 
+    {
+        const TileRegs ra = load_tile<LA>(g.A, g.lda, g.M, g.K, m0, 0);
+        const TileRegs rb = load_tile<LB>(g.B, g.ldb, g.N, g.K, n0, 0);
+        store_tile<LA>(As[0], ra);
+        store_tile<LB>(Bs[0], rb);
+    }
+    __syncthreads();
+    int cur = 0;
     for (int k0 = 0; k0 < g.K; k0 += BK) {
-        stage<LA>(As, g.A, g.lda, g.M, g.K, m0, k0);
-        stage<LB>(Bs, g.B, g.ldb, g.N, g.K, n0, k0);
-        __syncthreads();
+        const bool more = k0 + BK < g.K;
+        TileRegs ra, rb;
+        if (more) {
+            ra = load_tile<LA>(g.A, g.lda, g.M, g.K, m0, k0 + BK);
+            rb = load_tile<LB>(g.B, g.ldb, g.N, g.K, n0, k0 + BK);
+        }
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 16) {
             // lane: row (lane % 32) of a 32-row block, 8 consecutive k from (lane / 32) * 8.
@@ -124,16 +172,24 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs g) {
             const int kk = ks + (lane >> 5) * 8;
             bf16x8 af[2], bfr[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&As[wm + i * 32 + (lane & 31)][kk]);
+            for (int i = 0; i < 2; ++i)
+                af[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wm + i * 32 + (lane & 31)][kk]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + j * 32 + (lane & 31)][kk]);
+            for (int j = 0; j < 2; ++j)
+                bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wn + j * 32 + (lane & 31)][kk]);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
         }
+        if (more) {
+            // the other stage was last read before the previous barrier
+            store_tile<LA>(As[cur ^ 1], ra);
+            store_tile<LB>(Bs[cur ^ 1], rb);
+        }
         __syncthreads();
+        cur ^= 1;
     }
     // 32x32 accumulator layout: register r of lane l is C[8*(r/4) + 4*(l/32) + r%4][l%32]
 #pragma unroll
@@ -360,22 +416,33 @@ rbp_status colsum(rbp_mlp* p, const float* in, int B, int N, float* out, hipStre
     return RBP_OK;
 }
 
-// forward of B rows: x from syndromes, h1, h2 (workspace), delta into `dout`
-rbp_status forward(rbp_mlp* p, const uint32_t* syn, int B, float* dout, hipStream_t s) {
+// forward of B rows: x from syndromes, h1, h2 (workspace), delta into `dout`.
+// Training keeps x as BF16 (the weight gradient of layer 1 needs it); inference
+// expands the syndrome bits while staging the first product's tiles.
+rbp_status forward(rbp_mlp* p, const uint32_t* syn, int B, float* dout, hipStream_t s, bool keep_x) {
     const int words = (p->in + 31) / 32;
     bf16* xb = p->xb.as<bf16>();
     bf16* h1 = p->h1.as<bf16>();
     bf16* h2 = p->h2.as<bf16>();
     const bf16* wb = p->wb.as<bf16>();
     const float* w = p->w.as<float>();
-    hipLaunchKernelGGL(expand_bits_kernel, dim3(blocks((int64_t)B * p->in, 256)), dim3(256), 0, s, syn, words, p->in,
-                       B, xb);
-    RBP_HIP_CHECK(hipGetLastError());
-    GemmArgs a = ga(B, p->hid, p->in, xb, p->in, wb + p->oW1, p->in, p->hid);
-    a.bias = w + p->ob1;
-    a.out_bf16 = h1;
-    rbp_status st = gemm<K_CONTIG, K_CONTIG, EPI_BIAS_RELU_BF16>(a, s);
+    rbp_status st;
+    if (keep_x) {
+        hipLaunchKernelGGL(expand_bits_kernel, dim3(blocks((int64_t)B * p->in, 256)), dim3(256), 0, s, syn, words,
+                           p->in, B, xb);
+        RBP_HIP_CHECK(hipGetLastError());
+        GemmArgs a = ga(B, p->hid, p->in, xb, p->in, wb + p->oW1, p->in, p->hid);
+        a.bias = w + p->ob1;
+        a.out_bf16 = h1;
+        st = gemm<K_CONTIG, K_CONTIG, EPI_BIAS_RELU_BF16>(a, s);
+    } else {
+        GemmArgs a = ga(B, p->hid, p->in, reinterpret_cast<const bf16*>(syn), words, wb + p->oW1, p->in, p->hid);
+        a.bias = w + p->ob1;
+        a.out_bf16 = h1;
+        st = gemm<BITS, K_CONTIG, EPI_BIAS_RELU_BF16>(a, s);
+    }
     if (st) return st;
+    GemmArgs a;
     a = ga(B, p->hid, p->hid, h1, p->hid, wb + p->oW2, p->hid, p->hid);
     a.bias = w + p->ob2;
     a.out_bf16 = h2;
@@ -393,7 +460,7 @@ rbp_status gradients(rbp_mlp* p, const uint32_t* syn, const uint32_t* tgt, const
     rbp_status st = ensure_workspace(p, B, true);
     if (st) return st;
     float* delta = p->delta.as<float>();
-    st = forward(p, syn, B, delta, s);
+    st = forward(p, syn, B, delta, s, true);
     if (st) return st;
     const int twords = (p->out + 31) / 32;
     const int64_t n3 = (int64_t)B * p->out;
@@ -541,7 +608,7 @@ rbp_status rbp_mlp_forward(rbp_mlp_t p, const uint32_t* syndromes, uint64_t shot
     const int words = (p->in + 31) / 32;
     for (uint64_t b0 = 0; b0 < shots; b0 += chunk) {
         const int B = (int)std::min<uint64_t>(chunk, shots - b0);
-        st = forward(p, syndromes + b0 * words, B, delta + b0 * (uint64_t)p->out, s);
+        st = forward(p, syndromes + b0 * words, B, delta + b0 * (uint64_t)p->out, s, false);
         if (st) return st;
     }
     return RBP_OK;
