@@ -13,11 +13,18 @@ names:
              clock) and the all-legs worst case (stopping_criterion = 1)
   learned    train the proposal network on decoder-generated pairs and compare
              plain Relay-BP, the proposal and the delta = 0 control
+  gamma      grid search of the relay memory-strength interval [gamma_min,
+             gamma_max] at one noise strength, all intervals on the same
+             syndromes (App. "more numerics", Table "relay gamma intervals")
+  sweep      LER against the noise strength p with one interval, and the
+             sub-threshold fit p^(d_circ/2) exp(c0 + c1 p + c2 p^2) with its
+             extrapolation (Sec. 6.1)
 All inputs are seeded and synthetic (see workloads.py).
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import time
 
@@ -143,6 +150,81 @@ def learned_exp(name: str, pairs: int, eval_shots: int, p_eval, p_lo: float, p_h
     return learned.train_and_evaluate(dem, cfg, evals, eval_shots, 777)
 
 
+# code distances d of Table 1 (Sec. 1); the phenomenological models have no
+# hook errors, so their effective distance is d itself
+CODE_DISTANCE = {"cc160": 10, "phen160": 10, "phen240": 12, "phen320": 14, "phen390": 16, "phen550": 18,
+                 "phen775": 22}
+
+
+def _failures(code, dem, priors, syn, obs, params) -> tuple:
+    corr, obsp, st = code.decode(priors, syn, params)
+    s = rbp.stats_to_numpy(st)
+    f = stats.block_failures(rbp.to_u32(obsp), rbp.to_u32(obs), s["converged"])
+    return int(f.sum()), float(s["iters"].mean()), int((s["converged"] == 0).sum())
+
+
+def gamma_grid(name: str, p: float, gmins, gmaxs, shots: int, seed: int = 41,
+               params: rbp.RelayParams | None = None) -> dict:
+    """Grid search of [gamma_min, gamma_max] for the lowest LER at noise p.
+
+    Every interval decodes the same sampled syndromes, so the comparison is
+    paired.  The chosen interval has the fewest failures; among equal counts
+    the one with fewer BP iterations per shot, then the earlier grid point
+    (gamma_min outer, gamma_max inner loop).  Intervals with gamma_min >
+    gamma_max are skipped.
+    """
+    base = params or rbp.RelayParams()
+    dem = workloads.workload(name)
+    code = rbp.Code.from_dem(dem)
+    priors = np.full(dem.N, p)
+    syn, obs, _ = code.sample(priors, shots, seed)
+    rows = []
+    for gmin in gmins:
+        for gmax in gmaxs:
+            if gmin > gmax:
+                continue
+            prm = dataclasses.replace(base, gamma_min=float(gmin), gamma_max=float(gmax))
+            f, it, nc = _failures(code, dem, priors, syn, obs, prm)
+            lo, hi = stats.clopper_pearson(f, shots)
+            rows.append({"gamma_min": float(gmin), "gamma_max": float(gmax), "failures": f, "ler": f / shots,
+                         "ci95": [lo, hi], "mean_iters": it, "nonconverged": nc})
+    best = min(range(len(rows)), key=lambda i: (rows[i]["failures"], rows[i]["mean_iters"], i))
+    return {"model": name, "p": p, "shots": shots, "seed": seed, "grid": rows, "best": rows[best]}
+
+
+def ler_sweep(name: str, ps, shots: int, seed: int = 51, params: rbp.RelayParams | None = None,
+              d_circ: float | None = None, p_fit_max: float = 4e-3, p_eval: float = 1e-3) -> dict:
+    """LER per qubit-round against p, and the sub-threshold fit (Sec. 6.1).
+
+    The fit uses the points with p <= p_fit_max and at least one failure,
+    weighted by their failure counts, with d_circ defaulting to the code
+    distance; the fitted curve is evaluated at p_eval.
+    """
+    params = params or rbp.RelayParams()
+    dem = workloads.workload(name)
+    code = rbp.Code.from_dem(dem)
+    d_circ = float(CODE_DISTANCE.get(name, 0) if d_circ is None else d_circ)
+    rows = []
+    for i, p in enumerate(ps):
+        priors = np.full(dem.N, p)
+        syn, obs, _ = code.sample(priors, shots, seed + i)
+        f, it, nc = _failures(code, dem, priors, syn, obs, params)
+        s = stats.ler_summary(f, shots, dem.rounds, dem.k)
+        lo, hi = s["ci95"]
+        rows.append({"p": float(p), **s, "per_qubit_round_ci95": [stats.per_round(lo, dem.rounds * dem.k),
+                                                                   stats.per_round(hi, dem.rounds * dem.k)],
+                     "mean_iters": it, "nonconverged": nc})
+    out = {"model": name, "rounds": dem.rounds, "k": dem.k, "shots_per_point": shots, "d_circ": d_circ,
+           "gamma": [params.gamma_min, params.gamma_max], "points": rows}
+    fit = [r for r in rows if r["p"] <= p_fit_max and r["failures"] > 0]
+    if len(fit) >= 3 and d_circ > 0:
+        c = stats.fit_ler([r["p"] for r in fit], [r["per_qubit_round"] for r in fit], d_circ,
+                          [r["failures"] for r in fit])
+        out["fit"] = {"c": list(c), "points": len(fit), "p_fit_max": p_fit_max,
+                      "per_qubit_round_at": {f"{p_eval:g}": float(stats.ler_model(p_eval, c, d_circ))}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("what")
@@ -152,6 +234,11 @@ def main():
     ap.add_argument("--pairs", type=int, default=1000000)
     ap.add_argument("--p-eval", default="1e-3")
     ap.add_argument("--p-range", default="5e-4,2e-3")
+    ap.add_argument("--p", type=float, default=1e-2)
+    ap.add_argument("--gmin", default="-0.3,-0.24,-0.15,-0.1,0.0")
+    ap.add_argument("--gmax", default="0.5,0.6,0.66,0.75")
+    ap.add_argument("--ps", default="4e-3,6e-3,8e-3,1e-2,1.2e-2,1.5e-2")
+    ap.add_argument("--p-fit-max", type=float, default=1e-2)
     a = ap.parse_args()
     torch.cuda.set_device(0)
     if a.what == "multi":
@@ -163,6 +250,11 @@ def main():
     elif a.what == "learned":
         lo, hi = (float(x) for x in a.p_range.split(","))
         r = learned_exp(a.model, a.pairs, a.shots, [float(x) for x in a.p_eval.split(",")], lo, hi)
+    elif a.what == "gamma":
+        r = gamma_grid(a.model, a.p, [float(x) for x in a.gmin.split(",")], [float(x) for x in a.gmax.split(",")],
+                       a.shots)
+    elif a.what == "sweep":
+        r = ler_sweep(a.model, [float(x) for x in a.ps.split(",")], a.shots, p_fit_max=a.p_fit_max)
     else:
         raise SystemExit(__doc__)
     print(json.dumps(r, default=float), flush=True)

@@ -2,7 +2,9 @@
 
 Block failure = any observable predicted wrong or no converged solution.
 Intervals are 95 % Clopper-Pearson (beta quantiles); the per-round rate is
-1 - (1 - p)^(1/T) and the per-qubit-round rate uses T*k.
+1 - (1 - p)^(1/T) and the per-qubit-round rate uses T*k.  Low-p extrapolation
+uses the phenomenological form p^(d_circ/2) exp(c0 + c1 p + c2 p^2) that the
+paper fits to its sub-threshold points (Sec. 6.1, Fig. "LER vs kd^2/n").
 """
 from __future__ import annotations
 
@@ -39,3 +41,34 @@ def percentiles(x: np.ndarray, qs=(50, 99, 99.9)) -> dict:
     out["mean"] = float(x.mean())
     out["max"] = float(x.max())
     return out
+
+
+def fit_ler(p, pbar, d_circ: float, failures=None):
+    """Fit pbar = p^(d_circ/2) * exp(c0 + c1 p + c2 p^2) (Sec. 6.1).
+
+    In logs the model is linear in (c0, c1, c2):
+        log pbar - (d_circ/2) log p = c0 + c1 p + c2 p^2,
+    so the fit is a weighted linear least-squares problem.  With failure counts
+    given, each point is weighted by its count (the inverse of the binomial
+    variance of log pbar, 1/failures, to first order); otherwise all weights are
+    1.  Points with pbar <= 0 (no failures) carry no information in logs and
+    are dropped.  Returns (c0, c1, c2); needs at least three usable points.
+    """
+    p = np.asarray(p, dtype=np.float64)
+    pbar = np.asarray(pbar, dtype=np.float64)
+    w = np.ones_like(p) if failures is None else np.asarray(failures, dtype=np.float64)
+    keep = (pbar > 0) & (p > 0) & (w > 0)
+    if int(keep.sum()) < 3:
+        raise ValueError("the LER fit needs at least three points with failures")
+    p, pbar, w = p[keep], pbar[keep], w[keep]
+    y = np.log(pbar) - 0.5 * d_circ * np.log(p)
+    A = np.stack([np.ones_like(p), p, p * p], axis=1)
+    sw = np.sqrt(w)
+    c, *_ = np.linalg.lstsq(A * sw[:, None], y * sw, rcond=None)
+    return float(c[0]), float(c[1]), float(c[2])
+
+
+def ler_model(p, c, d_circ: float):
+    """pbar(p) = p^(d_circ/2) exp(c0 + c1 p + c2 p^2) for fitted c = (c0, c1, c2)."""
+    p = np.asarray(p, dtype=np.float64)
+    return p ** (0.5 * d_circ) * np.exp(c[0] + c[1] * p + c[2] * p * p)
