@@ -7,6 +7,10 @@ imports nothing from the product package (inputs arrive as plain numpy arrays).
 * ``rbp_oracle.c`` -- Philox4x32-10 sampler, GF(2) syndromes, FP32 Relay-BP
   (paper Sec. 6.1: flooding min-sum with memory, sequential relay legs,
   lowest-weight of ``stop_nconv`` solutions, single-precision messages).
+* ``spa_oracle.c`` -- BPSK-AWGN channel (Philox4x32-10 + Box-Muller, double)
+  and flooding sum-product BP with the phi-domain check update, LLRs and
+  variable-to-check messages clipped to +-llr_max, single-precision messages
+  (the paper's classical benchmark of its ZSZ-2BGA codes).
 * ``stats`` -- block logical error rate, Clopper-Pearson interval and per-round
   rate (Sec. 6.1, Fig. "numerics" caption).
 * ``mlp_ref`` -- float64 reference of the learned-proposal network.
@@ -22,6 +26,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rbp_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "spa_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -30,7 +35,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no fast-math, no FP contraction)."""
     if force or not os.path.exists(_LIB):
         cmd = ["gcc", "-O2", "-std=c11", "-D_POSIX_C_SOURCE=199309L", "-ffp-contract=off", "-fno-fast-math",
-               "-fPIC", "-shared", "-pthread", _SRC, "-o", _LIB + ".tmp", "-lm"]
+               "-fPIC", "-shared", "-pthread", *_SRCS, "-o", _LIB + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -39,7 +44,7 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
             build()
         L = ctypes.CDLL(_LIB)
         P = ctypes.POINTER
@@ -65,6 +70,14 @@ def lib():
         L.orc_bp_marginals.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, i32p, f64p, u32p, ctypes.c_float,
                                        ctypes.c_int32, f32p]
         L.orc_bp_marginals.restype = ctypes.c_int
+        L.orc_spa_phi.argtypes = [ctypes.c_float]
+        L.orc_spa_phi.restype = ctypes.c_float
+        L.orc_awgn.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                               f64p]
+        L.orc_spa_decode.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, i32p, f32p, ctypes.c_uint64,
+                                     ctypes.c_int32, ctypes.c_float, ctypes.c_int32, u8p, u8p, i32p, f32p,
+                                     ctypes.c_int32]
+        L.orc_spa_decode.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -233,4 +246,44 @@ def bp_marginals(g: Graph, priors: np.ndarray, syndrome_words: np.ndarray, gamma
                                 _p(pr, ctypes.c_double), _p(syn, ctypes.c_uint32), gamma, T, _p(out, ctypes.c_float))
     if rc:
         raise RuntimeError(f"orc_bp_marginals failed: {rc}")
+    return out
+
+
+# ------------------------------------------------------- sum-product BP (AWGN)
+def spa_phi(x: float) -> float:
+    """phi(x) = -ln tanh(x/2) in single precision, as the oracle decoder evaluates it."""
+    return float(lib().orc_spa_phi(float(x)))
+
+
+def awgn(N: int, shots: int, sigma: float, seed: int, shot_offset: int = 0) -> np.ndarray:
+    """Channel LLRs 2y/sigma^2 of the all-zero BPSK codeword, float64 [shots][N]."""
+    out = np.zeros((shots, N), dtype=np.float64)
+    lib().orc_awgn(N, shots, sigma, seed, shot_offset, _p(out, ctypes.c_double))
+    return out
+
+
+def spa_decode(H: np.ndarray, llr: np.ndarray, max_iterations: int = 100, llr_max: float = 20.0, stop: bool = True,
+               marginals: bool = False, nthreads: int | None = None) -> dict:
+    """Sum-product BP on channel LLRs float32 [shots][N]: hard decisions uint8
+    [shots][N], converged, iterations (and the final marginals)."""
+    H = np.asarray(H, dtype=np.uint8)
+    M, N = H.shape
+    cp, ri = _csc(H)
+    L = np.ascontiguousarray(llr, dtype=np.float32)
+    shots = L.shape[0]
+    assert L.shape == (shots, N)
+    bits = np.zeros((shots, N), dtype=np.uint8)
+    conv = np.zeros(shots, dtype=np.uint8)
+    iters = np.zeros(shots, dtype=np.int32)
+    marg = np.zeros((shots, N), dtype=np.float32) if marginals else None
+    nt = nthreads or os.cpu_count() or 1
+    rc = lib().orc_spa_decode(M, N, _p(cp, ctypes.c_int32), _p(ri, ctypes.c_int32), _p(L, ctypes.c_float), shots,
+                              max_iterations, llr_max, 1 if stop else 0, _p(bits, ctypes.c_uint8),
+                              _p(conv, ctypes.c_uint8), _p(iters, ctypes.c_int32),
+                              _p(marg, ctypes.c_float) if marg is not None else None, nt)
+    if rc:
+        raise RuntimeError(f"orc_spa_decode failed: {rc}")
+    out = dict(bits=bits, converged=conv, iters=iters)
+    if marg is not None:
+        out["marginals"] = marg
     return out

@@ -9,6 +9,7 @@ paper fits to its sub-threshold points (Sec. 6.1, Fig. "LER vs kd^2/n").
 from __future__ import annotations
 
 import numpy as np
+from scipy.optimize import brentq
 from scipy.stats import beta
 
 
@@ -72,3 +73,22 @@ def ler_model(p, c, d_circ: float):
     """pbar(p) = p^(d_circ/2) exp(c0 + c1 p + c2 p^2) for fitted c = (c0, c1, c2)."""
     p = np.asarray(p, dtype=np.float64)
     return p ** (0.5 * d_circ) * np.exp(c[0] + c[1] * p + c[2] * p * p)
+
+
+def bpsk_awgn_capacity(sigma: float, nodes: int = 200) -> float:
+    """Capacity (bits per channel use) of BPSK over AWGN with noise sigma:
+    1 - E[log2(1 + exp(-L))], L ~ N(2/sigma^2, 4/sigma^2) the LLR of a received
+    +1 (App. "classical channel coding", eq. "bpsk awgn capacity"), by
+    Gauss-Hermite quadrature."""
+    x, w = np.polynomial.hermite_e.hermegauss(nodes)
+    mu, sd = 2.0 / sigma ** 2, 2.0 / sigma
+    L = mu + sd * x
+    return float(1.0 - np.sum(w * np.logaddexp(0.0, -L)) / np.sqrt(2.0 * np.pi) / np.log(2.0))
+
+
+def shannon_limit_db(rate: float) -> float:
+    """E_b/N_0 (dB) at which the BPSK-AWGN capacity equals the code rate."""
+    def gap(db):
+        sigma = np.sqrt(1.0 / (2.0 * rate * 10.0 ** (db / 10.0)))
+        return bpsk_awgn_capacity(sigma) - rate
+    return float(brentq(gap, -10.0, 20.0, xtol=1e-10))

@@ -75,6 +75,16 @@ ZSZ_LP_NK: Dict[str, Tuple[int, int]] = {
 }
 
 
+# Classical seed codes H_left = (L[a] L[b]), H_right = (R[c] R[d]) of each
+# candidate (Sec. 2.3, eq. "H_left, H_right"; Table "classical ZSZ code
+# params"): name -> (ZSZ-LP code, n, k, d or its upper bound, Tanner girth).
+ZSZ_2BGA: Dict[str, Tuple[str, int, int, int, int]] = {
+    "ZSZ-2BGA-64": ("ZSZ-LP-160", 64, 32, 10, 6), "ZSZ-2BGA-96": ("ZSZ-LP-240", 96, 48, 12, 6),
+    "ZSZ-2BGA-128": ("ZSZ-LP-320", 128, 64, 14, 6), "ZSZ-2BGA-156": ("ZSZ-LP-390", 156, 78, 16, 6),
+    "ZSZ-2BGA-220": ("ZSZ-LP-550", 220, 110, 18, 8), "ZSZ-2BGA-310": ("ZSZ-LP-775", 310, 155, 22, 8),
+}
+
+
 # ---------------------------------------------------------------------------
 # ZSZ group (Sec. 2.2)
 # ---------------------------------------------------------------------------
@@ -389,6 +399,33 @@ def phenomenological_dem(code: CSSCode, rounds: int, p: float, q_meas: float | N
 # ---------------------------------------------------------------------------
 # Named workloads (sizes follow the configurations the benchmarks run)
 # ---------------------------------------------------------------------------
+def zsz_2bga(name: str, side: str = "left") -> np.ndarray:
+    """Parity-check matrix (l x 2l, uint8) of a classical ZSZ-2BGA code:
+    (L[a] L[b]) for the left code, (R[c] R[d]) for the right one (Sec. 2.3)."""
+    lp = ZSZ_2BGA[name][0]
+    l1, l2, q, a, b, c, d = ZSZ_LP_CODES[lp]
+    G = ZSZGroup(l1, l2, q)
+    if side == "left":
+        return np.concatenate([G.L(a), G.L(b)], axis=1)
+    if side == "right":
+        return np.concatenate([G.R(c), G.R(d)], axis=1)
+    raise ValueError("side is 'left' or 'right'")
+
+
+def awgn_sigma(ebn0_db: float, rate: float) -> float:
+    """Noise standard deviation of unit-energy BPSK at E_b/N_0 (dB) and code
+    rate R: E_b/N_0 = 1 / (2 R sigma^2) (App. "classical channel coding")."""
+    return float(np.sqrt(1.0 / (2.0 * rate * 10.0 ** (ebn0_db / 10.0))))
+
+
+def awgn_llrs(N: int, shots: int, sigma: float, seed: int) -> np.ndarray:
+    """Seeded channel LLRs 2y/sigma^2 of the all-zero codeword, y = 1 + sigma z
+    with z standard normal (numpy's generator), float32 [shots][N]."""
+    rng = np.random.default_rng(seed)
+    y = 1.0 + sigma * rng.standard_normal((shots, N))
+    return (2.0 * y / (sigma * sigma)).astype(np.float32)
+
+
 def workload(name: str) -> DEM:
     """Named DEMs.
 
