@@ -193,6 +193,50 @@ rbp_status rbp_mlp_num_params(rbp_mlp_t mlp, int64_t* n);
 rbp_status rbp_mlp_get_params(rbp_mlp_t mlp, float* host_out);
 rbp_status rbp_mlp_set_params(rbp_mlp_t mlp, const float* host_in);
 
+/* ---- classical channel coding: sum-product BP over BPSK-AWGN ------------ *
+ * The paper's classical benchmark of its ZSZ-2BGA codes (numerics appendix,
+ * "classical channel coding", with eq. "bpsk awgn capacity"): the all-zero
+ * codeword is sent as +1 symbols over an additive white Gaussian noise
+ * channel, y_j = 1 + sigma z_j, and decoded by flooding sum-product BP with the
+ * phi-domain ("boxplus-phi") check update and single-precision messages.  A
+ * handle for this use is made by rbp_code_create from the parity-check matrix
+ * with k = 0; rows of degree 2..32 (0 allowed). */
+
+/* Channel LLRs of the all-zero codeword: llr_dev float[shots][N] =
+ * 2 y / sigma^2 with y = 1 + sigma z (log P(bit 0 | y) / P(bit 1 | y)).
+ * z_j comes from Philox4x32-10 (key = seed, counter = (j / 4, shot lo, shot hi,
+ * 2)) by the Box-Muller transform: words 2h and 2h+1 give
+ * u1 = ((w >> 8) + 1) 2^-24 in (0, 1] and u2 = (w >> 8) 2^-24, and
+ * z_{4q+2h} = sqrt(-2 ln u1) cos(2 pi u2), z_{4q+2h+1} = sqrt(-2 ln u1) sin(2 pi u2),
+ * evaluated in single precision.  Shot s uses counter index shot_offset + s,
+ * so ranges of shots can be drawn independently.  sigma > 0. */
+rbp_status rbp_sample_awgn(rbp_code_t code, uint64_t shots, double sigma, uint64_t seed, uint64_t shot_offset,
+                           float* llr_dev, void* stream);
+
+typedef struct {
+    int32_t max_iterations; /* num_iter (paper: 100), >= 1 */
+    float llr_max;          /* clipping of the channel LLRs and of the variable-to-check messages (paper: 20), > 0 */
+    int32_t stop;           /* 1: stop after the first iteration whose hard decision satisfies every check;
+                               0: always run max_iterations */
+    int32_t waves_per_shot; /* wavefronts sharing one shot, 1..16; 0 = library default */
+} rbp_spa_params;
+
+/* Sum-product BP on channel LLRs llr_dev float[shots][N].  With L_j =
+ * clip(llr_j, +-llr_max) and nu(0) = L_j on every edge, one iteration is
+ *   mu_{i->j} = prod_{j' != j} s(nu_{j'->i}) * phi(sum_{j' != j} phi(|nu_{j'->i}|)),
+ *   phi(x) = -ln tanh(x/2), the sum taken in ascending column order, s(x) = -1 iff x < 0;
+ *   M_j = L_j + sum_i mu_{i->j} (ascending check order);
+ *   nu_{j->i} = clip(M_j - mu_{i->j}, +-llr_max);  c_j = [M_j < 0].
+ * Outputs (device, may be NULL except bits_dev): bits_dev uint32[shots][ceil(N/32)]
+ * = c when decoding stops; marginals_dev float[shots][N] = M then; stats_dev
+ * rbp_shot_stats[shots] with converged = (H c = 0), iters, path = 0 if c is the
+ * zero word and 1 otherwise, t_start/t_end; counts_dev uint64[3] +=
+ * {shots with c != 0 (block errors when the zero word was sent), shots with
+ * c != 0 and H c = 0 (undetected errors), shots with H c != 0}. */
+rbp_status rbp_decode_spa(rbp_code_t code, const float* llr_dev, uint64_t shots, const rbp_spa_params* params,
+                          uint32_t* bits_dev, float* marginals_dev, rbp_shot_stats* stats_dev,
+                          unsigned long long* counts_dev, void* stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* rbp_last_error(void);
 

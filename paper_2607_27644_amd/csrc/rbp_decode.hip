@@ -1350,7 +1350,7 @@ rbp_status rbp_code_destroy(rbp_code_t c) {
     for (DevBuf* b : {&c->row_ptr, &c->col_idx, &c->col_ptr, &c->csc_row, &c->rgrp, &c->rposp, &c->rposw, &c->rord, &c->vgrp,
                       &c->vord, &c->vdeg, &c->scheck, &c->scsc, &c->orow_ptr, &c->ocol_idx, &c->ocol_ptr,
                       &c->orow_idx, &c->thr, &c->lam, &c->lamp, &c->m1, &c->gtab, &c->lg, &c->queue, &c->gstate,
-                      &c->trace_hit})
+                      &c->trace_hit, &c->spa_queue})
         b->release();
     delete c;
     return RBP_OK;

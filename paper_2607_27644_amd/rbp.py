@@ -35,6 +35,24 @@ class RelayParamsC(ctypes.Structure):
                 ("gamma_seed", ctypes.c_uint64)]
 
 
+class SpaParamsC(ctypes.Structure):
+    _fields_ = [("max_iterations", ctypes.c_int32), ("llr_max", ctypes.c_float), ("stop", ctypes.c_int32),
+                ("waves_per_shot", ctypes.c_int32)]
+
+
+@dataclasses.dataclass
+class SpaParams:
+    """Sum-product BP settings of the classical AWGN benchmark (num_iter 100,
+    llr_max 20, stop at the first codeword)."""
+    max_iterations: int = 100
+    llr_max: float = 20.0
+    stop: bool = True
+    waves_per_shot: int = 0
+
+    def c(self) -> SpaParamsC:
+        return SpaParamsC(self.max_iterations, self.llr_max, 1 if self.stop else 0, self.waves_per_shot)
+
+
 class LaunchConfigC(ctypes.Structure):
     _fields_ = [("waves_per_shot", ctypes.c_int32), ("state", ctypes.c_int32), ("max_slots", ctypes.c_int32)]
 
@@ -95,6 +113,8 @@ def lib():
         "rbp_count_failures": [vp, vp, vp, u64, i32, vp, vp],
         "rbp_mlp_get_params": [vp, vp],
         "rbp_mlp_set_params": [vp, vp],
+        "rbp_sample_awgn": [vp, u64, ctypes.c_double, u64, u64, vp, vp],
+        "rbp_decode_spa": [vp, vp, u64, P(SpaParamsC), vp, vp, vp, vp, vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -227,6 +247,38 @@ class Code:
         pr = _f64(priors)
         check(lib().rbp_code_llr(self.h, pr.ctypes.data, _ptr(out), _stream(stream)))
         return out
+
+    # -- classical channel coding (BPSK-AWGN, sum-product BP) ---------------
+    def sample_awgn(self, shots: int, sigma: float, seed: int, shot_offset: int = 0, stream=None,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Channel LLRs of the all-zero codeword, float32 [shots][N] (rbp_sample_awgn)."""
+        if out is None:
+            out = torch.empty((shots, self.N), dtype=torch.float32, device="cuda")
+        assert out.dtype == torch.float32 and out.shape == (shots, self.N) and out.is_contiguous()
+        check(lib().rbp_sample_awgn(self.h, shots, float(sigma), seed, shot_offset, _ptr(out), _stream(stream)))
+        return out
+
+    def decode_spa(self, llr: torch.Tensor, params: Optional[SpaParams] = None, marginals: bool = False,
+                   stats: bool = True, counts: Optional[torch.Tensor] = None, stream=None, out=None):
+        """Sum-product BP (rbp_decode_spa) -> (bits, marginals or None, stats or None).
+        counts (int64[3], device) accumulates block errors, undetected errors and
+        non-converged shots with respect to the all-zero codeword."""
+        params = params or SpaParams()
+        shots = llr.shape[0]
+        assert llr.dtype == torch.float32 and llr.is_contiguous() and llr.shape == (shots, self.N)
+        dev = llr.device
+        if out is None:
+            bits = torch.empty((shots, words(self.N)), dtype=torch.int32, device=dev)
+            marg = torch.empty((shots, self.N), dtype=torch.float32, device=dev) if marginals else None
+            st = torch.empty((shots, 32), dtype=torch.uint8, device=dev) if stats else None
+        else:
+            bits, marg, st = out
+        if counts is not None:
+            assert counts.dtype == torch.int64 and counts.numel() >= 3 and counts.is_contiguous()
+        prm = params.c()
+        check(lib().rbp_decode_spa(self.h, _ptr(llr), shots, ctypes.byref(prm), _ptr(bits), _ptr(marg), _ptr(st),
+                                   _ptr(counts), _stream(stream)))
+        return bits, marg, st
 
     def set_launch_config(self, waves_per_shot: int = 0, state: int = 0, max_slots: int = 0):
         cfg = LaunchConfigC(waves_per_shot, state, max_slots)
