@@ -19,6 +19,10 @@ names:
   sweep      LER against the noise strength p with one interval, and the
              sub-threshold fit p^(d_circ/2) exp(c0 + c1 p + c2 p^2) with its
              extrapolation (Sec. 6.1)
+  awgn       block error rate of the classical ZSZ-2BGA codes over BPSK-AWGN
+             against E_b/N_0, sum-product BP (numerics appendix, "classical
+             channel coding"), with the decoder's throughput and the Shannon
+             limit of rate 1/2
 All inputs are seeded and synthetic (see workloads.py).
 """
 from __future__ import annotations
@@ -225,6 +229,60 @@ def ler_sweep(name: str, ps, shots: int, seed: int = 51, params: rbp.RelayParams
     return out
 
 
+def awgn_fer(names, ebn0s, max_frames: int = 10 ** 7, min_errors: int = 100, chunk: int = 10 ** 6,
+             seed: int = 61, params: rbp.SpaParams | None = None, side: str = "left") -> dict:
+    """Frame (block) error rate of the all-zero codeword over BPSK-AWGN.
+
+    Frames are drawn in chunks (shot offsets continue across chunks, so the
+    frames are those of one seeded stream) until min_errors block errors or
+    max_frames frames.  A block error is a decoded word other than the
+    all-zero one; an undetected error is such a word that satisfies every
+    check.  Throughput counts decode launches only, and separately the whole
+    sample + decode loop.
+    """
+    params = params or rbp.SpaParams()
+    out = {"shannon_limit_db": stats.shannon_limit_db(0.5), "params": dataclasses.asdict(params), "codes": {}}
+    for name in names:
+        H = workloads.zsz_2bga(name, side)
+        n = H.shape[1]
+        k = n - workloads.gf2_rank(H)
+        rate = k / n
+        code = rbp.Code(H, np.zeros((0, n), dtype=np.uint8))
+        dev = torch.device("cuda")
+        cap = min(chunk, max_frames)
+        llr = torch.empty((cap, n), dtype=torch.float32, device=dev)
+        bits = torch.empty((cap, rbp.words(n)), dtype=torch.int32, device=dev)
+        st = torch.empty((cap, 32), dtype=torch.uint8, device=dev)
+        rows = []
+        for ebn0 in ebn0s:
+            sigma = workloads.awgn_sigma(ebn0, rate)
+            counts = torch.zeros(3, dtype=torch.int64, device=dev)
+            iters = torch.zeros(1, dtype=torch.int64, device=dev)
+            frames, dec_ms = 0, 0.0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            while frames < max_frames and int(counts[0].item()) < min_errors:
+                m = min(cap, max_frames - frames)
+                code.sample_awgn(m, sigma, seed, shot_offset=frames, out=llr[:m])
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                code.decode_spa(llr[:m], params, counts=counts, out=(bits[:m], None, st[:m]))
+                e1.record()
+                iters += st[:m].view(torch.int32)[:, 2].sum()
+                torch.cuda.synchronize()
+                dec_ms += e0.elapsed_time(e1)
+                frames += m
+            wall = time.perf_counter() - t0
+            c = counts.cpu().numpy()
+            lo, hi = stats.clopper_pearson(int(c[0]), frames)
+            rows.append({"ebn0_db": ebn0, "sigma": sigma, "frames": frames, "block_errors": int(c[0]),
+                         "undetected": int(c[1]), "nonconverged": int(c[2]), "fer": c[0] / frames,
+                         "ci95": [lo, hi], "mean_iters": float(iters.item()) / frames,
+                         "decode_frames_per_s": frames / (dec_ms * 1e-3), "frames_per_s": frames / wall})
+        out["codes"][name] = {"n": n, "k": k, "side": side, "points": rows}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("what")
@@ -239,6 +297,10 @@ def main():
     ap.add_argument("--gmax", default="0.5,0.6,0.66,0.75")
     ap.add_argument("--ps", default="4e-3,6e-3,8e-3,1e-2,1.2e-2,1.5e-2")
     ap.add_argument("--p-fit-max", type=float, default=1e-2)
+    ap.add_argument("--codes", default="ZSZ-2BGA-64,ZSZ-2BGA-96,ZSZ-2BGA-128,ZSZ-2BGA-156,ZSZ-2BGA-220,ZSZ-2BGA-310")
+    ap.add_argument("--ebn0", default="0.5,1.0,1.25,1.5,2.0,2.5,3.0,3.5,4.0")
+    ap.add_argument("--max-frames", type=int, default=10 ** 7)
+    ap.add_argument("--min-errors", type=int, default=100)
     a = ap.parse_args()
     torch.cuda.set_device(0)
     if a.what == "multi":
@@ -253,6 +315,8 @@ def main():
     elif a.what == "gamma":
         r = gamma_grid(a.model, a.p, [float(x) for x in a.gmin.split(",")], [float(x) for x in a.gmax.split(",")],
                        a.shots)
+    elif a.what == "awgn":
+        r = awgn_fer(a.codes.split(","), [float(x) for x in a.ebn0.split(",")], a.max_frames, a.min_errors)
     elif a.what == "sweep":
         r = ler_sweep(a.model, [float(x) for x in a.ps.split(",")], a.shots, p_fit_max=a.p_fit_max)
     else:

@@ -150,3 +150,18 @@ def test_launch_shape_and_edge_cases(rbp):
         code.decode_spa(L, rbp.SpaParams(max_iterations=0))
     with pytest.raises(rbp.RbpError):
         code.decode_spa(L, rbp.SpaParams(llr_max=-1.0))
+
+
+def test_fer_experiment_chunking(rbp):
+    """The frame stream is one seeded stream: chunking does not change it, and
+    the frame error rate falls with E_b/N_0."""
+    from paper_2607_27644_amd import experiments as E
+    a = E.awgn_fer(["ZSZ-2BGA-64"], [1.0, 3.0], max_frames=20000, min_errors=10 ** 9, chunk=7000)
+    b = E.awgn_fer(["ZSZ-2BGA-64"], [1.0, 3.0], max_frames=20000, min_errors=10 ** 9, chunk=20000)
+    pa, pb = a["codes"]["ZSZ-2BGA-64"]["points"], b["codes"]["ZSZ-2BGA-64"]["points"]
+    for x, y in zip(pa, pb):
+        assert x["frames"] == y["frames"] == 20000
+        for key in ("block_errors", "undetected", "nonconverged", "mean_iters"):
+            assert x[key] == y[key], key
+    assert pa[0]["fer"] > 3 * pa[1]["fer"] > 0
+    assert abs(a["shannon_limit_db"] - 0.187) < 0.002
