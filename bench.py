@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--train-pairs", type=int, default=1_000_000)
+    ap.add_argument("--no-awgn", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates rocprof byte counters)")
     return ap.parse_args()
@@ -239,6 +240,19 @@ def main():
         paths["proposal_zero"]["note"] = "control: the same proposal leg with delta = 0 (no network)"
         out["learned"] = paths["learned"]
         out["proposal_zero"] = paths["proposal_zero"]
+
+    if not args.no_awgn:
+        # the classical benchmark beside the headline: the [310,155] ZSZ-2BGA code
+        # over BPSK-AWGN at 2.5 dB, sum-product BP (num_iter 100, llr_max 20)
+        from paper_2607_27644_amd import experiments
+        r = experiments.awgn_fer(["ZSZ-2BGA-310"], [2.5], max_frames=4_000_000, min_errors=10 ** 12,
+                                 chunk=1_000_000)
+        pt = r["codes"]["ZSZ-2BGA-310"]["points"][0]
+        out["awgn"] = {"code": "ZSZ-2BGA-310 [310,155]", "ebn0_db": pt["ebn0_db"], "frames": pt["frames"],
+                       "fer": pt["fer"], "ci95": pt["ci95"], "undetected": pt["undetected"],
+                       "mean_iters": pt["mean_iters"], "decode_frames_per_s": pt["decode_frames_per_s"],
+                       "frames_per_s_with_sampling": pt["frames_per_s"],
+                       "shannon_limit_db": r["shannon_limit_db"]}
 
     if not args.no_sequential:
         # the paper's latency mode: one shot per decode call, host clock around each
