@@ -75,7 +75,7 @@ def cpu_baseline(dem, shots_total: int, seed: int, params, target_s: float):
     def run(n):
         t0 = time.perf_counter()
         syn, obs, _ = oracle.sample(g, dem.priors, n, seed)
-        r = oracle.decode(g, dem.priors, syn, op, nthreads=threads)
+        r = oracle.decode(g, dem.priors, syn, op, nthreads=threads, timing=True)
         return time.perf_counter() - t0, r
 
     dt, _ = run(2000)
@@ -85,7 +85,21 @@ def cpu_baseline(dem, shots_total: int, seed: int, params, target_s: float):
     return {"value": n / dt, "unit": "shots/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} shots of the same model and seed (the first {min(n, shots_total)} are the first "
                       f"timed step's shots): oracle sampling + Relay-BP decode on {threads} threads, {dt:.1f} s",
-            "mean_iters_per_shot": float(np.mean(r["iters"]))}
+            "mean_iters_per_shot": float(np.mean(r["iters"])),
+            # each shot runs on one thread: its decode time is single-core latency
+            "single_core_latency_us": {"p50": float(np.percentile(r["seconds"], 50) * 1e6),
+                                       "p99": float(np.percentile(r["seconds"], 99) * 1e6)},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
