@@ -193,6 +193,34 @@ rbp_status rbp_mlp_num_params(rbp_mlp_t mlp, int64_t* n);
 rbp_status rbp_mlp_get_params(rbp_mlp_t mlp, float* host_out);
 rbp_status rbp_mlp_set_params(rbp_mlp_t mlp, const float* host_in);
 
+/* ---- sliding-window decoding --------------------------------------------- *
+ * The paper's latency discussion (Sec. 6.1) argues for sliding-window decoding
+ * with a commit region: a window decodes the syndrome of w consecutive rounds
+ * and commits the mechanisms that start in its first c rounds; their effect is
+ * removed from the running syndrome before the next window, c rounds later.
+ * Windows are decoded with rbp_decode on handles of the window matrices; these
+ * two calls move the bits in between. */
+
+/* dst_dev[s] (dst_words words) = bits [bit_offset, bit_offset + nbits) of
+ * src_dev[s] (src_words words), shifted to bit 0, LSB-first, zero above nbits.
+ * Requires nbits <= 32 dst_words and bit_offset + nbits <= 32 src_words. */
+rbp_status rbp_bits_extract(const uint32_t* src_dev, int32_t src_words, uint64_t shots, int64_t bit_offset,
+                            int32_t nbits, uint32_t* dst_dev, int32_t dst_words, void* stream);
+
+/* Commit a window's decoded mechanisms to the full model `code`.  For each shot
+ * s and each set bit j < n_win of win_corr_dev[s] (win_words words) whose
+ * cmap_dev[j] = J is a column of `code` (entries outside [0, N) mean "not
+ * committed"): set bit J of corrections_dev[s] (uint32[shots][ceil(N/32)]),
+ * XOR column J of H into syndromes_dev[s] (uint32[shots][ceil(M/32)]) and
+ * column J of O into obs_pred_dev[s] (uint32[shots][ceil(k/32)]; may be NULL
+ * when k = 0).  acc_stats_dev (may be NULL) accumulates the windows' decode
+ * statistics: first != 0 copies win_stats_dev[s]; later windows AND
+ * `converged`, take the minimum `nconv`, add `legs` and `iters` and set t_end. */
+rbp_status rbp_window_commit(rbp_code_t code, uint64_t shots, const uint32_t* win_corr_dev, int32_t win_words,
+                             const int32_t* cmap_dev, int32_t n_win, uint32_t* syndromes_dev, uint32_t* obs_pred_dev,
+                             uint32_t* corrections_dev, const rbp_shot_stats* win_stats_dev,
+                             rbp_shot_stats* acc_stats_dev, int32_t first, void* stream);
+
 /* ---- classical channel coding: sum-product BP over BPSK-AWGN ------------ *
  * The paper's classical benchmark of its ZSZ-2BGA codes (numerics appendix,
  * "classical channel coding", with eq. "bpsk awgn capacity"): the all-zero

@@ -115,6 +115,8 @@ def lib():
         "rbp_mlp_set_params": [vp, vp],
         "rbp_sample_awgn": [vp, u64, ctypes.c_double, u64, u64, vp, vp],
         "rbp_decode_spa": [vp, vp, u64, P(SpaParamsC), vp, vp, vp, vp, vp],
+        "rbp_bits_extract": [vp, i32, u64, i64, i32, vp, i32, vp],
+        "rbp_window_commit": [vp, u64, vp, i32, vp, i32, vp, vp, vp, vp, vp, i32, vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -312,6 +314,26 @@ def count_failures(obs_pred: torch.Tensor, obs: torch.Tensor, stats: torch.Tenso
     """count (int64[1] on the device) += block failures of the batch (GPU reduction)."""
     check(lib().rbp_count_failures(_ptr(obs_pred), _ptr(obs), _ptr(stats), obs.shape[0], obs.shape[1], _ptr(count),
                                    _stream(stream)))
+
+
+def bits_extract(src: torch.Tensor, bit_offset: int, nbits: int, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """out[s] = bits [bit_offset, bit_offset + nbits) of src[s] (rbp_bits_extract)."""
+    assert src.dtype == torch.int32 and out.dtype == torch.int32 and src.is_contiguous() and out.is_contiguous()
+    check(lib().rbp_bits_extract(_ptr(src), src.shape[1], src.shape[0], bit_offset, nbits, _ptr(out), out.shape[1],
+                                 _stream(stream)))
+    return out
+
+
+def window_commit(code: "Code", win_corr: torch.Tensor, cmap: torch.Tensor, n_win: int, syndromes: torch.Tensor,
+                  obs_pred: torch.Tensor, corrections: torch.Tensor, win_stats: Optional[torch.Tensor] = None,
+                  acc_stats: Optional[torch.Tensor] = None, first: bool = False, stream=None):
+    """Commit a window's decoded mechanisms to the full model (rbp_window_commit)."""
+    shots = win_corr.shape[0]
+    for t in (win_corr, cmap, syndromes, obs_pred, corrections):
+        assert t.dtype == torch.int32 and t.is_contiguous()
+    check(lib().rbp_window_commit(code.h, shots, _ptr(win_corr), win_corr.shape[1], _ptr(cmap), n_win,
+                                  _ptr(syndromes), _ptr(obs_pred), _ptr(corrections), _ptr(win_stats),
+                                  _ptr(acc_stats), 1 if first else 0, _stream(stream)))
 
 
 def stats_to_numpy(st: torch.Tensor) -> np.ndarray:

@@ -1,0 +1,110 @@
+"""GPU sliding-window decoding against the oracle's windowing.
+
+Bit moves are exact; each window decode is the parity-tested Relay-BP kernel,
+so windowed corrections, predicted observables and convergence flags must
+match the oracle's windowed decode on >= 99.9 % of shots (they are expected to
+be identical), and one window over every round must equal the global decode.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from oracle import window as owin  # noqa: E402
+from paper_2607_27644_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_27644_amd import rbp, window
+    return rbp, window
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def test_bits_extract(mods):
+    rbp, _ = mods
+    rng = np.random.default_rng(1)
+    src = rng.integers(0, 2 ** 32, size=(333, 7), dtype=np.uint64).astype(np.uint32)
+    bits = np.unpackbits(src.view(np.uint8), axis=1, bitorder="little")
+    t = torch.from_numpy(src.view(np.int32)).cuda()
+    for off, nb in [(0, 224), (5, 64), (37, 100), (63, 1), (96, 128), (200, 24), (0, 0)]:
+        dw = max((nb + 31) // 32, 1)
+        out = torch.full((333, dw), -1, dtype=torch.int32, device="cuda")
+        rbp.bits_extract(t, off, nb, out)
+        ref = np.zeros((333, dw * 32), dtype=np.uint8)
+        ref[:, :nb] = bits[:, off:off + nb]
+        want = np.packbits(ref, axis=1, bitorder="little").view(np.uint32).reshape(333, dw)
+        np.testing.assert_array_equal(u32(out), want, err_msg=f"{off} {nb}")
+    with pytest.raises(rbp.RbpError):
+        rbp.bits_extract(t, 200, 40, torch.empty((333, 2), dtype=torch.int32, device="cuda"))
+
+
+def test_window_commit(mods):
+    rbp, _ = mods
+    dem = W.phenomenological_dem(W.zsz_lp("ZSZ-LP-60"), 4, 0.02)
+    code = rbp.Code.from_dem(dem)
+    rng = np.random.default_rng(2)
+    shots, n_win = 257, 70
+    ew = (rng.random((shots, n_win)) < 0.05).astype(np.uint8)
+    cmap = np.where(rng.random(n_win) < 0.7, rng.choice(dem.N, n_win, replace=False), -1).astype(np.int32)
+    syn0 = rng.integers(0, 2 ** 32, size=(shots, (dem.M + 31) // 32), dtype=np.uint64).astype(np.uint32)
+    syn0[:, -1] &= np.uint32((1 << (dem.M % 32)) - 1) if dem.M % 32 else np.uint32(0xFFFFFFFF)
+    pack = owin._pack
+    tsyn = torch.from_numpy(syn0.view(np.int32).copy()).cuda()
+    tobs = torch.zeros((shots, (dem.k + 31) // 32), dtype=torch.int32, device="cuda")
+    tcorr = torch.zeros((shots, (dem.N + 31) // 32), dtype=torch.int32, device="cuda")
+    rbp.window_commit(code, torch.from_numpy(pack(ew).view(np.int32)).cuda(),
+                      torch.from_numpy(cmap).cuda(), n_win, tsyn, tobs, tcorr)
+    e = np.zeros((shots, dem.N), dtype=np.uint8)
+    for j in range(n_win):
+        if cmap[j] >= 0:
+            e[:, cmap[j]] = ew[:, j]
+    s = (owin._unpack(syn0, dem.M) + e.astype(np.int64) @ dem.H.T.astype(np.int64)) % 2
+    o = (e.astype(np.int64) @ dem.O.T.astype(np.int64)) % 2
+    np.testing.assert_array_equal(u32(tsyn), pack(s.astype(np.uint8)))
+    np.testing.assert_array_equal(u32(tobs), pack(o.astype(np.uint8)))
+    np.testing.assert_array_equal(u32(tcorr), pack(e))
+
+
+@pytest.mark.parametrize("w,c,T", [(5, 1, 12), (4, 2, 12), (3, 3, 9)])
+def test_windowed_decode_matches_oracle(mods, w, c, T):
+    rbp, window = mods
+    dem = W.phenomenological_dem(W.zsz_lp("ZSZ-LP-160"), T, 5e-3)
+    m = dem.M // T
+    g = oracle.Graph(dem.H, dem.O)
+    syn, obs, _ = oracle.sample(g, dem.priors, 2000, seed=33 + w)
+    p = rbp.RelayParams()
+    dec = window.SlidingWindowDecoder(dem.H, dem.O, m, w, c)
+    corr, obsp, st = dec.decode(dem.priors, torch.from_numpy(syn.view(np.int32)).cuda(), p)
+    op = oracle.RelayParams(**{k: getattr(p, k) for k in oracle.RelayParams.__dataclass_fields__})
+    ref = owin.decode_windowed(dem.H, dem.O, dem.priors, syn, m, w, c, op, nthreads=8)
+    same = (u32(corr) == ref["corrections"]).all(axis=1)
+    assert same.mean() >= 0.999, same.mean()
+    assert (u32(obsp)[:, : ref["obs_pred"].shape[1]] == ref["obs_pred"]).all(axis=1).mean() >= 0.999
+    s = rbp.stats_to_numpy(st)
+    assert (s["converged"] == ref["converged"]).mean() >= 0.999
+    assert (s["iters"] == ref["iters"]).mean() >= 0.999
+    dec.close()
+
+
+def test_one_window_is_the_global_decode(mods):
+    rbp, window = mods
+    dem = W.phenomenological_dem(W.zsz_lp("ZSZ-LP-160"), 6, 5e-3)
+    code = rbp.Code.from_dem(dem)
+    syn, obs, _ = code.sample(dem.priors, 3000, seed=5)
+    p = rbp.RelayParams()
+    corr, obsp, st = code.decode(dem.priors, syn, p)
+    dec = window.SlidingWindowDecoder(dem.H, dem.O, dem.M // 6, 6, 2)
+    wc, wo, ws = dec.decode(dem.priors, syn, p)
+    np.testing.assert_array_equal(u32(wc), u32(corr))
+    np.testing.assert_array_equal(u32(wo), u32(obsp))
+    np.testing.assert_array_equal(rbp.stats_to_numpy(ws)["converged"], rbp.stats_to_numpy(st)["converged"])
+    dec.close()
