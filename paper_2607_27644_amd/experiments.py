@@ -19,6 +19,10 @@ names:
   sweep      LER against the noise strength p with one interval, and the
              sub-threshold fit p^(d_circ/2) exp(c0 + c1 p + c2 p^2) with its
              extrapolation (Sec. 6.1)
+  window     sliding-window decoding (window w rounds, commit c rounds) of a
+             long phenomenological memory experiment against one global decode:
+             LER, throughput and the single-shot latency of one window
+             (Sec. 6.1 latency discussion)
   awgn       block error rate of the classical ZSZ-2BGA codes over BPSK-AWGN
              against E_b/N_0, sum-product BP (numerics appendix, "classical
              channel coding"), with the decoder's throughput and the Shannon
@@ -35,7 +39,7 @@ import time
 import numpy as np
 import torch
 
-from . import autotune, learned, rbp, stats, workloads
+from . import autotune, learned, rbp, stats, window, workloads
 
 
 def _timed(fn, repeats: int = 3):
@@ -229,6 +233,57 @@ def ler_sweep(name: str, ps, shots: int, seed: int = 51, params: rbp.RelayParams
     return out
 
 
+def windowed(code_name: str = "ZSZ-LP-160", rounds: int = 30, p: float = 8e-3, shots: int = 200000,
+             configs=((10, 1), (10, 5), (5, 1)), seed: int = 71, params: rbp.RelayParams | None = None,
+             latency_shots: int = 300) -> dict:
+    """Sliding-window against global decoding of one T-round memory experiment."""
+    params = params or rbp.RelayParams()
+    dem = workloads.phenomenological_dem(workloads.zsz_lp(code_name), rounds, p)
+    m = dem.M // rounds
+    code = rbp.Code.from_dem(dem)
+    syn, obs, _ = code.sample(dem.priors, shots, seed)
+
+    def summary(obsp, st, ms):
+        s = rbp.stats_to_numpy(st)
+        f = stats.block_failures(rbp.to_u32(obsp), rbp.to_u32(obs), s["converged"])
+        return {"ms": ms, "shots_per_s": shots / (ms * 1e-3), "rounds_per_s": shots * rounds / (ms * 1e-3),
+                "ler": stats.ler_summary(int(f.sum()), shots, rounds, dem.k),
+                "nonconverged": int((s["converged"] == 0).sum()), "mean_iters": float(s["iters"].mean())}
+
+    out = {"model": f"{code_name} phenomenological, T = {rounds}, p = {p:g}", "M": dem.M, "N": dem.N,
+           "shots": shots, "seed": seed}
+    ms, (corr, obsp, st) = _timed(lambda: code.decode(dem.priors, syn, params))
+    out["global"] = summary(obsp, st, ms)
+    for w, c in configs:
+        dec = window.SlidingWindowDecoder(dem.H, dem.O, m, w, c)
+        ms, (corr, obsp, st) = _timed(lambda: dec.decode(dem.priors, syn, params))
+        r = summary(obsp, st, ms)
+        r["windows"] = len(dec.windows)
+        # single-shot latency of one full-size window, host clock around each
+        # call: the first window, whose syndrome is the sampled one (an
+        # interior window's syndrome exists only after the earlier commits)
+        win = dec.windows[0]
+        nb = win.rounds * m
+        buf = torch.empty((1, rbp.words(nb)), dtype=torch.int32, device=syn.device)
+        o1 = (torch.empty((1, rbp.words(win.cols.size)), dtype=torch.int32, device=syn.device),
+              torch.empty((1, 1), dtype=torch.int32, device=syn.device),
+              torch.empty((1, 32), dtype=torch.uint8, device=syn.device))
+        pr = dem.priors[win.cols]
+        lat = []
+        for i in range(latency_shots):
+            rbp.bits_extract(syn[i:i + 1], win.start * m, nb, buf)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            win.code.decode(pr, buf, params, out=o1)
+            torch.cuda.synchronize()
+            lat.append(1e6 * (time.perf_counter() - t0))
+        r["window_latency_us"] = stats.percentiles(np.array(lat))
+        r["window_shape"] = {"rounds": win.rounds, "detectors": nb, "mechanisms": int(win.cols.size)}
+        out[f"w{w}_c{c}"] = r
+        dec.close()
+    return out
+
+
 def awgn_fer(names, ebn0s, max_frames: int = 10 ** 7, min_errors: int = 100, chunk: int = 10 ** 6,
              seed: int = 61, params: rbp.SpaParams | None = None, side: str = "left") -> dict:
     """Frame (block) error rate of the all-zero codeword over BPSK-AWGN.
@@ -301,6 +356,8 @@ def main():
     ap.add_argument("--ebn0", default="0.5,1.0,1.25,1.5,2.0,2.5,3.0,3.5,4.0")
     ap.add_argument("--max-frames", type=int, default=10 ** 7)
     ap.add_argument("--min-errors", type=int, default=100)
+    ap.add_argument("--rounds", type=int, default=30)
+    ap.add_argument("--p-window", type=float, default=8e-3)
     a = ap.parse_args()
     torch.cuda.set_device(0)
     if a.what == "multi":
@@ -315,6 +372,8 @@ def main():
     elif a.what == "gamma":
         r = gamma_grid(a.model, a.p, [float(x) for x in a.gmin.split(",")], [float(x) for x in a.gmax.split(",")],
                        a.shots)
+    elif a.what == "window":
+        r = windowed(rounds=a.rounds, p=a.p_window, shots=a.shots)
     elif a.what == "awgn":
         r = awgn_fer(a.codes.split(","), [float(x) for x in a.ebn0.split(",")], a.max_frames, a.min_errors)
     elif a.what == "sweep":
