@@ -15,8 +15,9 @@
 // 64x64 block with v_mfma_f32_32x32x16_bf16, operands staged through two LDS
 // buffers in a K-contiguous layout (operands stored M- or N-contiguous are
 // transposed while staging; the next K step's tiles are loaded while the
-// current ones are multiplied).  Epilogues fuse the bias, ReLU, the ReLU mask of the backward pass
-// and the BF16/FP32 stores.
+// current ones are multiplied).  Tiles are numbered so that each XCD works on
+// a contiguous run of row blocks.  Epilogues fuse the bias, ReLU, the ReLU
+// mask of the backward pass and the BF16/FP32 stores.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -32,7 +33,12 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int BM = 128, BN = 128, BK = 32;
+constexpr int BM = 128, BK = 32;
+// Register budget: the 64 x 64 wave tile is built for 4 waves per SIMD (128
+// VGPRs, accumulators included), which fits the 4 workgroups per CU that the
+// LDS stages allow; the wider tile for 2.
+constexpr int kMinWaves64 = 4, kMinWaves128 = 2;
+constexpr int kFwdTN = 2;  // MFMA column blocks per wave in the forward products
 constexpr int LDSK = BK + 8;  // padded row of the staged tiles (bank spread)
 
 enum Layout { K_CONTIG = 0, MN_CONTIG = 1, BITS = 2 };  // BITS: A is packed 0/1 bits, 32 per word, rows of lda words
@@ -56,20 +62,21 @@ struct GemmArgs {
     int ldc;
 };
 
-// A BM x BK (or BN x BK) tile of an operand in flight from device memory to
-// LDS: each thread holds VPT vectors of 8 BF16 between the load (issued one K
-// step ahead) and the store into tile[row][k].
-constexpr int VPT = BM * BK / 8 / 256;
-static_assert(BM == BN && VPT * 256 * 8 == BM * BK, "tile shape");
-
+// A ROWS x BK tile of an operand in flight from device memory to LDS: each
+// thread holds VPT vectors of 8 BF16 between the load (issued one K step
+// ahead) and the store into tile[row][k].
+template <int ROWS>
 struct TileRegs {
+    static constexpr int VPT = ROWS * BK / 8 / 256;
+    static_assert(VPT * 256 * 8 == ROWS * BK, "tile shape");
     bf16x8 x[VPT];
 };
 
-template <int LAYOUT>
-__device__ __forceinline__ TileRegs load_tile(const bf16* src, int ld, int rows, int K, int r0, int k0) {
+template <int LAYOUT, int ROWS>
+__device__ __forceinline__ TileRegs<ROWS> load_tile(const bf16* src, int ld, int rows, int K, int r0, int k0) {
+    constexpr int VPT = TileRegs<ROWS>::VPT;
     const int t = threadIdx.x;
-    TileRegs v;
+    TileRegs<ROWS> v;
     if constexpr (LAYOUT == BITS) {
         // rows x BK k as vectors of 8 bits, each inside one 32-bit word (k0 and
         // the vector offsets are multiples of 8): expanded to BF16 0/1 in registers
@@ -103,7 +110,7 @@ __device__ __forceinline__ TileRegs load_tile(const bf16* src, int ld, int rows,
             }
         } else {
             // BK k x rows, rows contiguous in memory: vectors of 8 rows
-            const int kk = q / (BM / 8), r = (q % (BM / 8)) * 8;
+            const int kk = q / (ROWS / 8), r = (q % (ROWS / 8)) * 8;
             const int gr = r0 + r, gk = k0 + kk;
             if (vec && gk < K && gr + 7 < rows) {
                 v.x[pass] = *reinterpret_cast<const bf16x8*>(src + (int64_t)gk * ld + gr);
@@ -117,8 +124,9 @@ __device__ __forceinline__ TileRegs load_tile(const bf16* src, int ld, int rows,
     return v;
 }
 
-template <int LAYOUT>
-__device__ __forceinline__ void store_tile(bf16 (*tile)[LDSK], const TileRegs& v) {
+template <int LAYOUT, int ROWS>
+__device__ __forceinline__ void store_tile(bf16 (*tile)[LDSK], const TileRegs<ROWS>& v) {
+    constexpr int VPT = TileRegs<ROWS>::VPT;
     const int t = threadIdx.x;
 #pragma unroll
     for (int pass = 0; pass < VPT; ++pass) {
@@ -127,42 +135,54 @@ __device__ __forceinline__ void store_tile(bf16 (*tile)[LDSK], const TileRegs& v
             const int r = q / (BK / 8), kk = (q % (BK / 8)) * 8;
             *reinterpret_cast<bf16x8*>(&tile[r][kk]) = v.x[pass];
         } else {
-            const int kk = q / (BM / 8), r = (q % (BM / 8)) * 8;
+            const int kk = q / (ROWS / 8), r = (q % (ROWS / 8)) * 8;
 #pragma unroll
             for (int i = 0; i < 8; ++i) tile[r + i][kk] = v.x[pass][i];
         }
     }
 }
 
-template <int LA, int LB, int EPI>
-__global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs g) {
+// TN: 32-column MFMA blocks per wave, so a wave computes 64 x 32 TN and the
+// workgroup (2 x 2 waves) a BM x 64 TN tile
+template <int LA, int LB, int EPI, int TN>
+__global__ void __launch_bounds__(256, TN == 2 ? kMinWaves64 : kMinWaves128) gemm_kernel(const GemmArgs g) {
+    constexpr int BNT = 64 * TN;
     // two LDS stages: the tiles of step k are read by the matrix cores while
     // those of step k + 1 arrive in registers
     __shared__ __align__(16) bf16 As[2][BM][LDSK];
-    __shared__ __align__(16) bf16 Bs[2][BN][LDSK];
+    __shared__ __align__(16) bf16 Bs[2][BNT][LDSK];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    const int wm = (wid >> 1) * 64, wn = (wid & 1) * 64;  // this wave's 64x64 block
-    f32x16 acc[2][2];
+    // Workgroups are dealt to the 8 XCDs round-robin.  Renumber them so that
+    // each XCD takes a contiguous run of tiles in row-major order: the column
+    // tiles of a row block then run on one XCD and share its L2 copy of the A
+    // rows (the B operand, a weight matrix, fits every L2).
+    const int tiles_n = (g.N + BNT - 1) / BNT, tiles = tiles_n * ((g.M + BM - 1) / BM);
+    const int per_xcd = (tiles + 7) / 8;
+    const int logical = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    if (logical >= tiles) return;
+    const int m0 = (logical / tiles_n) * BM, n0 = (logical % tiles_n) * BNT;
+    const int wm = (wid >> 1) * 64, wn = (wid & 1) * 32 * TN;  // this wave's 64 x 32 TN block
+    f32x16 acc[2][TN];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{};
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x16{};
 
     {
-        const TileRegs ra = load_tile<LA>(g.A, g.lda, g.M, g.K, m0, 0);
-        const TileRegs rb = load_tile<LB>(g.B, g.ldb, g.N, g.K, n0, 0);
-        store_tile<LA>(As[0], ra);
-        store_tile<LB>(Bs[0], rb);
+        const TileRegs<BM> ra = load_tile<LA, BM>(g.A, g.lda, g.M, g.K, m0, 0);
+        const TileRegs<BNT> rb = load_tile<LB, BNT>(g.B, g.ldb, g.N, g.K, n0, 0);
+        store_tile<LA, BM>(As[0], ra);
+        store_tile<LB, BNT>(Bs[0], rb);
     }
     __syncthreads();
     int cur = 0;
     for (int k0 = 0; k0 < g.K; k0 += BK) {
         const bool more = k0 + BK < g.K;
-        TileRegs ra, rb;
+        TileRegs<BM> ra;
+        TileRegs<BNT> rb;
         if (more) {
-            ra = load_tile<LA>(g.A, g.lda, g.M, g.K, m0, k0 + BK);
-            rb = load_tile<LB>(g.B, g.ldb, g.N, g.K, n0, k0 + BK);
+            ra = load_tile<LA, BM>(g.A, g.lda, g.M, g.K, m0, k0 + BK);
+            rb = load_tile<LB, BNT>(g.B, g.ldb, g.N, g.K, n0, k0 + BK);
         }
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 16) {
@@ -170,23 +190,23 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs g) {
             // A and B use the same k order, so the product is independent of how the
             // matrix core pairs the k slots.
             const int kk = ks + (lane >> 5) * 8;
-            bf16x8 af[2], bfr[2];
+            bf16x8 af[2], bfr[TN];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
                 af[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wm + i * 32 + (lane & 31)][kk]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < TN; ++j)
                 bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wn + j * 32 + (lane & 31)][kk]);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < TN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
         }
         if (more) {
             // the other stage was last read before the previous barrier
-            store_tile<LA>(As[cur ^ 1], ra);
-            store_tile<LB>(Bs[cur ^ 1], rb);
+            store_tile<LA, BM>(As[cur ^ 1], ra);
+            store_tile<LB, BNT>(Bs[cur ^ 1], rb);
         }
         __syncthreads();
         cur ^= 1;
@@ -195,7 +215,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs g) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int m = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -375,10 +395,11 @@ rbp_status ensure_workspace(rbp_mlp* p, int B, bool training) {
     return RBP_OK;
 }
 
-template <int LA, int LB, int EPI>
+template <int LA, int LB, int EPI, int TN = 2>
 rbp_status gemm(const GemmArgs& a, hipStream_t s) {
-    dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM);
-    hipLaunchKernelGGL((gemm_kernel<LA, LB, EPI>), grid, dim3(256), 0, s, a);
+    const int tiles = ((a.N + 64 * TN - 1) / (64 * TN)) * ((a.M + BM - 1) / BM);
+    dim3 grid(8 * ((tiles + 7) / 8));  // renumbered per XCD in the kernel
+    hipLaunchKernelGGL((gemm_kernel<LA, LB, EPI, TN>), grid, dim3(256), 0, s, a);
     RBP_HIP_CHECK(hipGetLastError());
     return RBP_OK;
 }
@@ -439,19 +460,19 @@ rbp_status forward(rbp_mlp* p, const uint32_t* syn, int B, float* dout, hipStrea
         GemmArgs a = ga(B, p->hid, p->in, reinterpret_cast<const bf16*>(syn), words, wb + p->oW1, p->in, p->hid);
         a.bias = w + p->ob1;
         a.out_bf16 = h1;
-        st = gemm<BITS, K_CONTIG, EPI_BIAS_RELU_BF16>(a, s);
+        st = gemm<BITS, K_CONTIG, EPI_BIAS_RELU_BF16, kFwdTN>(a, s);
     }
     if (st) return st;
     GemmArgs a;
     a = ga(B, p->hid, p->hid, h1, p->hid, wb + p->oW2, p->hid, p->hid);
     a.bias = w + p->ob2;
     a.out_bf16 = h2;
-    st = gemm<K_CONTIG, K_CONTIG, EPI_BIAS_RELU_BF16>(a, s);
+    st = gemm<K_CONTIG, K_CONTIG, EPI_BIAS_RELU_BF16, kFwdTN>(a, s);
     if (st) return st;
     a = ga(B, p->out, p->hid, h2, p->hid, wb + p->oW3, p->hid, p->out);
     a.bias = w + p->ob3;
     a.out_f32 = dout;
-    return gemm<K_CONTIG, K_CONTIG, EPI_BIAS_F32>(a, s);
+    return gemm<K_CONTIG, K_CONTIG, EPI_BIAS_F32, kFwdTN>(a, s);
 }
 
 // forward + backward of one batch into p->g (gradients of the mean loss)
