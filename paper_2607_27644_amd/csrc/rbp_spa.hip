@@ -102,9 +102,43 @@ __device__ __forceinline__ void xst(uint32_t off, float v) { *reinterpret_cast<s
 
 __device__ __forceinline__ int spa_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// phi(x) = -ln tanh(x / 2) = log1p(2 / expm1(x)) for x >= 0; phi(0) = +inf and
-// phi(+inf) = 0 follow from IEEE arithmetic
-__device__ __forceinline__ float phi(float x) { return log1pf(__fdiv_rn(2.0f, expm1f(x))); }
+// phi(x) = -ln tanh(x / 2) = log1p(2 / expm1(x)) for x >= 0, from the
+// hardware exp2, log2 and reciprocal and two short series, about 25
+// instructions instead of the ~150 of the math library's expm1f and log1pf:
+//   e = expm1(x): Taylor polynomial through x^7/7! for x < 1/4 (truncation
+//       below 1e-8 relative), else exp2(x log2 e) - 1;
+//   y = 2 / e;
+//   log1p(y): series through y^6/6 for y < 1/32 (x > 4.17), else
+//       log2(1 + y) ln 2.
+// Relative error at most 2e-6 for x <= 20 and 4e-6 up to x = 60 (where phi
+// is below 1e-25), measured against a double-precision phi with the hardware
+// operations rounded once.  phi(0) = +inf and phi(+inf) = 0 as before.
+__device__ __forceinline__ float phi(float x) {
+    float e;
+    if (x < 0.25f) {
+        float p = 1.0f / 5040.0f;
+        p = __builtin_fmaf(p, x, 1.0f / 720.0f);
+        p = __builtin_fmaf(p, x, 1.0f / 120.0f);
+        p = __builtin_fmaf(p, x, 1.0f / 24.0f);
+        p = __builtin_fmaf(p, x, 1.0f / 6.0f);
+        p = __builtin_fmaf(p, x, 0.5f);
+        p = __builtin_fmaf(p, x, 1.0f);
+        e = p * x;
+    } else {
+        e = __builtin_amdgcn_exp2f(x * 1.44269504088896341f) - 1.0f;
+    }
+    const float y = 2.0f * __builtin_amdgcn_rcpf(e);
+    if (y < 0.03125f) {
+        float q = -1.0f / 6.0f;
+        q = __builtin_fmaf(q, y, 0.2f);
+        q = __builtin_fmaf(q, y, -0.25f);
+        q = __builtin_fmaf(q, y, 1.0f / 3.0f);
+        q = __builtin_fmaf(q, y, -0.5f);
+        q = __builtin_fmaf(q, y, 1.0f);
+        return q * y;
+    }
+    return __builtin_amdgcn_logf(1.0f + y) * 0.693147180559945309f;
+}
 
 __device__ __forceinline__ float clip(float x, float c) { return fminf(fmaxf(x, -c), c); }
 

@@ -2,11 +2,14 @@
 sum-product BP of the ZSZ-2BGA codes) against the CPU oracle.
 
 Tolerances follow from the arithmetic.  Both sides evaluate the same single-
-precision operations in the same order except phi = log1p(2 / expm1(x)), whose
-library implementations (device math library vs glibc) may differ by an ulp or
-two.  Hence: channel LLRs (single vs double precision) agree to 1e-5 (1 +
-|llr|); marginals after one iteration to 1e-5 relative; after five iterations
-to 2e-3 relative (the few-ulp differences are propagated, not created).  In
+precision operations in the same order except phi = -ln tanh(x/2): the oracle
+calls the C library's log1pf(2 / expm1f(x)), the kernel a formulation from the
+hardware exp2 / log2 / reciprocal with two short series, within 2e-6 relative
+for the |nu| <= 20 it sees.  Hence: channel LLRs (single vs double precision)
+agree to 1e-5 (1 + |llr|); marginals after one iteration to 1e-5 relative;
+after five iterations to 2e-3 relative (the differences are propagated, not
+created); one iteration on a single check matches the float64 tanh rule
+2 atanh(prod tanh(L/2)) to 1e-5.  In
 full decodes, shots that never reach a codeword iterate chaotically for all
 max_iterations and their final hard decision depends on the last ulp: moving
 the oracle's own inputs by one ulp changes about 0.4 % of such words at 3 dB
@@ -122,6 +125,24 @@ def test_full_decode_matches_oracle(rbp, name, ebn0):
     c = counts.cpu().numpy()
     assert c[0] == nz.sum() and c[1] == (nz & conv).sum() and c[2] == (~conv).sum()
     assert (s["path"] == nz).all()
+
+
+@pytest.mark.parametrize("D", [2, 3, 6, 11])
+def test_single_check_against_tanh_rule(rbp, D):
+    """phi as the kernel evaluates it, through one check update: magnitudes
+    from 1e-6 to the clip value, both signs."""
+    rng = np.random.default_rng(40 + D)
+    H = np.ones((1, D), dtype=np.uint8)
+    mag = np.exp(rng.uniform(np.log(1e-6), np.log(20.0), size=(2000, D)))
+    L = (mag * rng.choice([-1.0, 1.0], size=mag.shape)).astype(np.float32)
+    code = code_of(rbp, H)
+    _, marg, _ = code.decode_spa(torch.from_numpy(L).cuda(), rbp.SpaParams(max_iterations=1, stop=False),
+                                 marginals=True)
+    Ld = L.astype(np.float64)
+    th = np.tanh(Ld / 2.0)
+    ref = np.stack([Ld[:, j] + 2.0 * np.arctanh(np.clip(np.prod(np.delete(th, j, axis=1), axis=1), -1 + 1e-16,
+                                                        1 - 1e-16)) for j in range(D)], axis=1)
+    assert rel_ok(marg.cpu().numpy(), ref, 1e-5, 1e-5).all()
 
 
 def test_launch_shape_and_edge_cases(rbp):
