@@ -259,6 +259,7 @@ def main():
         # the classical benchmark beside the headline: the [310,155] ZSZ-2BGA code
         # over BPSK-AWGN at 2.5 dB, sum-product BP (num_iter 100, llr_max 20)
         from paper_2607_27644_amd import experiments
+        experiments.awgn_fer(["ZSZ-2BGA-310"], [2.5], max_frames=100_000, min_errors=10 ** 12, chunk=100_000)
         r = experiments.awgn_fer(["ZSZ-2BGA-310"], [2.5], max_frames=4_000_000, min_errors=10 ** 12,
                                  chunk=1_000_000)
         pt = r["codes"]["ZSZ-2BGA-310"]["points"][0]
