@@ -87,6 +87,8 @@ struct SpaLaunch {
     int32_t off_L, off_M, off_par, off_dec, off_out, off_misc;
 };
 
+constexpr int kSpaRun = 8;  // frames taken per counter atomic while many remain
+
 struct SpaMisc {
     unsigned long long shot;
     int32_t count;  // unsatisfied checks of the current hard decision
@@ -284,10 +286,22 @@ __global__ void __launch_bounds__(1024) spa_kernel(const SpaLaunch a) {
     SpaMisc* ms = reinterpret_cast<SpaMisc*>(smem + a.off_misc);
     const float c = a.llr_max;
     unsigned long long n_block = 0, n_undetected = 0, n_nonconv = 0;  // kept by thread 0
+    // Frames come from the device counter in runs of kSpaRun (one atomic per
+    // run) while many remain, one at a time near the end: at high E_b/N_0 a
+    // frame takes about two iterations and one atomic per frame would bound
+    // the rate.
+    unsigned long long run_next = 0, run_end = 0, last_ticket = 0;
 
     for (;;) {
         if (tid == 0) {
-            ms->shot = atomicAdd(a.queue, 1ull);
+            if (run_next == run_end) {
+                const unsigned long long k =
+                    last_ticket + 8ull * kSpaRun * gridDim.x < a.shots ? (unsigned long long)kSpaRun : 1ull;
+                run_next = atomicAdd(a.queue, k);
+                run_end = run_next + k;
+                last_ticket = run_next;
+            }
+            ms->shot = run_next++;
             ms->count = 0;
             ms->nonzero = 0;
         }
