@@ -296,19 +296,6 @@ __global__ void first_message_kernel(const int32_t* row_ptr, const int32_t* col_
     }
 }
 
-template <class T>
-__device__ __forceinline__ T block_sum(T v, T* red) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (lane == 0) red[wid] = v;
-    __syncthreads();
-    T s = 0;
-    for (int i = 0; i < nw; ++i) s += red[i];
-    __syncthreads();
-    return s;
-}
-
 // median of three unsigned values: the new second minimum, given min1 <= min2
 __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
     uint32_t r;
@@ -575,6 +562,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
             ms->shot = run_next++;
             ms->count = 0;
             ms->W = 0.0;
+            ms->red[0] = 0;
         }
         __syncthreads();
         // the shot, its model and its row are uniform over the workgroup: keep them scalar
@@ -597,7 +585,10 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
             pc += __popc(v);
         }
         for (int w = tid; w < m.WK; w += nth) obw[w] = 0u;
-        const int base = block_sum<int>(pc, ms->red);
+        for (int w = tid; w < WN; w += nth) best[w] = 0u;  // the output bits, scattered at the end
+        if (pc) atomicAdd(&ms->red[0], pc);
+        __syncthreads();
+        const int base = uniform(ms->red[0]);  // syndrome weight
 
         int nconv = 0, legs = 0, iters = 0, path = 0;
         bool x_mu1 = false;  // X holds mu(1) of a plain leg
@@ -608,8 +599,6 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
         if (base == 0) {
             path = 3;
             have_best = true;
-            for (int w = tid; w < WN; w += nth) best[w] = 0u;
-            __syncthreads();
         } else {
             // syndrome bits in row-position order, one ballot per row group
             for (int g = wid; g < m.GR; g += nw) {
@@ -788,9 +777,8 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                     }
                 }
             }
-            for (int w = tid; w < WN; w += nth) best[w] = 0u;
-            __syncthreads();
-            // positions -> variable order: scatter the (few) set bits
+            // positions -> variable order: scatter the (few) set bits (each wave
+            // reads the ballots it wrote itself; `best` was cleared at set-up)
             for (int g = wid; g < m.GV; g += nw) {
                 if ((bestp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u) {
                     const int j = ldg(m.vord, (uint32_t)(g * 64 + lane));
