@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
 benchmark's ``cpu_baseline`` leg.  The product package never imports it, and it
 imports nothing from the product package (inputs arrive as plain numpy arrays).
 
-* ``rbp_oracle.c`` -- Philox4x32-10 sampler, GF(2) syndromes, FP32 Relay-BP
+* ``rbp_oracle.c`` -- Philox4x32-10 fault sampler (geometric gaps with
+  integer thresholds, thinned to per-mechanism priors), GF(2) syndromes, FP32 Relay-BP
   (paper Sec. 6.1: flooding min-sum with memory, sequential relay legs,
   lowest-weight of ``stop_nconv`` solutions, single-precision messages).
 * ``spa_oracle.c`` -- BPSK-AWGN channel (Philox4x32-10 + Box-Muller, double)
@@ -51,7 +52,8 @@ def lib():
         u32p, i32p, f32p, f64p, u8p = (P(ctypes.c_uint32), P(ctypes.c_int32), P(ctypes.c_float),
                                         P(ctypes.c_double), P(ctypes.c_uint8))
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
-        L.orc_thresholds.argtypes = [ctypes.c_int64, f64p, u32p]
+        L.orc_gap_table.argtypes = [ctypes.c_double, ctypes.c_int32, u32p]
+        L.orc_accept_table.argtypes = [ctypes.c_int64, f64p, ctypes.c_double, u32p]
         L.orc_llr.argtypes = [ctypes.c_int64, f64p, f32p]
         L.orc_gamma_table.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                       ctypes.c_uint64, f32p]
@@ -138,10 +140,18 @@ def philox4x32_10(ctr, key) -> np.ndarray:
     return out
 
 
-def thresholds(p: np.ndarray) -> np.ndarray:
+def gap_table(pmax: float, L: int) -> np.ndarray:
+    """T_k = floor((1 - pmax)^k 2^32), k = 1..L (the sampler's gap thresholds)."""
+    out = np.zeros(max(L, 1), dtype=np.uint32)
+    lib().orc_gap_table(pmax, L, _p(out, ctypes.c_uint32))
+    return out[:L]
+
+
+def accept_table(p: np.ndarray, pmax: float) -> np.ndarray:
+    """floor(p_j / pmax 2^32) for p_j < pmax, 0xFFFFFFFF where p_j = pmax."""
     p = np.ascontiguousarray(p, dtype=np.float64)
     out = np.zeros(p.size, dtype=np.uint32)
-    lib().orc_thresholds(p.size, _p(p, ctypes.c_double), _p(out, ctypes.c_uint32))
+    lib().orc_accept_table(p.size, _p(p, ctypes.c_double), pmax, _p(out, ctypes.c_uint32))
     return out
 
 

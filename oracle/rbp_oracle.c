@@ -10,8 +10,12 @@
  * paper cites for its memory experiments, run with flooding schedule,
  * sequential relay legs and single-precision messages):
  *
- *   sampling      e_j = [Philox4x32-10(seed; j/4, shot, 0)_{j mod 4} < thr_j],
- *                 thr_j = min(floor(p_j 2^32), 2^32 - 1)
+ *   sampling      independent faults e_j ~ Bernoulli(p_j): the mechanisms are cut
+ *                 into 64 segments; in each, candidates follow geometric gaps of
+ *                 parameter pmax = max p_j read off an integer table of
+ *                 floor((1 - pmax)^k 2^32), and a candidate is kept with
+ *                 probability p_j / pmax (integer thresholds); words from
+ *                 Philox4x32-10 (see sample_shot)
  *   syndromes     sigma = H e, observables o = O e over GF(2)
  *   LLRs          Lambda_j = (float) ln((1 - p_j) / p_j), evaluated in double
  *   Relay-BP      per shot, legs r = 0..R; leg 0 has memory strength gamma0 for
@@ -70,13 +74,6 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[3] = c3;
 }
 
-void orc_thresholds(int64_t n, const double* p, uint32_t* thr) {
-    for (int64_t j = 0; j < n; ++j) {
-        double t = floor(p[j] * 4294967296.0);
-        thr[j] = t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t;
-    }
-}
-
 void orc_llr(int64_t n, const double* p, float* llr) {
     for (int64_t j = 0; j < n; ++j) llr[j] = (float)log((1.0 - p[j]) / p[j]);
 }
@@ -103,33 +100,107 @@ static int get_bit(const uint32_t* w, int64_t b) { return (int)((w[b >> 5] >> (b
 static void flip_bit(uint32_t* w, int64_t b) { w[b >> 5] ^= (1u << (b & 31)); }
 static void set_bit(uint32_t* w, int64_t b) { w[b >> 5] |= (1u << (b & 31)); }
 
+/* Geometric gap table of the sampler: T_k = floor((1 - pmax)^k 2^32), k = 1..L,
+   with (1 - pmax)^k evaluated as exp(k log1p(-pmax)) in double, at most 2^32 - 1. */
+void orc_gap_table(double pmax, int32_t L, uint32_t* T) {
+    const double lq = log1p(-pmax);
+    for (int32_t k = 1; k <= L; ++k) {
+        double t = floor(exp((double)k * lq) * 4294967296.0);
+        T[k - 1] = t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t;
+    }
+}
+
+/* Acceptance thresholds: A_j = floor(p_j / pmax 2^32) (at most 2^32 - 2) when
+   p_j < pmax; 0xFFFFFFFF marks p_j = pmax (accepted without a draw). */
+void orc_accept_table(int64_t n, const double* p, double pmax, uint32_t* A) {
+    for (int64_t j = 0; j < n; ++j) {
+        if (p[j] >= pmax) { A[j] = 0xFFFFFFFFu; continue; }
+        double t = floor(p[j] / pmax * 4294967296.0);
+        A[j] = t >= 4294967294.0 ? 0xFFFFFFFEu : (uint32_t)t;
+    }
+}
+
+/* Faults of one shot.  The N mechanisms are cut into 64 segments of
+   L = ceil(N / 64); in each, candidate positions follow geometric gaps of
+   parameter pmax (gap G = number of k in 1..len with T_k > w for the next
+   word w), and a candidate j with p_j < pmax is kept when the next word is
+   below A_j.  Words of segment g come from Philox4x32-10 with key = seed and
+   counter (g 2^24 + d / 4, shot lo, shot hi, 3), word d mod 4, d = 0, 1, ... */
+static void sample_shot(int32_t N, const uint32_t* T, const uint32_t* A, const uint32_t key[2], uint64_t sid,
+                        void (*fault)(int32_t j, void* ctx), void* ctx) {
+    const int32_t L = (N + 63) / 64;
+    for (int32_t g = 0; g < 64; ++g) {
+        const int32_t base = g * L;
+        const int32_t len = N - base < L ? N - base : L;
+        if (len <= 0) break;
+        uint32_t buf[4];
+        int64_t d = 0, have = -1;
+        int32_t pos = -1;
+        for (;;) {
+            if (d / 4 != have) {
+                const uint32_t ctr[4] = {((uint32_t)g << 24) + (uint32_t)(d / 4), (uint32_t)sid,
+                                         (uint32_t)(sid >> 32), 3u};
+                orc_philox4x32_10(ctr, key, buf);
+                have = d / 4;
+            }
+            const uint32_t w = buf[d % 4];
+            ++d;
+            int32_t G = 0;
+            while (G < len && T[G] > w) ++G; /* T[G] is T_{G+1} */
+            pos += G + 1;
+            if (pos >= len) break;
+            const int32_t j = base + pos;
+            if (A[j] != 0xFFFFFFFFu) {
+                if (d / 4 != have) {
+                    const uint32_t ctr[4] = {((uint32_t)g << 24) + (uint32_t)(d / 4), (uint32_t)sid,
+                                             (uint32_t)(sid >> 32), 3u};
+                    orc_philox4x32_10(ctr, key, buf);
+                    have = d / 4;
+                }
+                const uint32_t a = buf[d % 4];
+                ++d;
+                if (a >= A[j]) continue;
+            }
+            fault(j, ctx);
+        }
+    }
+}
+
+typedef struct {
+    const int32_t *col_ptr, *row_idx, *ocol_ptr, *orow_idx;
+    uint32_t *sy, *ob, *er;
+} fault_ctx;
+
+static void apply_fault(int32_t j, void* vctx) {
+    fault_ctx* c = (fault_ctx*)vctx;
+    for (int32_t e = c->col_ptr[j]; e < c->col_ptr[j + 1]; ++e) flip_bit(c->sy, c->row_idx[e]);
+    for (int32_t e = c->ocol_ptr[j]; e < c->ocol_ptr[j + 1]; ++e) flip_bit(c->ob, c->orow_idx[e]);
+    if (c->er) set_bit(c->er, j);
+}
+
 int orc_sample(int32_t M, int32_t N, const int32_t* col_ptr, const int32_t* row_idx, int32_t k,
                const int32_t* ocol_ptr, const int32_t* orow_idx, const double* priors, uint64_t shots,
                uint64_t seed, uint64_t shot_offset, uint32_t* synd, uint32_t* obs, uint32_t* err) {
     int64_t wm = (M + 31) / 32, wk = (k + 31) / 32, wn = (N + 31) / 32;
-    uint32_t* thr = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(N > 0 ? N : 1));
-    if (!thr) return -4;
-    orc_thresholds(N, priors, thr);
+    const int32_t L = (N + 63) / 64;
+    double pmax = 0.0;
+    for (int32_t j = 0; j < N; ++j) pmax = priors[j] > pmax ? priors[j] : pmax;
+    uint32_t* T = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(L > 0 ? L : 1));
+    uint32_t* A = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(N > 0 ? N : 1));
+    if (!T || !A) { free(T); free(A); return -4; }
+    orc_gap_table(pmax, L, T);
+    orc_accept_table(N, priors, pmax, A);
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     for (uint64_t s = 0; s < shots; ++s) {
-        uint64_t sid = shot_offset + s;
-        uint32_t* sy = synd + s * wm;
-        uint32_t* ob = obs + s * wk;
-        memset(sy, 0, sizeof(uint32_t) * wm);
-        memset(ob, 0, sizeof(uint32_t) * wk);
-        if (err) memset(err + s * wn, 0, sizeof(uint32_t) * wn);
-        for (int32_t j = 0; j < N; ++j) {
-            uint32_t ctr[4] = {(uint32_t)(j / 4), (uint32_t)sid, (uint32_t)(sid >> 32), 0u};
-            uint32_t o[4];
-            orc_philox4x32_10(ctr, key, o);
-            if (o[j % 4] < thr[j]) {
-                for (int32_t e = col_ptr[j]; e < col_ptr[j + 1]; ++e) flip_bit(sy, row_idx[e]);
-                for (int32_t e = ocol_ptr[j]; e < ocol_ptr[j + 1]; ++e) flip_bit(ob, orow_idx[e]);
-                if (err) set_bit(err + s * wn, j);
-            }
-        }
+        fault_ctx c = {col_ptr, row_idx, ocol_ptr, orow_idx, synd + s * wm, obs + s * wk,
+                       err ? err + s * wn : NULL};
+        memset(c.sy, 0, sizeof(uint32_t) * wm);
+        memset(c.ob, 0, sizeof(uint32_t) * wk);
+        if (c.er) memset(c.er, 0, sizeof(uint32_t) * wn);
+        sample_shot(N, T, A, key, shot_offset + s, apply_fault, &c);
     }
-    free(thr);
+    free(T);
+    free(A);
     return 0;
 }
 

@@ -34,13 +34,19 @@ def test_philox_known_answers():
 
 
 # ---------------------------------------------------------------- thresholds, LLRs, gammas
-def test_thresholds_closed_form():
-    p = np.array([0.5, 0.25, 1e-3, 2.0 ** -32, 0.1])
-    thr = oracle.thresholds(p)
-    assert list(thr[:2]) == [2 ** 31, 2 ** 30]
-    assert thr[2] == 4294967  # floor(0.001 * 2^32) = floor(4294967.296)
-    assert thr[3] == 1
-    assert thr[4] == math.floor(0.1 * 2 ** 32)
+def test_sampler_tables_closed_form():
+    # T_k = floor((1 - pmax)^k 2^32): powers of two for pmax = 1/2 (up to one unit
+    # of rounding in exp), and floor(0.999 * 2^32) for pmax = 1e-3
+    T = oracle.gap_table(0.5, 40)
+    for k in range(1, 41):
+        assert int(T[k - 1]) in (2 ** (32 - k), 2 ** (32 - k) - 1) or (k > 32 and int(T[k - 1]) == 0)
+    assert int(oracle.gap_table(1e-3, 1)[0]) == math.floor(0.999 * 2 ** 32)
+    t = oracle.gap_table(1e-3, 2000).astype(np.int64)
+    assert (np.diff(t) <= 0).all()
+    assert abs(t[1999] / 2 ** 32 - 0.999 ** 2000) < 1e-9
+    # acceptance: p_j / pmax in 32-bit fixed point; p_j = pmax is marked
+    A = oracle.accept_table(np.array([1e-3, 5e-4, 2.5e-4, 1e-3]), 1e-3)
+    assert list(A) == [0xFFFFFFFF, 2 ** 31, 2 ** 30, 0xFFFFFFFF]
 
 
 def test_llr_closed_form():
@@ -102,6 +108,37 @@ def test_sampler_adjacent_pairs_uncorrelated():
     assert abs(c) < 0.01
     c2 = np.corrcoef(e[:-1].ravel(), e[1:].ravel())[0, 1]
     assert abs(c2) < 0.01
+
+
+def test_sampler_thinning_nonuniform_priors():
+    # per-mechanism frequencies follow p_j when the priors differ (geometric gaps
+    # at the largest prior, candidates kept with probability p_j / pmax)
+    dem = W.workload("cc160")
+    pri = W.random_priors(dem.N, 2e-3, 5e-2, seed=4)
+    shots = 20000
+    _, _, err = oracle.sample(_graph(dem), pri, shots, seed=21, want_errors=True)
+    cnt = W.unpack_bits(err, dem.N).sum(0)
+    z = (cnt - shots * pri) / np.sqrt(shots * pri * (1 - pri))
+    assert (z ** 2).sum() < dem.N + 6 * math.sqrt(2 * dem.N)
+    assert np.abs(z).max() < 5.0
+
+
+def test_sampler_segment_law():
+    # no fault in a segment of length len with probability (1 - p)^len; segments of
+    # one shot are independent (64 segments of ceil(N / 64) mechanisms)
+    dem = W.workload("phen160")
+    p = 2e-3
+    shots = 20000
+    _, _, err = oracle.sample(_graph(dem), np.full(dem.N, p), shots, seed=8, want_errors=True)
+    e = W.unpack_bits(err, dem.N)
+    L = (dem.N + 63) // 64
+    seg = np.add.reduceat(e, np.arange(0, dem.N, L), axis=1) > 0
+    q = (1 - p) ** L
+    n0 = (~seg[:, :-1]).sum()
+    n = seg[:, :-1].size
+    assert abs(n0 - n * q) < 5 * math.sqrt(n * q * (1 - q))
+    c = np.corrcoef(seg[:, 0].astype(float), seg[:, 1].astype(float))[0, 1]
+    assert abs(c) < 0.03
 
 
 def test_sampler_offsets_are_resumable():
