@@ -61,10 +61,17 @@ rbp_status rbp_code_info(rbp_code_t code, int32_t* M, int32_t* N, int32_t* nnz, 
                          int32_t* max_col_deg);
 
 /* sample(H, priors, shots, seed)  -- Bernoulli faults and their syndromes.
- * priors: host double[N], each in (0, 0.5].  Mechanism j of shot s faults iff
- * word (j mod 4) of Philox4x32-10 with key (seed lo, seed hi) and counter
- * (j / 4, shot lo, shot hi, 0), shot = shot_offset + s, is below
- * min(floor(p_j 2^32), 2^32 - 1).  So any shot range is reproducible on its own.
+ * priors: host double[N], each in (0, 0.5]; mechanism j faults independently
+ * with probability p_j (to 2^-32).  The mechanisms are cut into 64 segments of
+ * L = ceil(N/64).  In segment g, with pmax = max_j p_j, candidate positions
+ * follow geometric gaps: the gap G before the next candidate is the number of
+ * k in 1..len(g) with T_k > w, w the next 32-bit word and
+ * T_k = min(floor(exp(k log1p(-pmax)) 2^32), 2^32 - 1) (double precision); a
+ * candidate j with p_j < pmax is kept iff the next word is below
+ * A_j = min(floor(p_j / pmax 2^32), 2^32 - 2), one with p_j = pmax always.
+ * Word d of segment g of shot s is word (d mod 4) of Philox4x32-10 with key
+ * (seed lo, seed hi) and counter (g 2^24 + d / 4, shot lo, shot hi, 3),
+ * shot = shot_offset + s, so any shot range is reproducible on its own.
  * Outputs (device): syndromes_dev uint32[shots][ceil(M/32)] = H e,
  * obs_dev uint32[shots][ceil(k/32)] = O e (may be NULL when k = 0),
  * errors_dev uint32[shots][ceil(N/32)] = e (may be NULL). */

@@ -90,7 +90,8 @@ struct rbp_code {
     rbp::DevBuf orow_ptr, ocol_idx;     // CSR of O: orow_ptr[k+1], ocol_idx[nnzO]
     rbp::DevBuf ocol_ptr, orow_idx;     // CSC of O (sampler)
     // per-call data (cached by content)
-    rbp::DevBuf thr;                    // uint32[N] sampling thresholds
+    rbp::DevBuf thr;                    // uint32[N] sampler acceptance thresholds A_j
+    rbp::DevBuf gapt;                   // uint32[ceil(N/64)] sampler gap thresholds T_k
     std::vector<double> thr_key;
     rbp::DevBuf lam, lamp;              // float LLRs by variable [N] and by position [Np]
     rbp::DevBuf m1;                     // float[RB] first-iteration message magnitudes (layout of rposp)

@@ -62,15 +62,25 @@ void DevBuf::release() {
 }
 
 // ---------------------------------------------------------------------------
-// Sampling: e_j = [Philox(seed; j/4, shot, 0)_{j%4} < thr_j]; sigma = H e; o = O e
+// Sampling: independent faults e_j ~ Bernoulli(p_j); sigma = H e; o = O e.
+// The mechanisms are cut into 64 segments of L = ceil(N / 64), one per lane.
+// In a segment, candidate positions follow geometric gaps of parameter
+// pmax = max p_j: the gap G before the next candidate is the number of k in
+// 1..len with T_k > w for the next 32-bit word w, T_k = floor((1 - pmax)^k 2^32)
+// (a host table), so P(G >= k) = (1 - pmax)^k to 2^-32; a candidate j with
+// p_j < pmax is kept when the next word is below A_j = floor(p_j / pmax 2^32).
+// Words of segment g: Philox4x32-10, key = seed, counter (g 2^24 + d / 4,
+// shot lo, shot hi, 3), word d mod 4 for d = 0, 1, ...  At p = 1e-3 a lane
+// draws about one word per shot instead of one per mechanism.
 // ---------------------------------------------------------------------------
 struct SampleArgs {
-    int32_t M, N, k, WM, WK, WN;
+    int32_t M, N, k, WM, WK, WN, L;
     const int32_t* col_ptr;
     const int32_t* csc_row;
     const int32_t* ocol_ptr;
     const int32_t* orow_idx;
-    const uint32_t* thr;
+    const uint32_t* gap;  // [L] T_k, decreasing
+    const uint32_t* acc;  // [N] A_j; 0xFFFFFFFF where p_j = pmax (kept without a draw)
     uint64_t shots, seed, offset;
     uint32_t* syn;
     uint32_t* obs;
@@ -84,42 +94,65 @@ __global__ void __launch_bounds__(64 * kSampleWaves) sample_kernel(const SampleA
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const uint64_t s = (uint64_t)blockIdx.x * kSampleWaves + wid;
     const bool live = s < a.shots;
-    const int words = a.WM + a.WK;
+    const int words = a.WM + a.WK + (a.err ? a.WN : 0);
     uint32_t* sy = sm_sample + wid * words;
     uint32_t* ob = sy + a.WM;
+    uint32_t* er = ob + a.WK;
     for (int x = lane; x < words; x += 64) sy[x] = 0u;
     __syncthreads();
-    const uint64_t sid = a.offset + s;
-    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    const int nq = (a.N + 3) >> 2;
-    for (int qb = 0; qb < nq; qb += 64) {
-        const int q = qb + lane;
-        uint32_t nib = 0;
-        if (live && q < nq) {
-            const U4 r = philox4x32_10(U4{(uint32_t)q, (uint32_t)sid, (uint32_t)(sid >> 32), 0u}, k0, k1);
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const int j = 4 * q + w;
-                if (j < a.N && u4_get(r, w) < a.thr[j]) {
-                    nib |= 1u << w;
-                    for (int e = a.col_ptr[j]; e < a.col_ptr[j + 1]; ++e) {
-                        const int i = a.csc_row[e];
-                        atomicXor(sy + (i >> 5), 1u << (i & 31));
-                    }
-                    for (int e = a.ocol_ptr[j]; e < a.ocol_ptr[j + 1]; ++e) {
-                        const int i = a.orow_idx[e];
-                        atomicXor(ob + (i >> 5), 1u << (i & 31));
-                    }
-                }
+    const int base = lane * a.L;
+    const int len = min(a.L, a.N - base);
+    if (live && len > 0) {
+        const uint64_t sid = a.offset + s;
+        const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+        const uint32_t c0 = (uint32_t)lane << 24;
+        U4 buf{0u, 0u, 0u, 0u};
+        uint32_t have = 0xFFFFFFFFu, d = 0;
+        int pos = -1;
+        for (;;) {
+            if ((d >> 2) != have) {
+                have = d >> 2;
+                buf = philox4x32_10(U4{c0 + have, (uint32_t)sid, (uint32_t)(sid >> 32), 3u}, k0, k1);
             }
-        }
-        if (a.err) {
-            // eight consecutive lanes hold the eight nibbles of one 32-bit word
-            uint32_t v = nib << (4 * (lane & 7));
-            v |= __shfl_xor(v, 1);
-            v |= __shfl_xor(v, 2);
-            v |= __shfl_xor(v, 4);
-            if (live && (lane & 7) == 0 && q < nq) a.err[s * a.WN + (q >> 3)] = v;
+            const uint32_t w = u4_get(buf, (int)(d & 3u));
+            ++d;
+            // G = number of leading table entries above w (T decreasing)
+            int G;
+            if (a.gap[len - 1] > w) {
+                G = len;
+            } else {
+                int lo = 0, hi = len - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (a.gap[mid] > w)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                G = lo;
+            }
+            pos += G + 1;
+            if (pos >= len) break;
+            const int j = base + pos;
+            const uint32_t A = a.acc[j];
+            if (A != 0xFFFFFFFFu) {
+                if ((d >> 2) != have) {
+                    have = d >> 2;
+                    buf = philox4x32_10(U4{c0 + have, (uint32_t)sid, (uint32_t)(sid >> 32), 3u}, k0, k1);
+                }
+                const uint32_t u = u4_get(buf, (int)(d & 3u));
+                ++d;
+                if (u >= A) continue;
+            }
+            for (int e = a.col_ptr[j]; e < a.col_ptr[j + 1]; ++e) {
+                const int i = a.csc_row[e];
+                atomicXor(sy + (i >> 5), 1u << (i & 31));
+            }
+            for (int e = a.ocol_ptr[j]; e < a.ocol_ptr[j + 1]; ++e) {
+                const int i = a.orow_idx[e];
+                atomicXor(ob + (i >> 5), 1u << (i & 31));
+            }
+            if (a.err) atomicOr(er + (j >> 5), 1u << (j & 31));
         }
     }
     __syncthreads();
@@ -127,6 +160,8 @@ __global__ void __launch_bounds__(64 * kSampleWaves) sample_kernel(const SampleA
         for (int x = lane; x < a.WM; x += 64) a.syn[s * a.WM + x] = sy[x];
         if (a.obs)
             for (int x = lane; x < a.WK; x += 64) a.obs[s * a.WK + x] = ob[x];
+        if (a.err)
+            for (int x = lane; x < a.WN; x += 64) a.err[s * a.WN + x] = er[x];
     }
 }
 
@@ -871,19 +906,37 @@ static rbp_status ensure_llr(rbp_code* c, const double* priors, hipStream_t stre
     return RBP_OK;
 }
 
+// Sampler tables for the priors: T_k = floor((1 - pmax)^k 2^32), k = 1..L, with
+// (1 - pmax)^k evaluated as exp(k log1p(-pmax)) in double (at most 2^32 - 1),
+// and A_j = floor(p_j / pmax 2^32) (at most 2^32 - 2) for p_j < pmax,
+// 0xFFFFFFFF for p_j = pmax.
 static rbp_status ensure_thresholds(rbp_code* c, const double* priors, hipStream_t stream) {
     if (c->thr.p && c->thr_key.size() == (size_t)c->N &&
         std::memcmp(c->thr_key.data(), priors, sizeof(double) * c->N) == 0)
         return RBP_OK;
-    std::vector<uint32_t> thr(c->N);
-    for (int j = 0; j < c->N; ++j) {
-        const double t = std::floor(priors[j] * 4294967296.0);
-        thr[j] = t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t;
+    const int L = ceil_div(c->N, 64);
+    double pmax = 0.0;
+    for (int j = 0; j < c->N; ++j) pmax = std::max(pmax, priors[j]);
+    std::vector<uint32_t> T(std::max(L, 1)), A(std::max(c->N, 1));
+    const double lq = std::log1p(-pmax);
+    for (int kk = 1; kk <= L; ++kk) {
+        const double t = std::floor(std::exp((double)kk * lq) * 4294967296.0);
+        T[kk - 1] = t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t;
     }
-    rbp_status st = c->thr.reserve(sizeof(uint32_t) * std::max(c->N, 1));
+    for (int j = 0; j < c->N; ++j) {
+        if (priors[j] >= pmax) {
+            A[j] = 0xFFFFFFFFu;
+        } else {
+            const double t = std::floor(priors[j] / pmax * 4294967296.0);
+            A[j] = t >= 4294967294.0 ? 0xFFFFFFFEu : (uint32_t)t;
+        }
+    }
+    rbp_status st = c->thr.reserve(sizeof(uint32_t) * A.size());
+    if (!st) st = c->gapt.reserve(sizeof(uint32_t) * T.size());
     if (st) return st;
     RBP_HIP_CHECK(hipStreamSynchronize(stream));
-    RBP_HIP_CHECK(hipMemcpy(c->thr.p, thr.data(), sizeof(uint32_t) * c->N, hipMemcpyHostToDevice));
+    RBP_HIP_CHECK(hipMemcpy(c->thr.p, A.data(), sizeof(uint32_t) * A.size(), hipMemcpyHostToDevice));
+    RBP_HIP_CHECK(hipMemcpy(c->gapt.p, T.data(), sizeof(uint32_t) * T.size(), hipMemcpyHostToDevice));
     c->thr_key.assign(priors, priors + c->N);
     return RBP_OK;
 }
@@ -1338,7 +1391,7 @@ rbp_status rbp_code_destroy(rbp_code_t c) {
     for (DevBuf* b : {&c->row_ptr, &c->col_idx, &c->col_ptr, &c->csc_row, &c->rgrp, &c->rposp, &c->rposw, &c->rord, &c->vgrp,
                       &c->vord, &c->vdeg, &c->scheck, &c->scsc, &c->orow_ptr, &c->ocol_idx, &c->ocol_ptr,
                       &c->orow_idx, &c->thr, &c->lam, &c->lamp, &c->m1, &c->gtab, &c->lg, &c->queue, &c->gstate,
-                      &c->trace_hit, &c->spa_queue})
+                      &c->trace_hit, &c->spa_queue, &c->gapt})
         b->release();
     delete c;
     return RBP_OK;
@@ -1378,13 +1431,15 @@ rbp_status rbp_sample(rbp_code_t c, const double* priors, uint64_t shots, uint64
     a.csc_row = c->csc_row.as<int32_t>();
     a.ocol_ptr = c->ocol_ptr.as<int32_t>();
     a.orow_idx = c->orow_idx.as<int32_t>();
-    a.thr = c->thr.as<uint32_t>();
+    a.L = ceil_div(c->N, 64);
+    a.gap = c->gapt.as<uint32_t>();
+    a.acc = c->thr.as<uint32_t>();
     a.seed = seed;
     a.offset = shot_offset;
     a.syn = syndromes;
     a.obs = c->k > 0 ? obs : nullptr;
     a.err = errors;
-    const size_t lds = sizeof(uint32_t) * (size_t)kSampleWaves * (a.WM + a.WK);
+    const size_t lds = sizeof(uint32_t) * (size_t)kSampleWaves * (a.WM + a.WK + (errors ? a.WN : 0));
     if (lds > (size_t)kMaxLds) return fail(RBP_ERR_UNSUPPORTED, "detector/observable count too large for sampler");
     const uint64_t max_blocks = 1ull << 30;
     for (uint64_t done = 0; done < shots;) {
