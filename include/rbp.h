@@ -116,7 +116,10 @@ typedef struct {
  * Outputs (device): corrections_dev uint32[shots][ceil(N/32)] (the lowest
  * weight solution, or the last hard decision when no leg converged),
  * obs_pred_dev uint32[shots][ceil(k/32)] = O * correction (may be NULL when
- * k = 0), stats_dev rbp_shot_stats[shots] (may be NULL). */
+ * k = 0), stats_dev rbp_shot_stats[shots] (may be NULL).  Without a prior
+ * delta, batches of 8192 shots or more are decoded heaviest syndrome first (a
+ * counting sort on the device, into a per-handle buffer of 4 bytes per shot),
+ * so that the longest decodes do not finish last; no output depends on it. */
 rbp_status rbp_decode(rbp_code_t code, const double* priors, const uint32_t* syndromes_dev, uint64_t shots,
                       const rbp_relay_params* params, const float* prior_delta_dev, uint32_t* corrections_dev,
                       uint32_t* obs_pred_dev, rbp_shot_stats* stats_dev, void* stream);

@@ -216,6 +216,71 @@ __global__ void zero_u64_kernel(unsigned long long* p, int n) {
 }
 
 // ---------------------------------------------------------------------------
+// Shot order for rbp_decode: heaviest syndromes first.  A shot's decoding time
+// grows with its syndrome weight, and the batch ends when its slowest shot
+// ends; handing the heavy shots out first lets them overlap the light ones
+// instead of finishing last.  Counting sort on min(weight, 255), descending;
+// the order within a weight is arbitrary, which no output depends on.
+// ---------------------------------------------------------------------------
+constexpr int kOrderBins = 256;  // also the block size of the ordering kernels (one bin per thread)
+
+__device__ __forceinline__ int weight_bin(const uint32_t* row, int words) {
+    int w = 0;
+    for (int x = 0; x < words; ++x) w += __popc(row[x]);
+    return w < kOrderBins - 1 ? w : kOrderBins - 1;
+}
+
+// histogram of the batch: per-block counts in LDS, one global atomic per block
+// and non-empty bin
+__global__ void __launch_bounds__(256) order_hist_kernel(const uint32_t* syn, int words, uint64_t shots,
+                                                          uint32_t* hist) {
+    __shared__ uint32_t h[kOrderBins];
+    h[threadIdx.x] = 0u;
+    __syncthreads();
+    const uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s < shots) atomicAdd(&h[weight_bin(syn + s * words, words)], 1u);
+    __syncthreads();
+    if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// counts -> first position of each bin, heaviest bin first (one thread; 256 bins)
+__global__ void order_scan_kernel(uint32_t* hist) {
+    if (threadIdx.x != 0) return;
+    uint32_t run = 0;
+    for (int b = kOrderBins - 1; b >= 0; --b) {
+        const uint32_t c = hist[b];
+        hist[b] = run;
+        run += c;
+    }
+}
+
+// each block reserves a range per non-empty bin (one global atomic), then ranks
+// its shots inside the ranges with LDS atomics
+__global__ void __launch_bounds__(256) order_scatter_kernel(const uint32_t* syn, int words, uint64_t shots,
+                                                             uint32_t* cursor, uint32_t* order) {
+    __shared__ uint32_t cnt[kOrderBins];
+    __shared__ uint32_t base[kOrderBins];
+    cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    const uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    int bin = 0;
+    uint32_t rank = 0;
+    if (s < shots) {
+        bin = weight_bin(syn + s * words, words);
+        rank = atomicAdd(&cnt[bin], 1u);
+    }
+    __syncthreads();
+    const uint32_t c = cnt[threadIdx.x];
+    base[threadIdx.x] = c ? atomicAdd(&cursor[threadIdx.x], c) : 0u;
+    __syncthreads();
+    if (s < shots) order[base[bin] + rank] = (uint32_t)s;
+}
+
+__global__ void zero_u32_kernel(uint32_t* p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
 // Persistent Relay-BP
 //
 // A shot slot's state is one float per Tanner-graph edge slot, X[S], plus the
@@ -281,6 +346,7 @@ struct DecodeLaunch {
     int32_t n_models;
     const uint8_t* shot_code;
     const uint32_t* shot_index;
+    int32_t stats_by_row;  // statistics at the shot's row (rbp_decode) or at its ticket (rbp_decode_multi)
     uint64_t shots;
     const float* delta;
     rbp_shot_stats* stats;
@@ -853,7 +919,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                 st.reserved3 = 0;
                 st.t_start = t_start;
                 st.t_end = wall_clock64();
-                a.stats[s] = st;
+                a.stats[a.stats_by_row ? row : s] = st;
             }
         }
         __syncthreads();
@@ -1177,6 +1243,30 @@ static rbp_status launch_decode(rbp_code* const* cs, int n, DecodeLaunch& a, uin
     return RBP_OK;
 }
 
+// Batches smaller than this keep their own order (the four small launches
+// would cost more than the tail they save).  The learned path (a prior delta
+// per shot) keeps its order too: it measured slower when sorted.
+constexpr uint64_t kOrderMinShots = 8192;
+
+static rbp_status order_by_weight(rbp_code* c, const uint32_t* syn, uint64_t shots, hipStream_t stream) {
+    const unsigned blocks = (unsigned)((shots + 255) / 256);
+    rbp_status st = c->order.reserve(sizeof(uint32_t) * shots);
+    if (!st) st = c->ohist.reserve(sizeof(uint32_t) * kOrderBins);
+    if (st) return st;
+    const int words = ceil_div(c->M, 32);
+    uint32_t* hist = c->ohist.as<uint32_t>();
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, stream, hist, kOrderBins);
+    RBP_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(order_hist_kernel, dim3(blocks), dim3(256), 0, stream, syn, words, shots, hist);
+    RBP_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, stream, hist);
+    RBP_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, stream, syn, words, shots, hist,
+                       c->order.as<uint32_t>());
+    RBP_HIP_CHECK(hipGetLastError());
+    return RBP_OK;
+}
+
 static void fill_params(DecodeLaunch& a, const rbp_relay_params* p) {
     a.gamma0 = p->gamma0;
     a.T0 = p->pre_iter;
@@ -1391,7 +1481,7 @@ rbp_status rbp_code_destroy(rbp_code_t c) {
     for (DevBuf* b : {&c->row_ptr, &c->col_idx, &c->col_ptr, &c->csc_row, &c->rgrp, &c->rposp, &c->rposw, &c->rord, &c->vgrp,
                       &c->vord, &c->vdeg, &c->scheck, &c->scsc, &c->orow_ptr, &c->ocol_idx, &c->ocol_ptr,
                       &c->orow_idx, &c->thr, &c->lam, &c->lamp, &c->m1, &c->gtab, &c->lg, &c->queue, &c->gstate,
-                      &c->trace_hit, &c->spa_queue, &c->gapt})
+                      &c->trace_hit, &c->spa_queue, &c->gapt, &c->order, &c->ohist})
         b->release();
     delete c;
     return RBP_OK;
@@ -1480,6 +1570,12 @@ rbp_status rbp_decode(rbp_code_t c, const double* priors, const uint32_t* syndro
     a.delta = prior_delta;
     a.stats = stats;
     fill_params(a, params);
+    if (!prior_delta && shots >= kOrderMinShots && shots <= 0x7FFFFFFFull) {
+        st = order_by_weight(c, syndromes, shots, stream);
+        if (st) return st;
+        a.shot_index = c->order.as<uint32_t>();
+        a.stats_by_row = 1;
+    }
     rbp_code* cs[1] = {c};
     return launch_decode(cs, 1, a, shots, stream);
 }

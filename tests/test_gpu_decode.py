@@ -266,6 +266,26 @@ def test_outputs_do_not_depend_on_launch_shape(rbp):
     code.set_launch_config(0, 0, 0)
 
 
+@pytest.mark.parametrize("shots,slots", [(20000, 0), (8193, 7)])
+def test_heaviest_first_order_changes_no_output(rbp, shots, slots):
+    """Batches of 8192 shots or more are decoded heaviest syndrome first; every
+    output, statistics included (all but the two device timestamps, bytes 16 to
+    31), must equal the decode of the same shots in chunks below that size
+    (kept in their own order)."""
+    dem = dem_of("phen160")
+    code = rbp.Code.from_dem(dem)
+    params = rbp.RelayParams()
+    syn, _, _ = code.sample(dem.priors, shots, seed=808)
+    code.set_launch_config(0, 0, slots)
+    corr, obsp, st = code.decode(dem.priors, syn, params)
+    parts = [code.decode(dem.priors, syn[a:a + 4000].contiguous(), params) for a in range(0, shots, 4000)]
+    torch.cuda.synchronize()
+    code.set_launch_config(0, 0, 0)
+    np.testing.assert_array_equal(u32(corr), np.concatenate([u32(p[0]) for p in parts]))
+    np.testing.assert_array_equal(u32(obsp), np.concatenate([u32(p[1]) for p in parts]))
+    np.testing.assert_array_equal(st.cpu().numpy()[:, :16], np.concatenate([p[2].cpu().numpy()[:, :16] for p in parts]))
+
+
 # ----------------------------------------------------------------- edge cases
 def test_edge_cases(rbp):
     dem = dem_of("cc160")
