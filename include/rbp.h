@@ -41,7 +41,7 @@ typedef int32_t rbp_status;
 #define RBP_OK 0
 #define RBP_ERR_INVALID_ARG (-1) /* NULL pointer, bad enum or parameter range */
 #define RBP_ERR_SHAPE (-2)       /* inconsistent sizes, unsorted or duplicate CSC entries */
-#define RBP_ERR_UNSUPPORTED (-3) /* row degree outside [2, 32] (0 allowed), p outside (0, 0.5] */
+#define RBP_ERR_UNSUPPORTED (-3) /* row degree outside [2, 1024] (0 allowed), p outside (0, 0.5] */
 #define RBP_ERR_OOM (-4)         /* device or host allocation failed */
 #define RBP_ERR_HIP (-5)         /* HIP runtime error (message in rbp_last_error) */
 
@@ -51,7 +51,8 @@ typedef struct rbp_code* rbp_code_t;
  * H: M x N in CSC form, host arrays col_ptr[N+1], row_idx[nnz] (rows strictly
  * ascending within each column, 0 <= row < M).  O: k x N in CSC form
  * (obs_col_ptr[N+1], obs_row_idx), k may be 0 (then both may be NULL).
- * Every row of H must have degree 0 or 2..32.  The handle keeps device copies
+ * Every row of H must have degree 0 or 2..1024 (the sum-product decoder,
+ * rbp_decode_spa, takes rows of at most 32).  The handle keeps device copies
  * of H in CSR and CSC order and of O. */
 rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const int32_t* row_idx, int32_t k,
                            const int32_t* obs_col_ptr, const int32_t* obs_row_idx, rbp_code_t* out);

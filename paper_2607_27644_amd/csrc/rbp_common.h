@@ -67,6 +67,10 @@ struct LaunchCfg {
     int max_slots = 0;
 };
 
+// largest row degree of H the decoder accepts (rows above 32 edges take the
+// rolled check update)
+constexpr int kMaxRowDeg = 1024;
+
 }  // namespace rbp
 
 struct rbp_code {
@@ -78,7 +82,7 @@ struct rbp_code {
     int32_t S = 0;                      // edge slots (>= E)
     int32_t GR = 0, GV = 0, Np = 0;     // row groups, variable groups, 64 GV
     int32_t RB = 0;                     // length of the row position table
-    int32_t max_stored_row_deg = 0;     // largest stored row degree (<= 12, 16, 24 or 32)
+    int32_t max_stored_row_deg = 0;     // largest stored row degree (<= 12, 16, 24, 32, then multiples of 8)
     std::vector<int32_t> h_vord;        // host copy of vord
     // device copies
     rbp::DevBuf row_ptr, col_idx;       // CSR of H: row_ptr[M+1], col_idx[E]

@@ -512,7 +512,57 @@ __device__ __forceinline__ void check_row_d(const State<LDS> X, const int32_t* r
         check_row<D, false>(X, rp + o, wp + o, mp + o, sbit, first);
 }
 
-// stored row degrees: 2..12 exactly, larger rows padded to 16, 24 or 32 slots
+// Rows of more than 32 edges (circuit-level models) with D slots, D a multiple
+// of 8: the same operations as check_row in two rolled passes over 16-byte
+// chunks of the tables, the first for the two smallest magnitudes and the sign
+// product, the second re-reading each nu before its own slot is overwritten.
+template <bool MIXED, bool LDS>
+__device__ __forceinline__ void check_row_rolled(const State<LDS> X, const int32_t* rp, const int32_t* wp,
+                                                 const float* mp, int D, uint32_t sbit, bool first) {
+    const int Q = D >> 2;
+    const int4* r4 = reinterpret_cast<const int4*>(rp);
+    const int4* w4 = reinterpret_cast<const int4*>(MIXED ? wp : rp);
+    if (first) {
+        const float4* m4 = reinterpret_cast<const float4*>(mp);
+        for (int k = 0; k < Q; ++k) {
+            const int4 w = w4[k];
+            const float4 v = m4[k];
+            X.st((uint32_t)w.x, __uint_as_float(__float_as_uint(v.x) | sbit));
+            X.st((uint32_t)w.y, __uint_as_float(__float_as_uint(v.y) | sbit));
+            X.st((uint32_t)w.z, __uint_as_float(__float_as_uint(v.z) | sbit));
+            X.st((uint32_t)w.w, __uint_as_float(__float_as_uint(v.w) | sbit));
+        }
+        return;
+    }
+    uint32_t min1 = 0x7f800000u, min2 = 0x7f800000u, sgn = sbit;
+    for (int k = 0; k < Q; ++k) {
+        const int4 v = r4[k];
+        const uint32_t n[4] = {__float_as_uint(X.ld((uint32_t)v.x)), __float_as_uint(X.ld((uint32_t)v.y)),
+                               __float_as_uint(X.ld((uint32_t)v.z)), __float_as_uint(X.ld((uint32_t)v.w))};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t av = n[r] & 0x7fffffffu;
+            sgn ^= n[r];
+            min2 = umed3(min1, min2, av);
+            min1 = min1 < av ? min1 : av;
+        }
+    }
+    for (int k = 0; k < Q; ++k) {
+        const int4 v = r4[k];
+        const int4 w = w4[k];
+        const uint32_t n[4] = {__float_as_uint(X.ld((uint32_t)v.x)), __float_as_uint(X.ld((uint32_t)v.y)),
+                               __float_as_uint(X.ld((uint32_t)v.z)), __float_as_uint(X.ld((uint32_t)v.w))};
+        const uint32_t wo[4] = {(uint32_t)w.x, (uint32_t)w.y, (uint32_t)w.z, (uint32_t)w.w};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t mag = ((n[r] & 0x7fffffffu) == min1) ? min2 : min1;
+            X.st(wo[r], __uint_as_float(mag | ((sgn ^ n[r]) & 0x80000000u)));
+        }
+    }
+}
+
+// stored row degrees: 2..12 exactly, 13..32 padded to 16, 24 or 32 slots,
+// larger rows to a multiple of 8 (rolled)
 template <int RD, bool LDS>
 __device__ __forceinline__ void check_dispatch(const State<LDS> X, const int32_t* rp, const int32_t* wp,
                                                const float* mp, int lane, int dg, bool mixed, uint32_t sbit,
@@ -526,7 +576,13 @@ __device__ __forceinline__ void check_dispatch(const State<LDS> X, const int32_t
             if constexpr (RD > 12) {
                 switch (dg) {
                     RBP_ROW(16) RBP_ROW(24) RBP_ROW(32)
-                    default: break;
+                    default: {
+                        const uint32_t o = (uint32_t)lane * (uint32_t)dg;
+                        if (mixed)
+                            check_row_rolled<true>(X, rp + o, wp + o, mp + o, dg, sbit, first);
+                        else
+                            check_row_rolled<false>(X, rp + o, wp + o, mp + o, dg, sbit, first);
+                    } break;
                 }
             }
             break;
@@ -1309,9 +1365,9 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
     }
     int maxrow = 0;
     for (int i = 0; i < M; ++i) {
-        if (deg[i] == 1 || deg[i] > 32)
+        if (deg[i] == 1 || deg[i] > kMaxRowDeg)
             return fail(RBP_ERR_UNSUPPORTED, "row " + std::to_string(i) + " has degree " + std::to_string(deg[i]) +
-                                                 " (supported: 0 or 2..32)");
+                                                 " (supported: 0 or 2.." + std::to_string(kMaxRowDeg) + ")");
         maxrow = std::max(maxrow, deg[i]);
     }
     int nnzO = 0;
@@ -1373,7 +1429,8 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
         }
     }
     // Row groups: checks sorted the same way; rows of up to 12 edges are stored
-    // at their group's degree, larger ones padded to 16, 24 or 32 slots.
+    // at their group's degree, up to 32 padded to 16, 24 or 32 slots, larger
+    // ones to a multiple of 8.
     const int GR = ceil_div(M, 64);
     std::vector<int32_t> rperm(M), rord(64 * (size_t)GR, -1), rinv(M), rgrp(4 * (size_t)GR, 0);
     for (int i = 0; i < M; ++i) rperm[i] = i;
@@ -1386,7 +1443,7 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
     int maxstored = 0;
     for (int g = 0; g < GR; ++g) {
         const int dmax = deg[rord[64 * g]];
-        const int dst = dmax <= 12 ? dmax : dmax <= 16 ? 16 : dmax <= 24 ? 24 : 32;
+        const int dst = dmax <= 12 ? dmax : dmax <= 16 ? 16 : dmax <= 24 ? 24 : dmax <= 32 ? 32 : (dmax + 7) & ~7;
         bool mixed = false;
         for (int l = 0; l < 64; ++l) {
             const int i = rord[64 * g + l];

@@ -520,6 +520,8 @@ rbp_status rbp_decode_spa(rbp_code_t c, const float* llr, uint64_t shots, const 
         const int groups = std::max(c->GR, c->GV);
         waves = std::min(4, std::max(1, (groups + 2) / 3));
     }
+    if (c->max_stored_row_deg > 32)
+        return fail(RBP_ERR_UNSUPPORTED, "the sum-product decoder takes rows of at most 32 edges");
     void (*kern)(SpaLaunch) = c->max_stored_row_deg <= 12 ? spa_kernel<12> : spa_kernel<32>;
     RBP_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                       lds));

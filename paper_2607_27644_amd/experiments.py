@@ -23,6 +23,12 @@ names:
              long phenomenological memory experiment against one global decode:
              LER, throughput and the single-shot latency of one window
              (Sec. 6.1 latency discussion)
+  circuit    circuit-level memory experiments (d rounds of the greedy-AOD
+             syndrome extraction, Sec. 7.1 noise model, DEM sizes of Table
+             "decoding latency") with the relay intervals of Table "relay gamma
+             intervals": batched throughput and service times, sequential
+             single-shot latency, the all-legs worst case, block LER, per code
+             and memory basis
   awgn       block error rate of the classical ZSZ-2BGA codes over BPSK-AWGN
              against E_b/N_0, sum-product BP (numerics appendix, "classical
              channel coding"), with the decoder's throughput and the Shannon
@@ -39,7 +45,7 @@ import time
 import numpy as np
 import torch
 
-from . import autotune, learned, rbp, stats, window, workloads
+from . import autotune, circuits, learned, rbp, stats, window, workloads
 
 
 def _timed(fn, repeats: int = 3):
@@ -149,6 +155,70 @@ def latency(name: str, shots: int = 300, all_shots: int = 100, seed: int = 31) -
     return {"model": {"name": name, "M": dem.M, "N": dem.N, "nnz": dem.nnz},
             "sequential_us": stats.percentiles(np.array(lat)),
             "all_legs_us": stats.percentiles(np.array(lat_all)), "launch": code.launch_config()}
+
+
+# Table "relay gamma intervals" (App. "more numerics"): [gamma_min, gamma_max]
+# of each code's circuit-level memory decoding
+CIRCUIT_GAMMA = {"ZSZ-LP-160": (-0.15, 0.61), "ZSZ-LP-240": (-0.1, 0.6), "ZSZ-LP-320": (-0.16, 0.66),
+                 "ZSZ-LP-390": (-0.16, 0.7), "ZSZ-LP-550": (-0.12, 0.62)}
+
+
+def _seq_latency(code, priors, syn, params, n: int) -> np.ndarray:
+    out = code.decode(priors, syn[:1], params)
+    torch.cuda.synchronize()
+    lat = []
+    for i in range(n):
+        t0 = time.perf_counter()
+        code.decode(priors, syn[i:i + 1], params, out=out)
+        torch.cuda.synchronize()
+        lat.append(1e6 * (time.perf_counter() - t0))
+    return np.array(lat)
+
+
+def circuit_exp(codes, p: float = 1e-3, shots: int = 100000, seq_shots: int = 300, all_shots: int = 3,
+                num_sets: int = 1000, bases: str = "XZ", seed: int = 61, tune: bool = True) -> dict:
+    import sys
+    rows = []
+    for name in codes:
+        gmin, gmax = CIRCUIT_GAMMA[name]
+        params = rbp.RelayParams(num_sets=num_sets, gamma_min=gmin, gamma_max=gmax)
+        for basis in bases:
+            t0 = time.perf_counter()
+            dem = circuits.memory_dem(name, basis, p)
+            build_s = time.perf_counter() - t0
+            code = rbp.Code.from_dem(dem)
+            tr = autotune.tune(code, dem.H, dem.priors, params, shots=4000, use_cache=False) if tune else None
+            syn, obs, _ = code.sample(dem.priors, shots, seed)
+            ms, out = _timed(lambda: code.decode(dem.priors, syn, params), repeats=2)
+            r = _summary(dem, obs, out[1], out[2], shots, ms)
+            st = rbp.stats_to_numpy(out[2])
+            it = st["iters"].astype(np.float64).sum()
+            print(f"[circuit] {name} {basis}: batched {r['shots_per_s']:.0f} shots/s", file=sys.stderr, flush=True)
+            # one shot per launch: the widest workgroup (16 waves) on the shot
+            tuned = code.launch_config()
+            code.set_launch_config(16, 2, 0)
+            seq = _seq_latency(code, dem.priors, syn, params, seq_shots)
+            # the all-legs worst case: num_sets + 1 legs on the first shots with a
+            # nonzero syndrome
+            allp = dataclasses.replace(params, stopping_criterion=1)
+            nzs = [i for i in range(min(shots, 1000)) if bool(syn[i].any())][:all_shots]
+            lat_all = _seq_latency(code, dem.priors, syn[nzs].contiguous(), allp, len(nzs))
+            code.set_launch_config(tuned["waves_per_shot"], tuned["state"], 0)
+            print(f"[circuit] {name} {basis}: sequential mean {seq.mean():.0f} us, all-legs "
+                  f"{lat_all.mean() / 1e3:.1f} ms", file=sys.stderr, flush=True)
+            r.update({"code": name, "basis": basis, "p": p, "rounds": dem.rounds,
+                      "dem": {"N_det": dem.M, "N_loc": dem.N, "nnz": dem.nnz, "k": dem.k,
+                              "max_row_deg": int(dem.H.sum(axis=1).max()),
+                              "paper_size": circuits.PAPER_DEM_SIZES.get(name)},
+                      "build_s": build_s, "relay": dataclasses.asdict(params), "tuned": tr,
+                      "launch": tuned, "sequential_launch": {"waves_per_shot": 16, "state": 2},
+                      "nonconverged": int((st["converged"] == 0).sum()),
+                      "algorithmic_GBps": it * (8 * dem.nnz + 8 * dem.N) / (ms * 1e-3) / 1e9,
+                      "sequential_us": stats.percentiles(seq),
+                      "all_legs_ms": stats.percentiles(lat_all / 1e3)})
+            rows.append(r)
+            code.close()
+    return {"experiment": "circuit-level memory", "rows": rows}
 
 
 def learned_exp(name: str, pairs: int, eval_shots: int, p_eval, p_lo: float, p_hi: float) -> dict:
@@ -358,6 +428,12 @@ def main():
     ap.add_argument("--min-errors", type=int, default=100)
     ap.add_argument("--rounds", type=int, default=30)
     ap.add_argument("--p-window", type=float, default=8e-3)
+    ap.add_argument("--circuit-codes", default="ZSZ-LP-320,ZSZ-LP-390,ZSZ-LP-550")
+    ap.add_argument("--p-circuit", type=float, default=1e-3)
+    ap.add_argument("--seq-shots", type=int, default=300)
+    ap.add_argument("--all-shots", type=int, default=3)
+    ap.add_argument("--num-sets", type=int, default=1000)
+    ap.add_argument("--bases", default="XZ")
     a = ap.parse_args()
     torch.cuda.set_device(0)
     if a.what == "multi":
@@ -376,6 +452,9 @@ def main():
         r = windowed(rounds=a.rounds, p=a.p_window, shots=a.shots)
     elif a.what == "awgn":
         r = awgn_fer(a.codes.split(","), [float(x) for x in a.ebn0.split(",")], a.max_frames, a.min_errors)
+    elif a.what == "circuit":
+        r = circuit_exp(a.circuit_codes.split(","), a.p_circuit, a.shots, a.seq_shots, a.all_shots, a.num_sets,
+                        a.bases)
     elif a.what == "sweep":
         r = ler_sweep(a.model, [float(x) for x in a.ps.split(",")], a.shots, p_fit_max=a.p_fit_max)
     else:

@@ -2,7 +2,9 @@
 
 This module builds the *inputs* of the Monte-Carlo decoding path; it holds none of
 the sampling or decoding arithmetic.  Both the HIP path and the CPU oracle take
-their matrices from here, so it imports nothing else from this package.
+their matrices from here, so it imports nothing else from this package except
+``circuits`` (circuit-level models, built on this module) for the named
+circuit workloads.
 
 Contents
 --------
@@ -435,6 +437,8 @@ def workload(name: str) -> DEM:
     phen840    [[840,168]] code, T = 12, 1e-3               (4032 x 13776)
     hgp56      seeded HGP n1 = 56, T = 12, 1e-3             (18816 x 64288)
     tiny60     [[60,12,6]] code capacity (tests)
+    circ320x   circuit-level d-round memory of ZSZ-LP-320 in basis X (x or z;
+               160, 240, 320, 390, 550), p = 1e-3      (1920 x 28992 for 320)
     """
     if name == "cc160":
         return code_capacity_dem(zsz_lp("ZSZ-LP-160"), 0.01)
@@ -444,6 +448,9 @@ def workload(name: str) -> DEM:
         num = name[4:]
         T = 12 if num == "840" else 9
         return phenomenological_dem(zsz_lp(f"ZSZ-LP-{num}"), T, 1e-3)
+    if name.startswith("circ"):
+        from . import circuits
+        return circuits.memory_dem(f"ZSZ-LP-{name[4:-1]}", name[-1].upper(), 1e-3)
     if name.startswith("hgp"):
         n1 = int(name[3:])
         T = 12 if n1 >= 56 else 9

@@ -1,0 +1,150 @@
+"""GPU parity on circuit-level detector error models (rows of 20 to 100 edges,
+decoded by the rolled check update; per-slot state in device memory).
+
+The bar is the decode parity suite's: traced messages and marginals within
+1e-5 relative (expected bitwise equal), corrections identical on >= 99.9 % of
+shots (here: all but at most one of the shots the oracle decodes), and equal
+statistics on the identical shots.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2607_27644_amd import circuits as C  # noqa: E402
+from paper_2607_27644_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+_DEMS = {}
+
+
+@pytest.fixture(scope="module")
+def rbp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_27644_amd import rbp as mod
+    return mod
+
+
+def dem_of(name):
+    if name not in _DEMS:
+        _DEMS[name] = W.workload(name)
+    return _DEMS[name]
+
+
+def oparams(p):
+    return oracle.RelayParams(**{k: getattr(p, k) for k in oracle.RelayParams.__dataclass_fields__})
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def rel_close(a, b, rtol=1e-5, atol=1e-6):
+    return np.all(np.abs(a - b) <= rtol * np.maximum(np.abs(a), np.abs(b)) + atol)
+
+
+def compare(rbp, dem, syn_np, out, ref, max_diff):
+    corr, obsp, st = out
+    s = rbp.stats_to_numpy(st)
+    same = (u32(corr) == ref["corrections"]).all(axis=1)
+    assert (~same).sum() <= max_diff, (~same).sum()
+    o = u32(obsp)[:, : ref["obs_pred"].shape[1]]
+    assert np.array_equal(o[same], ref["obs_pred"][same])
+    for key in ("converged", "nconv", "legs", "iters"):
+        assert np.array_equal(s[key][same], ref[key][same]), key
+    e = W.unpack_bits(u32(corr), dem.N)
+    conv = s["converged"] == 1
+    resyn = (e.astype(np.int64) @ dem.H.T.astype(np.int64)) % 2
+    assert np.array_equal(resyn[conv], W.unpack_bits(syn_np, dem.M)[conv])
+    return same
+
+
+def test_circuit_model_shape(rbp):
+    dem = dem_of("circ160x")
+    code = rbp.Code.from_dem(dem)
+    info = code.info()
+    assert info["max_row_deg"] > 32
+    code.decode(dem.priors, code.sample(dem.priors, 64, seed=1)[0], rbp.RelayParams())
+    torch.cuda.synchronize()
+    assert code.launch_config()["state"] == 2
+
+
+def test_traced_messages_circuit(rbp):
+    dem = dem_of("circ160x")
+    code = rbp.Code.from_dem(dem)
+    g = oracle.Graph(dem.H, dem.O)
+    params = rbp.RelayParams(num_sets=4)
+    osyn, _, _ = oracle.sample(g, dem.priors, 40, seed=91)
+    nz = [s for s in range(40) if osyn[s].any()][:4]
+    syn_dev = torch.from_numpy(osyn.view(np.int32)).cuda()
+    checked = 0
+    for s in nz:
+        for leg, t in [(0, 1), (0, 2), (0, 7), (0, 30), (1, 1), (1, 2), (2, 5)]:
+            ref = oracle.trace(g, dem.priors, osyn[s], oparams(params), leg=leg, t=t)
+            got = code.trace(dem.priors, syn_dev[s].contiguous(), params, leg=leg, t=t)
+            assert (ref is None) == (got is None), (s, leg, t)
+            if ref is None:
+                continue
+            assert rel_close(got[0], ref[0]), (s, leg, t)
+            assert rel_close(got[1], ref[1]), (s, leg, t)
+            checked += 1
+    assert checked >= 8
+
+
+@pytest.mark.parametrize("name,p", [("ZSZ-LP-160", 1e-3), ("ZSZ-LP-160", 3e-3)])
+@pytest.mark.parametrize("basis", ["X", "Z"])
+def test_circuit_decode_matches_oracle(rbp, name, p, basis):
+    dem = C.memory_dem(name, basis, p)
+    code = rbp.Code.from_dem(dem)
+    params = rbp.RelayParams()
+    shots = 300 if p < 2e-3 else 160
+    syn, obs, _ = code.sample(dem.priors, shots, seed=4000 + int(p * 1e4))
+    out = code.decode(dem.priors, syn, params)
+    torch.cuda.synchronize()
+    syn_np = u32(syn)
+    ref = oracle.decode(oracle.Graph(dem.H, dem.O), dem.priors, syn_np, oparams(params), nthreads=16)
+    compare(rbp, dem, syn_np, out, ref, max_diff=0)
+
+
+def test_circuit_launch_shapes_agree(rbp):
+    dem = dem_of("circ160z")
+    code = rbp.Code.from_dem(dem)
+    params = rbp.RelayParams(num_sets=20)
+    syn, _, _ = code.sample(dem.priors, 700, seed=12)
+    base = None
+    for waves, slots in [(4, 0), (8, 0), (16, 0), (16, 5), (2, 33)]:
+        code.set_launch_config(waves, 2, slots)
+        corr, obsp, st = code.decode(dem.priors, syn, params)
+        torch.cuda.synchronize()
+        s = rbp.stats_to_numpy(st)
+        cur = (u32(corr), u32(obsp), s["converged"], s["legs"], s["iters"])
+        if base is None:
+            base = cur
+        else:
+            for a, b in zip(base, cur):
+                assert np.array_equal(a, b), (waves, slots)
+    code.set_launch_config(0, 0, 0)
+
+
+def test_circuit_full_size_sampled(rbp):
+    """ZSZ-LP-320 X memory over d = 14 rounds (1920 x 28992, the paper's DEM
+    size), 20000 shots in one launch (heaviest syndromes first); the oracle
+    decodes 48 shots spread over the batch."""
+    dem = dem_of("circ320x")
+    code = rbp.Code.from_dem(dem)
+    params = rbp.RelayParams()
+    shots = 20000
+    syn, obs, _ = code.sample(dem.priors, shots, seed=2026)
+    corr, obsp, st = code.decode(dem.priors, syn, params)
+    torch.cuda.synchronize()
+    idx = np.linspace(0, shots - 1, 48).astype(int)
+    syn_np = u32(syn)[idx]
+    ref = oracle.decode(oracle.Graph(dem.H, dem.O), dem.priors, syn_np, oparams(params), nthreads=16)
+    ti = torch.from_numpy(idx).cuda()
+    sub = (corr[ti], obsp[ti], st[ti])
+    compare(rbp, dem, syn_np, sub, ref, max_diff=1)
+    s = rbp.stats_to_numpy(st)
+    assert (s["converged"] == 1).mean() > 0.999
