@@ -163,6 +163,43 @@ rbp_status rbp_set_launch_config(rbp_code_t code, const rbp_launch_config* cfg);
 /* Launch shape rbp_decode would use for this handle (after defaults). */
 rbp_status rbp_get_launch_config(rbp_code_t code, rbp_launch_config* cfg, int32_t* slots, int32_t* lds_bytes);
 
+/* Latency mode: decode shots one after another, each by several workgroups
+ * together (the paper's sequential single-shot decoding, Sec. 7.1 Table
+ * "decoding latency").  The row and variable groups of every sweep are spread
+ * over all participating wavefronts; the sweeps are separated by grid
+ * barriers.  Results are those of rbp_decode without a prior delta
+ * (identical arithmetic); outputs and statistics as there, shot s at row s.
+ * workgroups: participating workgroups (0: one per CU of one XCD, CUs / 8).
+ * stride: participants are the workgroups whose index is a multiple of it
+ * (0: 8 while workgroups * 8 <= CUs, which keeps them on one XCD, else 1).
+ * waves: wavefronts per workgroup, 1..8 (0: 8).  spin_limit: bound on the polls of
+ * one barrier wait (0: 2^21, about 2 s); when a wait expires the launch stops
+ * at the next barrier, leaving later shots unwritten, and rbp_coop_aborted
+ * reports it.  phantom (tests of that path only, else 0): the barriers wait
+ * for this many extra workgroups that never arrive, so every wait expires.
+ * When all participants run on one XCD (checked at the start of each launch
+ * from the hardware XCD id) the barriers only wait for stores and invalidate
+ * the L1, since the participants share one L2; otherwise, or with
+ * device_fences = 1, they use device-scope fences (L2 write-back and
+ * invalidation).
+ * Uses per-handle scratch (one shot's state, bit arrays and barrier words).
+ * Returns UNSUPPORTED when the workgroups cannot all be resident (cooperative
+ * launch). */
+typedef struct {
+    int32_t workgroups;
+    int32_t stride;
+    int32_t waves;
+    uint32_t spin_limit;
+    int32_t phantom;
+    int32_t device_fences;
+} rbp_coop_params;
+rbp_status rbp_decode_coop(rbp_code_t code, const double* priors, const uint32_t* syndromes_dev, uint64_t shots,
+                           const rbp_relay_params* params, const rbp_coop_params* coop, uint32_t* corrections_dev,
+                           uint32_t* obs_pred_dev, rbp_shot_stats* stats_dev, void* stream);
+/* 1 in *aborted if the last rbp_decode_coop launch on this handle stopped on an
+ * expired barrier wait, else 0.  Synchronizes the stream. */
+rbp_status rbp_coop_aborted(rbp_code_t code, void* stream, int32_t* aborted);
+
 /* Debug trace of one shot: the marginals M (float[N]) and check-to-variable
  * messages (float[nnz], CSC edge order of H) right after iteration t (>= 1) of
  * leg `leg` of phase `phase` (0 plain Relay-BP, 1 proposal leg).  syndrome_dev

@@ -111,6 +111,7 @@ struct rbp_code {
     int32_t gtab_R = -1;
     rbp::DevBuf queue;                  // work counter of the persistent decoder
     rbp::DevBuf order, ohist;           // shot order of rbp_decode (heaviest syndrome first) and its histogram
+    rbp::DevBuf coop;                   // rbp_decode_coop: parity, best solution, barrier words
     rbp::DevBuf spa_queue;              // work counter of the sum-product decoder
     rbp::DevBuf gstate;                 // per-slot state when it does not fit in LDS
     rbp::DevBuf trace_hit;

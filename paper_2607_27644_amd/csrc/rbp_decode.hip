@@ -983,6 +983,409 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
 }
 
 // ---------------------------------------------------------------------------
+// Cooperative single-shot Relay-BP (latency mode)
+//
+// One shot at a time, decoded by G workgroups together: the row and variable
+// groups of each sweep are spread over all G x W waves, so a shot gets the
+// memory bandwidth of G CUs instead of one.  The shot's state (messages,
+// marginals), the parity bits, the unsatisfied-check count and the weight live
+// in device memory; the sweeps are separated by grid barriers (two per
+// iteration).  The per-group arithmetic is the persistent kernel's (the same
+// check_dispatch / var_dispatch calls on the same operands in the same order),
+// so results are identical; only the distribution over waves differs.
+//
+// Participants are the workgroups with index % stride == 0 (stride 8 keeps
+// them on one XCD when workgroups are dealt round-robin to the 8 XCDs, so they
+// share one L2; correctness does not depend on it).  The launch is
+// cooperative, so all workgroups are resident.  A barrier wait polls a
+// generation counter at most spin_limit times; on expiry it raises the abort
+// flag and every workgroup leaves at its next barrier, so no launch can hang.
+// ---------------------------------------------------------------------------
+struct CoopShared {
+    unsigned int arrive, gen, abort, xmask;  // xmask: XCDs of the participants
+    int32_t count, pad2;
+    double W;
+};
+
+struct CoopLaunch {
+    DecodeModel m;
+    uint64_t shots;
+    rbp_shot_stats* stats;
+    float* X;        // the shot's state: X[S + 2], marginals at X + Smax + 4
+    int32_t Smax;
+    uint32_t* par;   // [WM] parity of the current hard decision
+    uint32_t* bestp; // [Np / 32] best solution by position
+    uint32_t* best;  // [WN] best solution by variable
+    CoopShared* sh;
+    int32_t nwg, stride;
+    uint32_t arrivals;  // arrivals that complete a barrier (nwg, more only to test expiry)
+    uint32_t spin_limit;
+    int32_t force_device;  // device-scope fences even on one XCD (for comparison)
+    int32_t T0, Tr, R, S, crit;
+    int32_t off_sig, off_sigp, off_obs, off_misc;
+};
+
+struct CoopMisc {
+    int32_t red, flag, pad0, pad1;
+};
+
+// Ordering of the shot's state around a barrier.  When every participant
+// runs on one XCD (`local`), they share that XCD's L2 and the vector L1 is
+// write-through: waiting for this wave's stores, then an agent-scope
+// invalidate (which drops the L1 and only non-coherent L2 lines; a
+// workgroup-scope one leaves the L1, coherent at that scope, in place)
+// suffice, and the L2 keeps the state.  Otherwise device-scope fences also
+// write the L2 back before the barrier.
+__device__ __forceinline__ void coop_release(bool local) {
+    if (local)
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    else
+        __threadfence();
+}
+
+__device__ __forceinline__ void coop_acquire(bool local) {
+    if (local)
+        asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
+    else
+        __threadfence();
+}
+
+// grid barrier over the participating workgroups; false if the launch aborted
+__device__ __forceinline__ bool grid_sync(CoopShared* sh, unsigned nwg, unsigned& gen, uint32_t spin_limit,
+                                          CoopMisc* ms, bool local) {
+    coop_release(local);  // this wave's stores are complete (and visible to the other participants)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        if (__hip_atomic_load(&sh->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+            ok = 0;
+        } else {
+            const unsigned my = gen;
+            if (atomicAdd(&sh->arrive, 1u) == nwg - 1u) {
+                atomicExch(&sh->arrive, 0u);
+                coop_release(local);
+                atomicAdd(&sh->gen, 1u);
+            } else {
+                uint32_t spins = 0;
+                while (__hip_atomic_load(&sh->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == my) {
+                    if (++spins > spin_limit) {
+                        atomicExch(&sh->abort, 1u);
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(4);
+                }
+            }
+        }
+        ms->flag = ok;
+        // see the other workgroups' stores: the L1 is shared by the CU's waves,
+        // which load again only after the barrier below
+        coop_acquire(local);
+    }
+    __syncthreads();
+    const bool ok = ms->flag != 0;
+    ++gen;
+    return ok;
+}
+
+constexpr int kQuarterRegs = 32;  // edges per lane kept in registers (rows up to 128)
+
+// the four lanes of a row exchange their two smallest magnitudes and sign
+// products: the two smallest of the row are the two smallest of the four pairs
+__device__ __forceinline__ void quarter_combine(uint32_t& min1, uint32_t& min2, uint32_t& sgn) {
+#pragma unroll
+    for (int d = 1; d <= 2; d <<= 1) {
+        const uint32_t b1 = (uint32_t)__shfl_xor((int)min1, d, 64);
+        const uint32_t b2 = (uint32_t)__shfl_xor((int)min2, d, 64);
+        sgn ^= (uint32_t)__shfl_xor((int)sgn, d, 64);
+        const uint32_t hi = min1 < b1 ? b1 : min1;
+        const uint32_t lo2 = min2 < b2 ? min2 : b2;
+        min1 = min1 < b1 ? min1 : b1;
+        min2 = hi < lo2 ? hi : lo2;
+    }
+}
+
+// A quarter of a row group of stored degree D > 32 (multiple of 8): rows
+// q*16 + (lane >> 2) of the group, four lanes per row, lane k of a row taking
+// the edges k, k + 4, ...  The lanes combine their two smallest magnitudes and
+// sign products (quarter_combine), so every message equals the one-lane
+// update's.
+template <bool MIXED>
+__device__ __forceinline__ void check_quarter(const State<false> X, const int32_t* rp, const int32_t* wp,
+                                              const float* mp, int lane, int q, int D, uint32_t sbit, bool first) {
+    const int k = lane & 3;
+    const uint32_t o = (uint32_t)(q * 16 + (lane >> 2)) * (uint32_t)D;
+    const int32_t* r = rp + o;
+    const int32_t* w = (MIXED ? wp : rp) + o;
+    if (first) {
+        const float* mm = mp + o;
+        for (int p = k; p < D; p += 4) X.st((uint32_t)w[p], __uint_as_float(__float_as_uint(mm[p]) | sbit));
+        return;
+    }
+    uint32_t min1 = 0x7f800000u, min2 = 0x7f800000u, sgn = 0u;
+    if (D <= 4 * kQuarterRegs) {
+        // rows of up to 128 edges: the lane's messages are gathered at once and
+        // kept in registers for the write pass
+        uint32_t pos[kQuarterRegs], nv[kQuarterRegs];
+#pragma unroll
+        for (int i = 0; i < kQuarterRegs; ++i) pos[i] = k + 4 * i < D ? (uint32_t)r[k + 4 * i] : 0u;
+#pragma unroll
+        for (int i = 0; i < kQuarterRegs; ++i) nv[i] = k + 4 * i < D ? __float_as_uint(X.ld(pos[i])) : 0x7f800000u;
+#pragma unroll
+        for (int i = 0; i < kQuarterRegs; ++i) {
+            const uint32_t av = nv[i] & 0x7fffffffu;
+            sgn ^= nv[i];
+            min2 = umed3(min1, min2, av);
+            min1 = min1 < av ? min1 : av;
+        }
+        quarter_combine(min1, min2, sgn);
+        sgn ^= sbit;
+#pragma unroll
+        for (int i = 0; i < kQuarterRegs; ++i) {
+            if (k + 4 * i < D) {
+                const uint32_t mag = ((nv[i] & 0x7fffffffu) == min1) ? min2 : min1;
+                X.st(MIXED ? (uint32_t)w[k + 4 * i] : pos[i], __uint_as_float(mag | ((sgn ^ nv[i]) & 0x80000000u)));
+            }
+        }
+        return;
+    }
+    for (int p = k; p < D; p += 4) {
+        const uint32_t n = __float_as_uint(X.ld((uint32_t)r[p]));
+        const uint32_t av = n & 0x7fffffffu;
+        sgn ^= n;
+        min2 = umed3(min1, min2, av);
+        min1 = min1 < av ? min1 : av;
+    }
+    quarter_combine(min1, min2, sgn);
+    sgn ^= sbit;
+    for (int p = k; p < D; p += 4) {
+        const uint32_t n = __float_as_uint(X.ld((uint32_t)r[p]));
+        const uint32_t mag = ((n & 0x7fffffffu) == min1) ? min2 : min1;
+        X.st((uint32_t)w[p], __uint_as_float(mag | ((sgn ^ n) & 0x80000000u)));
+    }
+}
+
+template <int RD>
+__global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (blockIdx.x % (unsigned)a.stride) return;
+    const int rank = (int)(blockIdx.x / (unsigned)a.stride);
+    if (rank >= a.nwg) return;
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63;
+    const int wid = uniform(tid >> 6), nw = nth >> 6;
+    const int gw = rank * nw + wid, GW = a.nwg * nw;
+    const DecodeModel& m = a.m;
+    State<false> X;
+    X.g = a.X;
+    float* Mg = a.X + a.Smax + 4;
+    uint32_t* sig = reinterpret_cast<uint32_t*>(smem + a.off_sig);
+    uint32_t* sigp = reinterpret_cast<uint32_t*>(smem + a.off_sigp);
+    uint32_t* obw = reinterpret_cast<uint32_t*>(smem + a.off_obs);
+    CoopMisc* ms = reinterpret_cast<CoopMisc*>(smem + a.off_misc);
+    CoopShared* sh = a.sh;
+    const unsigned nwg = a.arrivals;
+    unsigned gen = 0;
+    const int WM = m.WM, WN = m.WN;
+    // which XCDs the participants run on (hardware register XCC_ID, bits 3:0)
+    if (tid == 0) atomicOr(&sh->xmask, 1u << (__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u));
+    if (!grid_sync(sh, nwg, gen, a.spin_limit, ms, false)) return;
+    const bool local =
+        __popc(__hip_atomic_load(&sh->xmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 1 && !a.force_device;
+
+    for (uint64_t s = 0; s < a.shots; ++s) {
+        const uint64_t t_start = wall_clock64();
+        // ---- set-up: every workgroup keeps the syndrome and its row-group
+        // ballots in LDS; rank 0 resets the shared arrays
+        if (tid == 0) ms->red = 0;
+        __syncthreads();
+        int pc = 0;
+        for (int w = tid; w < WM; w += nth) {
+            const uint32_t v = m.syn[s * WM + w];
+            sig[w] = v;
+            pc += __popc(v);
+            if (rank == 0) a.par[w] = v;
+        }
+        if (rank == 0) {
+            for (int w = tid; w < WN; w += nth) a.best[w] = 0u;
+            for (int w = tid; w < m.WK; w += nth) obw[w] = 0u;
+            if (tid == 0) {
+                sh->count = 0;
+                sh->W = 0.0;
+                X.st(4u * (uint32_t)m.S, INFINITY);  // read-only padding cell
+            }
+        }
+        if (pc) atomicAdd(&ms->red, pc);
+        __syncthreads();
+        const int base = uniform(ms->red);
+        for (int g = wid; g < m.GR; g += nw) {
+            const int i = m.rord[g * 64 + lane];
+            const bool b = i >= 0 && ((sig[i >> 5] >> (i & 31)) & 1u);
+            const unsigned long long bb = __ballot(b);
+            if (lane == 0) {
+                sigp[2 * g] = (uint32_t)bb;
+                sigp[2 * g + 1] = (uint32_t)(bb >> 32);
+            }
+        }
+        for (int g = gw; g < m.GV; g += GW) Mg[g * 64 + lane] = ldg(m.lamp, (uint32_t)(g * 64 + lane));
+        if (!grid_sync(sh, nwg, gen, a.spin_limit, ms, local)) return;
+
+        int nconv = 0, legs = 0, iters = 0, path = 0;
+        bool x_mu1 = false, have_best = false;
+        double bestW = 0.0;
+        if (base == 0) {
+            path = 3;
+            have_best = true;
+        } else {
+            for (int leg = 0; leg <= a.R; ++leg) {
+                const int T = leg == 0 ? a.T0 : a.Tr;
+                const float2* lgl = m.lg + (int64_t)leg * m.Np;
+                bool conv = false;
+                ++legs;
+                for (int t = 1; t <= T; ++t) {
+                    const bool first_plain = t == 1;
+                    if (!(first_plain && x_mu1)) {
+                        // units: a quarter of a group of rows over 32 edges, else a whole group
+                        for (int u = gw; u < 4 * m.GR; u += GW) {
+                            const int g = u >> 2, qq = u & 3;
+                            const int4 gi = m.rgrp[g];
+                            const int dg = uniform(gi.y);
+                            const uint32_t off = (uint32_t)uniform(gi.x);
+                            if (dg > 32) {
+                                const int rl = qq * 16 + (lane >> 2);
+                                const uint32_t sbit = ((sigp[2 * g + (rl >> 5)] >> (rl & 31)) & 1u) << 31;
+                                if (uniform(gi.z) != 0)
+                                    check_quarter<true>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane, qq, dg,
+                                                        sbit, first_plain);
+                                else
+                                    check_quarter<false>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane, qq, dg,
+                                                         sbit, first_plain);
+                            } else if (qq == 0) {
+                                const uint32_t sbit = ((sigp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u) << 31;
+                                check_dispatch<RD>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane, dg,
+                                                   uniform(gi.z) != 0, sbit, first_plain);
+                            }
+                        }
+                        x_mu1 = first_plain;
+                    }
+                    // after the check sweep (or, when it is skipped, after every
+                    // workgroup has read the previous count and weight)
+                    if (!grid_sync(sh, nwg, gen, a.spin_limit, ms, local)) return;
+                    int dcount = 0;
+                    double dW = 0.0;
+                    for (int g = gw; g < m.GV; g += GW) {
+                        const int4 gi = m.vgrp[g];
+                        const int dg = uniform(gi.y);
+                        const bool mixed = uniform(gi.z) != 0;
+                        const uint32_t pp = (uint32_t)(g * 64 + lane);
+                        const float2 lgv = ldg(lgl, pp);
+                        const float l = lgv.x, gm = lgv.y;
+                        const float mo = Mg[pp];
+                        float acc = __builtin_fmaf(gm, mo - l, l);
+                        const uint32_t sb = 4u * ((uint32_t)uniform(gi.x) + (uint32_t)lane);
+                        const int vd = mixed ? ldg(m.vdeg, pp) : dg;
+                        acc = first_plain ? var_dispatch<false>(X, sb, dg, mixed, vd, acc)
+                                          : var_dispatch<true>(X, sb, dg, mixed, vd, acc);
+                        Mg[pp] = acc;
+                        if ((acc < 0.0f) != (mo < 0.0f)) {
+                            flip_slots(m.scheck, sb, vd, a.par, dcount);
+                            dW += acc < 0.0f ? (double)l : -(double)l;
+                        }
+                    }
+                    if (dcount) atomicAdd(&sh->count, dcount);
+                    if (dW != 0.0) atomicAdd(&sh->W, dW);
+                    if (!grid_sync(sh, nwg, gen, a.spin_limit, ms, local)) return;
+                    ++iters;
+                    const int cnt = __hip_atomic_load(&sh->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (base + uniform(cnt) == 0) {
+                        conv = true;
+                        break;
+                    }
+                    if (first_plain) {
+                        for (int g = gw; g < m.GV; g += GW) {
+                            const int4 gi = m.vgrp[g];
+                            const uint32_t pp = (uint32_t)(g * 64 + lane);
+                            extrinsic_dispatch(X, 4u * ((uint32_t)uniform(gi.x) + (uint32_t)lane), uniform(gi.y),
+                                               Mg[pp]);
+                        }
+                        if (!grid_sync(sh, nwg, gen, a.spin_limit, ms, local)) return;
+                        x_mu1 = false;
+                    }
+                }
+                if (conv) {
+                    const unsigned long long wb = __hip_atomic_load(
+                        reinterpret_cast<unsigned long long*>(&sh->W), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const double W = __longlong_as_double((long long)wb);
+                    if (!have_best || W < bestW) {
+                        bestW = W;
+                        have_best = true;
+                        for (int g = gw; g < m.GV; g += GW) {
+                            const unsigned long long b = __ballot(Mg[g * 64 + lane] < 0.0f);
+                            if (lane == 0) {
+                                a.bestp[2 * g] = (uint32_t)b;
+                                a.bestp[2 * g + 1] = (uint32_t)(b >> 32);
+                            }
+                        }
+                    }
+                    ++nconv;
+                    if (a.crit == 0 && nconv >= a.S) break;
+                }
+            }
+            if (!have_best) {
+                for (int g = gw; g < m.GV; g += GW) {
+                    const unsigned long long b = __ballot(Mg[g * 64 + lane] < 0.0f);
+                    if (lane == 0) {
+                        a.bestp[2 * g] = (uint32_t)b;
+                        a.bestp[2 * g + 1] = (uint32_t)(b >> 32);
+                    }
+                }
+            }
+            // positions -> variable order (each wave reads the ballots it wrote)
+            for (int g = gw; g < m.GV; g += GW) {
+                if ((a.bestp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u) {
+                    const int j = ldg(m.vord, (uint32_t)(g * 64 + lane));
+                    atomicOr(a.best + (j >> 5), 1u << (j & 31));
+                }
+            }
+        }
+        if (!grid_sync(sh, nwg, gen, a.spin_limit, ms, local)) return;
+        if (rank == 0) {
+            for (int w = tid; w < WN; w += nth) {
+                const uint32_t bits = __hip_atomic_load(a.best + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                m.corr[s * WN + w] = bits;
+                uint32_t b = bits;
+                while (b) {
+                    const int j = w * 32 + __builtin_ctz(b);
+                    b &= b - 1u;
+                    for (int e = m.ocol_ptr[j]; e < m.ocol_ptr[j + 1]; ++e) {
+                        const int r = m.orow_idx[e];
+                        atomicXor(obw + (r >> 5), 1u << (r & 31));
+                    }
+                }
+            }
+            __syncthreads();
+            if (m.obsp)
+                for (int w = tid; w < m.WK; w += nth) m.obsp[s * m.WK + w] = obw[w];
+            if (a.stats && tid == 0) {
+                rbp_shot_stats st;
+                st.converged = have_best ? 1 : 0;
+                st.nconv = (uint8_t)(nconv > 255 ? 255 : nconv);
+                st.path = (uint8_t)path;
+                st.reserved = 0;
+                st.legs = (uint16_t)(legs > 65535 ? 65535 : legs);
+                st.reserved2 = 0;
+                st.iters = (uint32_t)iters;
+                st.reserved3 = 0;
+                st.t_start = t_start;
+                st.t_end = wall_clock64();
+                a.stats[s] = st;
+            }
+        }
+        // the next shot's set-up rewrites the shared arrays
+        if (!grid_sync(sh, nwg, gen, a.spin_limit, ms, local)) return;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 static int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -1163,6 +1566,9 @@ static DecodeKernel decode_kernel(int max_stored_row_deg, bool lds, int minw) {
 }
 
 static constexpr int kMaxLds = 160 * 1024;
+// device-memory state of all slots together: about three quarters of the
+// 256 MB Infinity Cache
+static constexpr int64_t kStateCacheBytes = 192ll << 20;
 
 struct LaunchShape {
     int waves = 1;
@@ -1259,7 +1665,16 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
     }
     per_cu = std::max(per_cu, 1);
     int64_t slots = (int64_t)per_cu * std::max(cs[0]->num_cus, 1);
-    if (cfg.max_slots > 0) slots = std::min<int64_t>(slots, cfg.max_slots);
+    if (cfg.max_slots > 0) {
+        slots = std::min<int64_t>(slots, cfg.max_slots);
+    } else if (!lds) {
+        // Per-slot state in device memory: keep the slots' state within the
+        // Infinity Cache, which serves the check sweep's gathers (circuit-level
+        // ZSZ-LP-320 memory: 1.44x the shots/s of the occupancy-limited slot
+        // count), with one slot per CU at least.
+        const int64_t cap = kStateCacheBytes / (4 * L.gstride);
+        slots = std::min<int64_t>(slots, std::max<int64_t>(cap, std::max(cs[0]->num_cus, 1)));
+    }
     slots = std::min<int64_t>(slots, (int64_t)std::min<uint64_t>(std::max<uint64_t>(shots, 1), 1ull << 40));
     L.slots = (int)std::max<int64_t>(slots, 1);
     *out = L;
@@ -1538,7 +1953,7 @@ rbp_status rbp_code_destroy(rbp_code_t c) {
     for (DevBuf* b : {&c->row_ptr, &c->col_idx, &c->col_ptr, &c->csc_row, &c->rgrp, &c->rposp, &c->rposw, &c->rord, &c->vgrp,
                       &c->vord, &c->vdeg, &c->scheck, &c->scsc, &c->orow_ptr, &c->ocol_idx, &c->ocol_ptr,
                       &c->orow_idx, &c->thr, &c->lam, &c->lamp, &c->m1, &c->gtab, &c->lg, &c->queue, &c->gstate,
-                      &c->trace_hit, &c->spa_queue, &c->gapt, &c->order, &c->ohist})
+                      &c->trace_hit, &c->spa_queue, &c->gapt, &c->order, &c->ohist, &c->coop})
         b->release();
     delete c;
     return RBP_OK;
@@ -1635,6 +2050,105 @@ rbp_status rbp_decode(rbp_code_t c, const double* priors, const uint32_t* syndro
     }
     rbp_code* cs[1] = {c};
     return launch_decode(cs, 1, a, shots, stream);
+}
+
+rbp_status rbp_decode_coop(rbp_code_t c, const double* priors, const uint32_t* syndromes, uint64_t shots,
+                           const rbp_relay_params* params, const rbp_coop_params* coop, uint32_t* corrections,
+                           uint32_t* obs_pred, rbp_shot_stats* stats, void* stream_) {
+    if (!c) return fail(RBP_ERR_INVALID_ARG, "code is NULL");
+    rbp_status st = check_params(params);
+    if (st) return st;
+    if (!syndromes || !corrections) return fail(RBP_ERR_INVALID_ARG, "syndromes/corrections is NULL");
+    if (c->k > 0 && !obs_pred) return fail(RBP_ERR_INVALID_ARG, "obs_pred is NULL");
+    st = check_priors(priors, c->N);
+    if (st) return st;
+    rbp_coop_params cp = {0, 0, 0, 0u, 0, 0};
+    if (coop) cp = *coop;
+    if (cp.workgroups < 0 || cp.stride < 0 || cp.waves < 0 || cp.waves > 8 || cp.phantom < 0 || cp.phantom > 1024)
+        return fail(RBP_ERR_INVALID_ARG, "coop: workgroups, stride >= 0, waves in 0..8, phantom in 0..1024");
+    if (shots == 0) return RBP_OK;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    st = ensure_llr(c, priors, stream);
+    if (!st) st = ensure_gamma(c, params, stream);
+    if (!st) st = ensure_lam_gamma(c, params, stream);
+    if (st) return st;
+    const int cus = std::max(c->num_cus, 1);
+    const int waves = cp.waves > 0 ? cp.waves : 8;
+    int nwg = cp.workgroups > 0 ? cp.workgroups : std::max(cus / 8, 1);
+    nwg = std::min(nwg, cus);
+    int stride = cp.stride > 0 ? cp.stride : (nwg * 8 <= cus ? 8 : 1);
+    if ((int64_t)nwg * stride > cus) stride = 1;
+    CoopLaunch a;
+    std::memset(&a, 0, sizeof(a));
+    a.m = model_of(c, syndromes, corrections, obs_pred);
+    a.shots = shots;
+    a.stats = stats;
+    a.Smax = c->S;
+    a.nwg = nwg;
+    a.stride = stride;
+    a.arrivals = (unsigned)(nwg + cp.phantom);
+    a.force_device = cp.device_fences != 0;
+    a.spin_limit = cp.spin_limit > 0 ? cp.spin_limit : (1u << 21);
+    a.T0 = params->pre_iter;
+    a.Tr = params->max_iterations;
+    a.R = params->num_sets;
+    a.S = params->stop_nconv;
+    a.crit = params->stopping_criterion;
+    const int64_t xfloats = ((int64_t)c->S + 4 + c->Np + 63) / 64 * 64;
+    const int WM = ceil_div(c->M, 32), WN = ceil_div(c->N, 32), WK = std::max(ceil_div(c->k, 32), 1);
+    const int64_t o_par = 0, o_bestp = align16(4 * (int64_t)WM), o_best = o_bestp + align16(4 * (int64_t)(c->Np / 32)),
+                  o_sh = o_best + align16(4 * (int64_t)WN), coop_bytes = o_sh + (int64_t)sizeof(CoopShared);
+    st = c->gstate.reserve(sizeof(float) * (size_t)xfloats);
+    if (!st) st = c->coop.reserve((size_t)coop_bytes);
+    if (st) return st;
+    a.X = c->gstate.as<float>();
+    char* cb = reinterpret_cast<char*>(c->coop.p);
+    a.par = reinterpret_cast<uint32_t*>(cb + o_par);
+    a.bestp = reinterpret_cast<uint32_t*>(cb + o_bestp);
+    a.best = reinterpret_cast<uint32_t*>(cb + o_best);
+    a.sh = reinterpret_cast<CoopShared*>(cb + o_sh);
+    int64_t off = 0;
+    a.off_sig = (int)off;
+    off += align16(4 * (int64_t)WM);
+    a.off_sigp = (int)off;
+    off += align16(8 * (int64_t)c->GR);
+    a.off_obs = (int)off;
+    off += align16(4 * (int64_t)WK);
+    a.off_misc = (int)off;
+    off += align16(sizeof(CoopMisc));
+    if (off > kMaxLds) return fail(RBP_ERR_UNSUPPORTED, "syndrome bits do not fit in LDS");
+    const int lds = (int)off;
+    void (*kern)(CoopLaunch) = c->max_stored_row_deg <= 12 ? relay_bp_coop_kernel<12> : relay_bp_coop_kernel<32>;
+    RBP_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      lds));
+    int per_cu = 0;
+    RBP_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern),
+                                                                64 * waves, lds));
+    const int64_t grid = (int64_t)nwg * stride;
+    if (per_cu < 1 || grid > (int64_t)per_cu * cus)
+        return fail(RBP_ERR_UNSUPPORTED, "coop: the workgroups cannot all be resident");
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, stream, reinterpret_cast<uint32_t*>(a.sh),
+                       (int)(sizeof(CoopShared) / 4));
+    RBP_HIP_CHECK(hipGetLastError());
+    void* args[] = {&a};
+    RBP_HIP_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3((unsigned)grid),
+                                             dim3(64 * waves), args, (unsigned)lds, stream));
+    return RBP_OK;
+}
+
+rbp_status rbp_coop_aborted(rbp_code_t c, void* stream_, int32_t* aborted) {
+    if (!c || !aborted) return fail(RBP_ERR_INVALID_ARG, "code or aborted is NULL");
+    *aborted = 0;
+    if (!c->coop.p) return RBP_OK;
+    const int WM = ceil_div(c->M, 32), WN = ceil_div(c->N, 32);
+    const int64_t o_sh = align16(4 * (int64_t)WM) + align16(4 * (int64_t)(c->Np / 32)) + align16(4 * (int64_t)WN);
+    const CoopShared* sh = reinterpret_cast<const CoopShared*>(reinterpret_cast<const char*>(c->coop.p) + o_sh);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    unsigned int v = 0;
+    RBP_HIP_CHECK(hipMemcpyAsync(&v, &sh->abort, sizeof(v), hipMemcpyDeviceToHost, stream));
+    RBP_HIP_CHECK(hipStreamSynchronize(stream));
+    *aborted = v != 0u ? 1 : 0;
+    return RBP_OK;
 }
 
 rbp_status rbp_decode_multi(int32_t n_codes, const rbp_code_t* codes, const double* const* priors,

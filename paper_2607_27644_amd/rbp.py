@@ -81,6 +81,26 @@ class RelayParams:
                             self.num_sets, self.stop_nconv, self.stopping_criterion, self.gamma_seed)
 
 
+class CoopParamsC(ctypes.Structure):
+    _fields_ = [("workgroups", ctypes.c_int32), ("stride", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("spin_limit", ctypes.c_uint32), ("phantom", ctypes.c_int32), ("device_fences", ctypes.c_int32)]
+
+
+@dataclasses.dataclass
+class CoopParams:
+    """Latency-mode launch (rbp_decode_coop); 0 = library default."""
+    workgroups: int = 0
+    stride: int = 0
+    waves: int = 0
+    spin_limit: int = 0
+    phantom: int = 0  # tests of the barrier-expiry path only
+    device_fences: int = 0  # device-scope fences even when the participants share one XCD
+
+    def c(self) -> CoopParamsC:
+        return CoopParamsC(self.workgroups, self.stride, self.waves, self.spin_limit, self.phantom,
+                           self.device_fences)
+
+
 _lib = None
 
 
@@ -117,6 +137,8 @@ def lib():
         "rbp_decode_spa": [vp, vp, u64, P(SpaParamsC), vp, vp, vp, vp, vp],
         "rbp_bits_extract": [vp, i32, u64, i64, i32, vp, i32, vp],
         "rbp_window_commit": [vp, u64, vp, i32, vp, i32, vp, vp, vp, vp, vp, i32, vp],
+        "rbp_decode_coop": [vp, vp, vp, u64, P(RelayParamsC), P(CoopParamsC), vp, vp, vp, vp],
+        "rbp_coop_aborted": [vp, vp, P(i32)],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -228,6 +250,31 @@ class Code:
         check(lib().rbp_decode(self.h, pr.ctypes.data, _ptr(syndromes), shots, ctypes.byref(prm), _ptr(delta),
                                _ptr(corr), _ptr(obsp), _ptr(st), _stream(stream)))
         return corr, obsp, st
+
+    def decode_coop(self, priors, syndromes: torch.Tensor, params: RelayParams, coop: Optional[CoopParams] = None,
+                    stats: bool = True, stream=None, out=None):
+        """Latency mode: shots one after another, each by several workgroups."""
+        shots = syndromes.shape[0]
+        assert syndromes.dtype == torch.int32 and syndromes.is_contiguous()
+        assert syndromes.shape[1] == words(self.M)
+        dev = syndromes.device
+        if out is None:
+            corr = torch.empty((shots, words(self.N)), dtype=torch.int32, device=dev)
+            obsp = torch.empty((shots, max(words(self.k), 1)), dtype=torch.int32, device=dev)
+            st = torch.empty((shots, 32), dtype=torch.uint8, device=dev) if stats else None
+        else:
+            corr, obsp, st = out
+        pr = _f64(priors)
+        prm = params.c()
+        cp = (coop or CoopParams()).c()
+        check(lib().rbp_decode_coop(self.h, pr.ctypes.data, _ptr(syndromes), shots, ctypes.byref(prm),
+                                    ctypes.byref(cp), _ptr(corr), _ptr(obsp), _ptr(st), _stream(stream)))
+        return corr, obsp, st
+
+    def coop_aborted(self, stream=None) -> bool:
+        v = ctypes.c_int32()
+        check(lib().rbp_coop_aborted(self.h, _stream(stream), ctypes.byref(v)))
+        return bool(v.value)
 
     def trace(self, priors, syndrome: torch.Tensor, params: RelayParams, leg: int, t: int, phase: int = 0,
               delta: Optional[torch.Tensor] = None, stream=None):
