@@ -1002,9 +1002,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
 // flag and every workgroup leaves at its next barrier, so no launch can hang.
 // ---------------------------------------------------------------------------
 struct CoopShared {
-    unsigned int arrive, gen, abort, xmask;  // xmask: XCDs of the participants
-    int32_t count, pad2;
-    double W;
+    unsigned int abort, xmask, pad0, pad1;  // xmask: XCDs of the participants
 };
 
 struct CoopLaunch {
@@ -1017,8 +1015,11 @@ struct CoopLaunch {
     uint32_t* bestp; // [Np / 32] best solution by position
     uint32_t* best;  // [WN] best solution by variable
     CoopShared* sh;
+    uint32_t* flags;   // [arrivals] barrier generation each workgroup has reached
+    int32_t* cnt;      // [nwg] change of the unsatisfied-check count, per workgroup (cumulative)
+    double* wsum;      // [nwg] weight of the hard decision, per workgroup (cumulative)
     int32_t nwg, stride;
-    uint32_t arrivals;  // arrivals that complete a barrier (nwg, more only to test expiry)
+    uint32_t arrivals;  // workgroups a barrier waits for (nwg, more only to test expiry)
     uint32_t spin_limit;
     int32_t force_device;  // device-scope fences even on one XCD (for comparison)
     int32_t T0, Tr, R, S, crit;
@@ -1026,7 +1027,8 @@ struct CoopLaunch {
 };
 
 struct CoopMisc {
-    int32_t red, flag, pad0, pad1;
+    int32_t red, flag, dcnt, pad;
+    double dW;
 };
 
 // Ordering of the shot's state around a barrier.  When every participant
@@ -1050,42 +1052,59 @@ __device__ __forceinline__ void coop_acquire(bool local) {
         __threadfence();
 }
 
-// grid barrier over the participating workgroups; false if the launch aborted
-__device__ __forceinline__ bool grid_sync(CoopShared* sh, unsigned nwg, unsigned& gen, uint32_t spin_limit,
-                                          CoopMisc* ms, bool local) {
+// Grid barrier over the participating workgroups; false if the launch
+// aborted.  Workgroup r announces barrier g by storing g in flags[r]; wave 0
+// then polls all flags (one load per lane) until every one has reached g, at
+// most spin_limit times.  No read-modify-write on a shared word is needed.
+__device__ __forceinline__ bool grid_sync(CoopShared* sh, uint32_t* flags, int rank, unsigned nflags, unsigned& gen,
+                                          uint32_t spin_limit, CoopMisc* ms, bool local) {
     coop_release(local);  // this wave's stores are complete (and visible to the other participants)
     __syncthreads();
-    if (threadIdx.x == 0) {
+    ++gen;
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        if (lane == 0) __hip_atomic_store(flags + rank, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1;
-        if (__hip_atomic_load(&sh->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-            ok = 0;
-        } else {
-            const unsigned my = gen;
-            if (atomicAdd(&sh->arrive, 1u) == nwg - 1u) {
-                atomicExch(&sh->arrive, 0u);
-                coop_release(local);
-                atomicAdd(&sh->gen, 1u);
-            } else {
-                uint32_t spins = 0;
-                while (__hip_atomic_load(&sh->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == my) {
-                    if (++spins > spin_limit) {
-                        atomicExch(&sh->abort, 1u);
-                        ok = 0;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(4);
-                }
+        uint32_t spins = 0;
+        for (;;) {
+            int reached = 1;
+            for (unsigned i = (unsigned)lane; i < nflags; i += 64u)
+                reached &= (int)(__hip_atomic_load(flags + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - gen) >= 0;
+            if (__all(reached)) break;
+            if (++spins > spin_limit) {
+                ok = 0;
+                break;
             }
+            __builtin_amdgcn_s_sleep(2);
         }
-        ms->flag = ok;
-        // see the other workgroups' stores: the L1 is shared by the CU's waves,
-        // which load again only after the barrier below
-        coop_acquire(local);
+        if (lane == 0) {
+            if (!ok) atomicExch(&sh->abort, 1u);
+            ms->flag = ok;
+            // see the other workgroups' stores: the L1 is shared by the CU's waves,
+            // which load again only after the barrier below
+            coop_acquire(local);
+        }
     }
     __syncthreads();
-    const bool ok = ms->flag != 0;
-    ++gen;
-    return ok;
+    return ms->flag != 0;
+}
+
+// sum of the per-workgroup slots (every wave computes it)
+template <class T>
+__device__ __forceinline__ T coop_total(const T* v, int n, int lane) {
+    T acc = 0;
+    for (int i = lane; i < n; i += 64) {
+        if constexpr (sizeof(T) == 8) {
+            const unsigned long long b = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(v + i),
+                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            acc += __longlong_as_double((long long)b);
+        } else {
+            acc += __hip_atomic_load(v + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) acc += __shfl_xor(acc, d, 64);
+    return acc;
 }
 
 constexpr int kQuarterRegs = 32;  // edges per lane kept in registers (rows up to 128)
@@ -1183,12 +1202,12 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
     uint32_t* obw = reinterpret_cast<uint32_t*>(smem + a.off_obs);
     CoopMisc* ms = reinterpret_cast<CoopMisc*>(smem + a.off_misc);
     CoopShared* sh = a.sh;
-    const unsigned nwg = a.arrivals;
+    const unsigned nflags = a.arrivals;
     unsigned gen = 0;
     const int WM = m.WM, WN = m.WN;
     // which XCDs the participants run on (hardware register XCC_ID, bits 3:0)
     if (tid == 0) atomicOr(&sh->xmask, 1u << (__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u));
-    if (!grid_sync(sh, nwg, gen, a.spin_limit, ms, false)) return;
+    if (!grid_sync(sh, a.flags, rank, nflags, gen, a.spin_limit, ms, false)) return;
     const bool local =
         __popc(__hip_atomic_load(&sh->xmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 1 && !a.force_device;
 
@@ -1196,7 +1215,13 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
         const uint64_t t_start = wall_clock64();
         // ---- set-up: every workgroup keeps the syndrome and its row-group
         // ballots in LDS; rank 0 resets the shared arrays
-        if (tid == 0) ms->red = 0;
+        if (tid == 0) {
+            ms->red = 0;
+            ms->dcnt = 0;
+            ms->dW = 0.0;
+            a.cnt[rank] = 0;
+            a.wsum[rank] = 0.0;
+        }
         __syncthreads();
         int pc = 0;
         for (int w = tid; w < WM; w += nth) {
@@ -1208,11 +1233,7 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
         if (rank == 0) {
             for (int w = tid; w < WN; w += nth) a.best[w] = 0u;
             for (int w = tid; w < m.WK; w += nth) obw[w] = 0u;
-            if (tid == 0) {
-                sh->count = 0;
-                sh->W = 0.0;
-                X.st(4u * (uint32_t)m.S, INFINITY);  // read-only padding cell
-            }
+            if (tid == 0) X.st(4u * (uint32_t)m.S, INFINITY);  // read-only padding cell
         }
         if (pc) atomicAdd(&ms->red, pc);
         __syncthreads();
@@ -1227,7 +1248,7 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
             }
         }
         for (int g = gw; g < m.GV; g += GW) Mg[g * 64 + lane] = ldg(m.lamp, (uint32_t)(g * 64 + lane));
-        if (!grid_sync(sh, nwg, gen, a.spin_limit, ms, local)) return;
+        if (!grid_sync(sh, a.flags, rank, nflags, gen, a.spin_limit, ms, local)) return;
 
         int nconv = 0, legs = 0, iters = 0, path = 0;
         bool x_mu1 = false, have_best = false;
@@ -1269,7 +1290,7 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
                     }
                     // after the check sweep (or, when it is skipped, after every
                     // workgroup has read the previous count and weight)
-                    if (!grid_sync(sh, nwg, gen, a.spin_limit, ms, local)) return;
+                    if (!grid_sync(sh, a.flags, rank, nflags, gen, a.spin_limit, ms, local)) return;
                     int dcount = 0;
                     double dW = 0.0;
                     for (int g = gw; g < m.GV; g += GW) {
@@ -1291,11 +1312,19 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
                             dW += acc < 0.0f ? (double)l : -(double)l;
                         }
                     }
-                    if (dcount) atomicAdd(&sh->count, dcount);
-                    if (dW != 0.0) atomicAdd(&sh->W, dW);
-                    if (!grid_sync(sh, nwg, gen, a.spin_limit, ms, local)) return;
+                    // the workgroup's changes, added to its own slots
+                    if (dcount) atomicAdd(&ms->dcnt, dcount);
+                    if (dW != 0.0) atomicAdd(&ms->dW, dW);
+                    __syncthreads();
+                    if (tid == 0 && (ms->dcnt != 0 || ms->dW != 0.0)) {
+                        a.cnt[rank] += ms->dcnt;
+                        a.wsum[rank] += ms->dW;
+                        ms->dcnt = 0;
+                        ms->dW = 0.0;
+                    }
+                    if (!grid_sync(sh, a.flags, rank, nflags, gen, a.spin_limit, ms, local)) return;
                     ++iters;
-                    const int cnt = __hip_atomic_load(&sh->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const int cnt = coop_total(a.cnt, a.nwg, lane);
                     if (base + uniform(cnt) == 0) {
                         conv = true;
                         break;
@@ -1307,14 +1336,12 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
                             extrinsic_dispatch(X, 4u * ((uint32_t)uniform(gi.x) + (uint32_t)lane), uniform(gi.y),
                                                Mg[pp]);
                         }
-                        if (!grid_sync(sh, nwg, gen, a.spin_limit, ms, local)) return;
+                        if (!grid_sync(sh, a.flags, rank, nflags, gen, a.spin_limit, ms, local)) return;
                         x_mu1 = false;
                     }
                 }
                 if (conv) {
-                    const unsigned long long wb = __hip_atomic_load(
-                        reinterpret_cast<unsigned long long*>(&sh->W), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const double W = __longlong_as_double((long long)wb);
+                    const double W = coop_total(a.wsum, a.nwg, lane);
                     if (!have_best || W < bestW) {
                         bestW = W;
                         have_best = true;
@@ -1347,7 +1374,7 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
                 }
             }
         }
-        if (!grid_sync(sh, nwg, gen, a.spin_limit, ms, local)) return;
+        if (!grid_sync(sh, a.flags, rank, nflags, gen, a.spin_limit, ms, local)) return;
         if (rank == 0) {
             for (int w = tid; w < WN; w += nth) {
                 const uint32_t bits = __hip_atomic_load(a.best + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1381,7 +1408,7 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
             }
         }
         // the next shot's set-up rewrites the shared arrays
-        if (!grid_sync(sh, nwg, gen, a.spin_limit, ms, local)) return;
+        if (!grid_sync(sh, a.flags, rank, nflags, gen, a.spin_limit, ms, local)) return;
     }
 }
 
@@ -2097,7 +2124,9 @@ rbp_status rbp_decode_coop(rbp_code_t c, const double* priors, const uint32_t* s
     const int64_t xfloats = ((int64_t)c->S + 4 + c->Np + 63) / 64 * 64;
     const int WM = ceil_div(c->M, 32), WN = ceil_div(c->N, 32), WK = std::max(ceil_div(c->k, 32), 1);
     const int64_t o_par = 0, o_bestp = align16(4 * (int64_t)WM), o_best = o_bestp + align16(4 * (int64_t)(c->Np / 32)),
-                  o_sh = o_best + align16(4 * (int64_t)WN), coop_bytes = o_sh + (int64_t)sizeof(CoopShared);
+                  o_sh = o_best + align16(4 * (int64_t)WN), o_flags = o_sh + (int64_t)sizeof(CoopShared),
+                  o_cnt = o_flags + align16(4 * (int64_t)a.arrivals), o_wsum = o_cnt + align16(4 * (int64_t)nwg),
+                  coop_bytes = o_wsum + 8 * (int64_t)nwg;
     st = c->gstate.reserve(sizeof(float) * (size_t)xfloats);
     if (!st) st = c->coop.reserve((size_t)coop_bytes);
     if (st) return st;
@@ -2107,6 +2136,9 @@ rbp_status rbp_decode_coop(rbp_code_t c, const double* priors, const uint32_t* s
     a.bestp = reinterpret_cast<uint32_t*>(cb + o_bestp);
     a.best = reinterpret_cast<uint32_t*>(cb + o_best);
     a.sh = reinterpret_cast<CoopShared*>(cb + o_sh);
+    a.flags = reinterpret_cast<uint32_t*>(cb + o_flags);
+    a.cnt = reinterpret_cast<int32_t*>(cb + o_cnt);
+    a.wsum = reinterpret_cast<double*>(cb + o_wsum);
     int64_t off = 0;
     a.off_sig = (int)off;
     off += align16(4 * (int64_t)WM);
@@ -2127,8 +2159,8 @@ rbp_status rbp_decode_coop(rbp_code_t c, const double* priors, const uint32_t* s
     const int64_t grid = (int64_t)nwg * stride;
     if (per_cu < 1 || grid > (int64_t)per_cu * cus)
         return fail(RBP_ERR_UNSUPPORTED, "coop: the workgroups cannot all be resident");
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, stream, reinterpret_cast<uint32_t*>(a.sh),
-                       (int)(sizeof(CoopShared) / 4));
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, stream, reinterpret_cast<uint32_t*>(a.sh),
+                       (int)((o_cnt - o_sh) / 4));
     RBP_HIP_CHECK(hipGetLastError());
     void* args[] = {&a};
     RBP_HIP_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3((unsigned)grid),
