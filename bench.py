@@ -7,7 +7,9 @@ with Relay-BP (gamma0 0.125, pre_iter 80, max_iterations 60, 100 relay legs,
 stop_nconv 5, gamma in [-0.24, 0.66]) and count block failures on the GPU; the
 failure count comes back to the host at the end of the timed steps.  The
 learned path adds the proposal network's forward pass before decoding.
-Prints one JSON line.
+Beside the headline: the classical AWGN benchmark, sequential single-shot
+latency, and the paper's latency-table workload (circuit-level ZSZ-LP-320
+memory decoded one shot at a time in latency mode).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -40,6 +42,7 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--train-pairs", type=int, default=1_000_000)
     ap.add_argument("--no-awgn", action="store_true")
+    ap.add_argument("--no-circuit", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates rocprof byte counters)")
     return ap.parse_args()
@@ -100,6 +103,51 @@ def cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
+
+
+def circuit_latency(seed: int, shots: int = 100, batch: int = 4000) -> dict:
+    """The paper's latency table workload: circuit-level d-round memory of
+    ZSZ-LP-320 (DEM 1920 x 28992), p = 1e-3, num_sets 1000, gamma in
+    [-0.16, 0.66]; single shots in latency mode (one XCD's CUs per shot, host
+    clock around each call) and one batched launch, X and Z memory."""
+    import numpy as np
+    import torch
+    from paper_2607_27644_amd import circuits, experiments, rbp, stats
+    gmin, gmax = experiments.CIRCUIT_GAMMA["ZSZ-LP-320"]
+    params = rbp.RelayParams(num_sets=1000, gamma_min=gmin, gamma_max=gmax)
+    res = {"code": "ZSZ-LP-320", "p": 1e-3, "relay": {"num_sets": 1000, "gamma": [gmin, gmax]}}
+    lat_all = []
+    for basis in "XZ":
+        dem = circuits.memory_dem("ZSZ-LP-320", basis, 1e-3)
+        code = rbp.Code.from_dem(dem)
+        syn, obs, _ = code.sample(dem.priors, batch, seed)
+        out = code.decode_coop(dem.priors, syn[:1], params)
+        torch.cuda.synchronize()
+        lat = []
+        for i in range(shots):
+            t0 = time.perf_counter()
+            code.decode_coop(dem.priors, syn[i:i + 1], params, out=out)
+            torch.cuda.synchronize()
+            lat.append(1e6 * (time.perf_counter() - t0))
+        if code.coop_aborted():
+            raise RuntimeError("latency-mode launch stopped on an expired barrier wait")
+        code.set_launch_config(8, 2, 0)
+        corr, obsp, st = code.decode(dem.priors, syn, params)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        code.decode(dem.priors, syn, params, out=(corr, obsp, st))
+        e1.record()
+        torch.cuda.synchronize()
+        s = rbp.stats_to_numpy(st)
+        res[f"{basis}_memory"] = {"dem": [dem.M, dem.N], "latency_mode_us": stats.percentiles(np.array(lat)),
+                                  "batched_shots_per_s": batch / (e0.elapsed_time(e1) * 1e-3),
+                                  "mean_iters": float(s["iters"].mean())}
+        lat_all += lat
+        code.close()
+    res["latency_mode_us_xz"] = stats.percentiles(np.array(lat_all))
+    res["paper_l40s_ms"] = {"mean": 1.2, "p99": 2.0, "p99.9": 3.2, "note": "NVIDIA L40S, Table 'decoding latency'"}
+    return res
 
 
 def main():
@@ -282,6 +330,9 @@ def main():
             lat.append(1e6 * (time.perf_counter() - ta))
         del one_syn
         out["latency_us"]["sequential_single_shot"] = stats.percentiles(np.array(lat))
+
+    if not args.no_circuit:
+        out["circuit_latency"] = circuit_latency(args.seed)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dem, S, args.seed, params, args.cpu_seconds)
