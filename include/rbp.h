@@ -269,6 +269,21 @@ rbp_status rbp_window_commit(rbp_code_t code, uint64_t shots, const uint32_t* wi
                              uint32_t* corrections_dev, const rbp_shot_stats* win_stats_dev,
                              rbp_shot_stats* acc_stats_dev, int32_t first, void* stream);
 
+/* Bit gather (parallel-window decoding: windows whose rows are not one
+ * contiguous range, and rows above a gap that fix single columns): bit t of
+ * dst_dev[s] is bit rows_dev[t] of src_dev[s], t < nrows (device int32;
+ * a row outside 0 .. 32 src_words - 1 reads as 0); higher bits are 0.
+ * src_dev uint32[shots][src_words], dst_dev uint32[shots][dst_words], nrows <=
+ * 32 dst_words (SHAPE otherwise). */
+rbp_status rbp_bits_gather(const uint32_t* src_dev, int32_t src_words, uint64_t shots, const int32_t* rows_dev,
+                           int32_t nrows, uint32_t* dst_dev, int32_t dst_words, void* stream);
+
+/* Final check of windowed decoding: a shot whose running syndrome
+ * syn_dev[s] (uint32[shots][words]) still has a set bit gets
+ * acc_stats_dev[s].converged = 0. */
+rbp_status rbp_window_residual(const uint32_t* syn_dev, int32_t words, uint64_t shots, rbp_shot_stats* acc_stats_dev,
+                               void* stream);
+
 /* ---- classical channel coding: sum-product BP over BPSK-AWGN ------------ *
  * The paper's classical benchmark of its ZSZ-2BGA codes (numerics appendix,
  * "classical channel coding", with eq. "bpsk awgn capacity"): the all-zero

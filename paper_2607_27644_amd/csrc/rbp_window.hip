@@ -13,6 +13,12 @@
 //                          mechanism in the full correction and XOR its column
 //                          of H and of O (CSC on the device) into the running
 //                          syndrome and the predicted observables.
+//  * bits_gather_kernel    one thread per (shot, output word): bit t of the
+//                          output is bit rows[t] of the source (windows whose
+//                          rows are not one contiguous range, and the rows that
+//                          fix single columns in parallel-window decoding).
+//  * residual_kernel       one thread per shot: a shot whose running syndrome
+//                          is not zero after every window is not converged.
 #include <algorithm>
 #include <string>
 
@@ -36,6 +42,32 @@ __global__ void __launch_bounds__(256) bits_extract_kernel(const uint32_t* src, 
     const int rem = nbits - 32 * w;
     if (rem < 32) v &= rem > 0 ? ((1u << rem) - 1u) : 0u;
     dst[s * (uint64_t)dw + w] = v;
+}
+
+__global__ void __launch_bounds__(256) bits_gather_kernel(const uint32_t* src, int32_t sw, uint64_t shots,
+                                                           const int32_t* rows, int32_t n, uint32_t* dst, int32_t dw) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t s = t / (uint64_t)dw;
+    if (s >= shots) return;
+    const int w = (int)(t - s * (uint64_t)dw);
+    const uint32_t* row = src + s * (uint64_t)sw;
+    uint32_t v = 0u;
+    const int b0 = 32 * w, b1 = n < b0 + 32 ? n : b0 + 32;
+    const int nb = 32 * sw;
+    for (int b = b0; b < b1; ++b) {
+        const int i = rows[b];
+        if (i >= 0 && i < nb) v |= ((row[i >> 5] >> (i & 31)) & 1u) << (b - b0);
+    }
+    dst[s * (uint64_t)dw + w] = v;
+}
+
+__global__ void __launch_bounds__(256) residual_kernel(const uint32_t* syn, int32_t sw, uint64_t shots,
+                                                        rbp_shot_stats* acc) {
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= shots) return;
+    uint32_t any = 0u;
+    for (int w = 0; w < sw; ++w) any |= syn[s * (uint64_t)sw + w];
+    if (any) acc[s].converged = 0;
 }
 
 struct CommitArgs {
@@ -120,6 +152,34 @@ rbp_status rbp_bits_extract(const uint32_t* src, int32_t src_words, uint64_t sho
     if ((threads + 255) / 256 > max_blocks) return fail(RBP_ERR_UNSUPPORTED, "too many shots for one launch");
     hipLaunchKernelGGL(bits_extract_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, src,
                        src_words, shots, bit_offset, nbits, dst, dst_words);
+    RBP_HIP_CHECK(hipGetLastError());
+    return RBP_OK;
+}
+
+rbp_status rbp_bits_gather(const uint32_t* src, int32_t src_words, uint64_t shots, const int32_t* rows_dev,
+                           int32_t nrows, uint32_t* dst, int32_t dst_words, void* stream_) {
+    if (shots == 0) return RBP_OK;
+    if (!src || !dst || (nrows > 0 && !rows_dev)) return fail(RBP_ERR_INVALID_ARG, "src, dst or rows is NULL");
+    if (src_words < 1 || dst_words < 1 || nrows < 0) return fail(RBP_ERR_INVALID_ARG, "bad word or row counts");
+    if ((int64_t)nrows > 32 * (int64_t)dst_words) return fail(RBP_ERR_SHAPE, "nrows exceeds the destination");
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    const uint64_t threads = shots * (uint64_t)dst_words;
+    if ((threads + 255) / 256 > (1ull << 31)) return fail(RBP_ERR_UNSUPPORTED, "too many shots for one launch");
+    hipLaunchKernelGGL(bits_gather_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, src,
+                       src_words, shots, rows_dev, nrows, dst, dst_words);
+    RBP_HIP_CHECK(hipGetLastError());
+    return RBP_OK;
+}
+
+rbp_status rbp_window_residual(const uint32_t* syn, int32_t words, uint64_t shots, rbp_shot_stats* acc,
+                               void* stream_) {
+    if (shots == 0) return RBP_OK;
+    if (!syn || !acc) return fail(RBP_ERR_INVALID_ARG, "syn or acc is NULL");
+    if (words < 1) return fail(RBP_ERR_INVALID_ARG, "words must be >= 1");
+    if ((shots + 255) / 256 > (1ull << 31)) return fail(RBP_ERR_UNSUPPORTED, "too many shots for one launch");
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    hipLaunchKernelGGL(residual_kernel, dim3((unsigned)((shots + 255) / 256)), dim3(256), 0, stream, syn, words, shots,
+                       acc);
     RBP_HIP_CHECK(hipGetLastError());
     return RBP_OK;
 }

@@ -138,6 +138,8 @@ def lib():
         "rbp_bits_extract": [vp, i32, u64, i64, i32, vp, i32, vp],
         "rbp_window_commit": [vp, u64, vp, i32, vp, i32, vp, vp, vp, vp, vp, i32, vp],
         "rbp_decode_coop": [vp, vp, vp, u64, P(RelayParamsC), P(CoopParamsC), vp, vp, vp, vp],
+        "rbp_bits_gather": [vp, i32, u64, vp, i32, vp, i32, vp],
+        "rbp_window_residual": [vp, i32, u64, vp, vp],
         "rbp_coop_aborted": [vp, vp, P(i32)],
     }
     for name, args in sigs.items():
@@ -369,6 +371,22 @@ def bits_extract(src: torch.Tensor, bit_offset: int, nbits: int, out: torch.Tens
     check(lib().rbp_bits_extract(_ptr(src), src.shape[1], src.shape[0], bit_offset, nbits, _ptr(out), out.shape[1],
                                  _stream(stream)))
     return out
+
+
+def bits_gather(src: torch.Tensor, rows: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """out[s] bit t = src[s] bit rows[t] (rbp_bits_gather); rows int32 on the device."""
+    assert src.dtype == torch.int32 and out.dtype == torch.int32 and rows.dtype == torch.int32
+    assert src.is_contiguous() and out.is_contiguous() and rows.is_contiguous()
+    check(lib().rbp_bits_gather(_ptr(src), src.shape[1], src.shape[0], _ptr(rows), rows.numel(), _ptr(out),
+                                out.shape[1], _stream(stream)))
+    return out
+
+
+def window_residual(syndromes: torch.Tensor, acc_stats: torch.Tensor, stream=None):
+    """Clear `converged` of the shots whose running syndrome is not zero (rbp_window_residual)."""
+    assert syndromes.dtype == torch.int32 and syndromes.is_contiguous()
+    check(lib().rbp_window_residual(_ptr(syndromes), syndromes.shape[1], syndromes.shape[0], _ptr(acc_stats),
+                                    _stream(stream)))
 
 
 def window_commit(code: "Code", win_corr: torch.Tensor, cmap: torch.Tensor, n_win: int, syndromes: torch.Tensor,

@@ -108,3 +108,65 @@ def test_one_window_is_the_global_decode(mods):
     np.testing.assert_array_equal(u32(wo), u32(obsp))
     np.testing.assert_array_equal(rbp.stats_to_numpy(ws)["converged"], rbp.stats_to_numpy(st)["converged"])
     dec.close()
+
+
+# ---------------------------------------------------------------- parallel windows
+def test_bits_gather(mods):
+    rbp, _ = mods
+    rng = np.random.default_rng(4)
+    src = rng.integers(0, 2 ** 32, size=(257, 5), dtype=np.uint64).astype(np.uint32)
+    bits = np.unpackbits(src.view(np.uint8), axis=1, bitorder="little")
+    t = torch.from_numpy(src.view(np.int32)).cuda()
+    for rows in ([3], [159, 0, 64, 65, 31, 32], list(rng.permutation(160)[:70]), [5, 200, -1, 7]):
+        r = torch.tensor(rows, dtype=torch.int32, device="cuda")
+        dw = (len(rows) + 31) // 32
+        out = torch.full((257, dw), -1, dtype=torch.int32, device="cuda")
+        rbp.bits_gather(t, r, out)
+        ref = np.zeros((257, dw * 32), dtype=np.uint8)
+        for k, i in enumerate(rows):
+            if 0 <= i < 160:
+                ref[:, k] = bits[:, i]
+        want = np.packbits(ref, axis=1, bitorder="little").view(np.uint32).reshape(257, dw)
+        np.testing.assert_array_equal(u32(out), want)
+
+
+@pytest.mark.parametrize("model,core,buffer,gap,shots", [("phen", 3, 2, 2, 2000), ("phen", 2, 1, 1, 2000),
+                                                          ("circ", 3, 2, 2, 150)])
+def test_parallel_windows_match_oracle(mods, model, core, buffer, gap, shots):
+    rbp, window = mods
+    if model == "phen":
+        dem = W.phenomenological_dem(W.zsz_lp("ZSZ-LP-160"), 12, 5e-3)
+        m = dem.M // 12
+    else:
+        from paper_2607_27644_amd import circuits
+        dem = circuits.memory_dem("ZSZ-LP-160", "X", 2e-3, rounds=6)
+        m = 64
+    g = oracle.Graph(dem.H, dem.O)
+    syn, obs, _ = oracle.sample(g, dem.priors, shots, seed=90 + core)
+    p = rbp.RelayParams()
+    dec = window.ParallelWindowDecoder(dem.H, dem.O, m, core, buffer, gap)
+    corr, obsp, st = dec.decode(dem.priors, torch.from_numpy(syn.view(np.int32)).cuda(), p)
+    op = oracle.RelayParams(**{k: getattr(p, k) for k in oracle.RelayParams.__dataclass_fields__})
+    ref = owin.decode_parallel(dem.H, dem.O, dem.priors, syn, m, core, buffer, gap, op, nthreads=16)
+    same = (u32(corr) == ref["corrections"]).all(axis=1)
+    assert same.mean() >= 0.999, same.mean()
+    assert (u32(obsp)[:, : ref["obs_pred"].shape[1]] == ref["obs_pred"]).all(axis=1).mean() >= 0.999
+    s = rbp.stats_to_numpy(st)
+    assert (s["converged"] == ref["converged"]).mean() >= 0.999
+    assert (s["iters"] == ref["iters"]).mean() >= 0.999
+    dec.close()
+
+
+def test_one_parallel_window_is_the_global_decode(mods):
+    rbp, window = mods
+    dem = W.phenomenological_dem(W.zsz_lp("ZSZ-LP-160"), 6, 5e-3)
+    code = rbp.Code.from_dem(dem)
+    syn, obs, _ = code.sample(dem.priors, 3000, seed=6)
+    p = rbp.RelayParams()
+    corr, obsp, st = code.decode(dem.priors, syn, p)
+    dec = window.ParallelWindowDecoder(dem.H, dem.O, dem.M // 6, 6, 2, 1)
+    wc, wo, ws = dec.decode(dem.priors, syn, p)
+    np.testing.assert_array_equal(u32(wc), u32(corr))
+    np.testing.assert_array_equal(u32(wo), u32(obsp))
+    np.testing.assert_array_equal(rbp.stats_to_numpy(ws)["converged"], rbp.stats_to_numpy(st)["converged"])
+    dec.close()

@@ -68,3 +68,48 @@ def test_converged_shots_explain_the_syndrome(model, w, c):
     np.testing.assert_array_equal(owin._pack(s.astype(np.uint8))[conv], syn[conv])
     o = (e.astype(np.int64) @ dem.O.T.astype(np.int64)) % 2
     np.testing.assert_array_equal(owin._pack(o.astype(np.uint8)), r["obs_pred"])
+
+
+# ---------------------------------------------------------------- parallel windows
+@pytest.mark.parametrize("core,buffer,gap", [(3, 2, 2), (2, 1, 1), (4, 3, 2)])
+def test_parallel_windows_commit_every_column_once(model, core, buffer, gap):
+    dem, m, _, _ = model
+    A, B = owin.parallel_windows(dem.H, m, core, buffer, gap)
+    count = np.zeros(dem.N, dtype=int)
+    for rows, cols, cm in A:
+        count[cols[cm]] += 1
+    for rows, cols, cm, fixed in B:
+        count[cols[cm]] += 1
+        for i, j in fixed:
+            count[j] += 1
+            # a fixing row meets exactly one of the gap's columns
+            gap_cols = np.concatenate([cols, [f[1] for f in fixed]]).astype(int)
+            assert dem.H[i, gap_cols].sum() == 1
+    assert (count[dem.H.any(axis=0)] == 1).all()
+    # every window row meets at least two window columns (the decoder's requirement)
+    for w in A + B:
+        deg = dem.H[w[0]][:, w[1]].sum(axis=1)
+        assert deg.min() >= 2
+
+
+def test_one_parallel_window_is_the_global_decode(model):
+    dem, m, syn, _ = model
+    p = oracle.RelayParams(num_sets=20)
+    ref = oracle.decode(oracle.Graph(dem.H, dem.O), dem.priors, syn, p, nthreads=4)
+    r = owin.decode_parallel(dem.H, dem.O, dem.priors, syn, m, dem.rounds, 2, 1, p, nthreads=4)
+    np.testing.assert_array_equal(r["corrections"], ref["corrections"])
+    np.testing.assert_array_equal(r["obs_pred"][:, : ref["obs_pred"].shape[1]], ref["obs_pred"])
+    np.testing.assert_array_equal(r["converged"], ref["converged"])
+
+
+@pytest.mark.parametrize("core,buffer,gap", [(3, 2, 2), (2, 1, 1)])
+def test_parallel_converged_shots_explain_the_syndrome(model, core, buffer, gap):
+    dem, m, syn, obs = model
+    p = oracle.RelayParams(num_sets=20)
+    r = owin.decode_parallel(dem.H, dem.O, dem.priors, syn, m, core, buffer, gap, p, nthreads=4)
+    conv = r["converged"] == 1
+    assert conv.mean() > 0.85
+    assert not r["residual"][conv].any()
+    e = owin._unpack(r["corrections"], dem.N)
+    s = (e.astype(np.int64) @ dem.H.T.astype(np.int64)) % 2
+    np.testing.assert_array_equal(owin._pack(s.astype(np.uint8))[conv], syn[conv])
