@@ -19,10 +19,10 @@ names:
   sweep      LER against the noise strength p with one interval, and the
              sub-threshold fit p^(d_circ/2) exp(c0 + c1 p + c2 p^2) with its
              extrapolation (Sec. 6.1)
-  window     sliding-window decoding (window w rounds, commit c rounds) of a
-             long phenomenological memory experiment against one global decode:
-             LER, throughput and the single-shot latency of one window
-             (Sec. 6.1 latency discussion)
+  window     sliding-window decoding (window w rounds, commit c rounds) and
+             two-layer parallel-window decoding of a long phenomenological
+             memory experiment against one global decode: LER, throughput and
+             the single-shot latency of one window (Sec. 6.1 latency discussion)
   circuit    circuit-level memory experiments (d rounds of the greedy-AOD
              syndrome extraction, Sec. 7.1 noise model, DEM sizes of Table
              "decoding latency") with the relay intervals of Table "relay gamma
@@ -324,8 +324,9 @@ def ler_sweep(name: str, ps, shots: int, seed: int = 51, params: rbp.RelayParams
 
 def windowed(code_name: str = "ZSZ-LP-160", rounds: int = 30, p: float = 8e-3, shots: int = 200000,
              configs=((10, 1), (10, 5), (5, 1)), seed: int = 71, params: rbp.RelayParams | None = None,
-             latency_shots: int = 300) -> dict:
-    """Sliding-window against global decoding of one T-round memory experiment."""
+             latency_shots: int = 300, parallel=((5, 3, 3), (4, 3, 2), (6, 4, 4))) -> dict:
+    """Sliding-window and parallel-window against global decoding of one
+    T-round memory experiment (parallel: (core, buffer, gap) in rounds)."""
     params = params or rbp.RelayParams()
     dem = workloads.phenomenological_dem(workloads.zsz_lp(code_name), rounds, p)
     m = dem.M // rounds
@@ -369,6 +370,13 @@ def windowed(code_name: str = "ZSZ-LP-160", rounds: int = 30, p: float = 8e-3, s
         r["window_latency_us"] = stats.percentiles(np.array(lat))
         r["window_shape"] = {"rounds": win.rounds, "detectors": nb, "mechanisms": int(win.cols.size)}
         out[f"w{w}_c{c}"] = r
+        dec.close()
+    for core, buf, gap in parallel:
+        dec = window.ParallelWindowDecoder(dem.H, dem.O, m, core, buf, gap)
+        ms, (corr, obsp, st) = _timed(lambda: dec.decode(dem.priors, syn, params))
+        r = summary(obsp, st, ms)
+        r["windows"] = {"A": len(dec.layers[0]), "B": len(dec.layers[1]), "distinct_matrices": len(dec.codes)}
+        out[f"parallel_core{core}_buffer{buf}_gap{gap}"] = r
         dec.close()
     return out
 
