@@ -260,6 +260,17 @@ def _failures(code, dem, priors, syn, obs, params) -> tuple:
     return int(f.sum()), float(s["iters"].mean()), int((s["converged"] == 0).sum())
 
 
+def _model_at(name: str, p: float):
+    """(DEM, priors) of a named model at noise strength p: a circuit-level
+    memory ("circ160x": ZSZ-LP-160, X basis) carries its own merged priors,
+    the other models take p for every mechanism."""
+    if name.startswith("circ"):
+        dem = circuits.memory_dem(f"ZSZ-LP-{name[4:-1]}", name[-1].upper(), p)
+        return dem, dem.priors
+    dem = workloads.workload(name)
+    return dem, np.full(dem.N, p)
+
+
 def gamma_grid(name: str, p: float, gmins, gmaxs, shots: int, seed: int = 41,
                params: rbp.RelayParams | None = None) -> dict:
     """Grid search of [gamma_min, gamma_max] for the lowest LER at noise p.
@@ -270,10 +281,10 @@ def gamma_grid(name: str, p: float, gmins, gmaxs, shots: int, seed: int = 41,
     (gamma_min outer, gamma_max inner loop).  Intervals with gamma_min >
     gamma_max are skipped.
     """
+    import sys
     base = params or rbp.RelayParams()
-    dem = workloads.workload(name)
+    dem, priors = _model_at(name, p)
     code = rbp.Code.from_dem(dem)
-    priors = np.full(dem.N, p)
     syn, obs, _ = code.sample(priors, shots, seed)
     rows = []
     for gmin in gmins:
@@ -285,6 +296,8 @@ def gamma_grid(name: str, p: float, gmins, gmaxs, shots: int, seed: int = 41,
             lo, hi = stats.clopper_pearson(f, shots)
             rows.append({"gamma_min": float(gmin), "gamma_max": float(gmax), "failures": f, "ler": f / shots,
                          "ci95": [lo, hi], "mean_iters": it, "nonconverged": nc})
+            print(f"[gamma] {name} [{gmin}, {gmax}]: {f} failures, {it:.1f} iterations", file=sys.stderr,
+                  flush=True)
     best = min(range(len(rows)), key=lambda i: (rows[i]["failures"], rows[i]["mean_iters"], i))
     return {"model": name, "p": p, "shots": shots, "seed": seed, "grid": rows, "best": rows[best]}
 
@@ -297,13 +310,18 @@ def ler_sweep(name: str, ps, shots: int, seed: int = 51, params: rbp.RelayParams
     weighted by their failure counts, with d_circ defaulting to the code
     distance; the fitted curve is evaluated at p_eval.
     """
+    import sys
     params = params or rbp.RelayParams()
-    dem = workloads.workload(name)
+    dem, _ = _model_at(name, ps[0])
     code = rbp.Code.from_dem(dem)
-    d_circ = float(CODE_DISTANCE.get(name, 0) if d_circ is None else d_circ)
+    if d_circ is None:
+        # circuit-level models: d_circ = d - 2 as the paper takes (App. "more numerics")
+        d_circ = (circuits.DISTANCE[f"ZSZ-LP-{name[4:-1]}"] - 2 if name.startswith("circ")
+                  else CODE_DISTANCE.get(name, 0))
+    d_circ = float(d_circ)
     rows = []
     for i, p in enumerate(ps):
-        priors = np.full(dem.N, p)
+        _, priors = _model_at(name, p)  # the same mechanisms at every p, only their priors change
         syn, obs, _ = code.sample(priors, shots, seed + i)
         f, it, nc = _failures(code, dem, priors, syn, obs, params)
         s = stats.ler_summary(f, shots, dem.rounds, dem.k)
@@ -311,6 +329,7 @@ def ler_sweep(name: str, ps, shots: int, seed: int = 51, params: rbp.RelayParams
         rows.append({"p": float(p), **s, "per_qubit_round_ci95": [stats.per_round(lo, dem.rounds * dem.k),
                                                                    stats.per_round(hi, dem.rounds * dem.k)],
                      "mean_iters": it, "nonconverged": nc})
+        print(f"[sweep] {name} p = {p:g}: {f} failures, {it:.1f} iterations", file=sys.stderr, flush=True)
     out = {"model": name, "rounds": dem.rounds, "k": dem.k, "shots_per_point": shots, "d_circ": d_circ,
            "gamma": [params.gamma_min, params.gamma_max], "points": rows}
     fit = [r for r in rows if r["p"] <= p_fit_max and r["failures"] > 0]
@@ -455,6 +474,8 @@ def main():
     ap.add_argument("--min-errors", type=int, default=100)
     ap.add_argument("--rounds", type=int, default=30)
     ap.add_argument("--p-window", type=float, default=8e-3)
+    ap.add_argument("--num-sets-grid", type=int, default=100, help="relay legs of the gamma and sweep runs")
+    ap.add_argument("--sweep-gamma", default="-0.24,0.66", help="relay interval of the sweep")
     ap.add_argument("--circuit-codes", default="ZSZ-LP-320,ZSZ-LP-390,ZSZ-LP-550")
     ap.add_argument("--p-circuit", type=float, default=1e-3)
     ap.add_argument("--seq-shots", type=int, default=300)
@@ -474,7 +495,7 @@ def main():
         r = learned_exp(a.model, a.pairs, a.shots, [float(x) for x in a.p_eval.split(",")], lo, hi)
     elif a.what == "gamma":
         r = gamma_grid(a.model, a.p, [float(x) for x in a.gmin.split(",")], [float(x) for x in a.gmax.split(",")],
-                       a.shots)
+                       a.shots, params=rbp.RelayParams(num_sets=a.num_sets_grid))
     elif a.what == "window":
         r = windowed(rounds=a.rounds, p=a.p_window, shots=a.shots)
     elif a.what == "awgn":
@@ -483,7 +504,9 @@ def main():
         r = circuit_exp(a.circuit_codes.split(","), a.p_circuit, a.shots, a.seq_shots, a.all_shots, a.num_sets,
                         a.bases)
     elif a.what == "sweep":
-        r = ler_sweep(a.model, [float(x) for x in a.ps.split(",")], a.shots, p_fit_max=a.p_fit_max)
+        gmin, gmax = (float(x) for x in a.sweep_gamma.split(","))
+        r = ler_sweep(a.model, [float(x) for x in a.ps.split(",")], a.shots, p_fit_max=a.p_fit_max,
+                      params=rbp.RelayParams(gamma_min=gmin, gamma_max=gmax, num_sets=a.num_sets_grid))
     else:
         raise SystemExit(__doc__)
     print(json.dumps(r, default=float), flush=True)
