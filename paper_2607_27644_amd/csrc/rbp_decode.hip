@@ -680,6 +680,98 @@ __device__ __forceinline__ void flip_slots(const int32_t* scheck, uint32_t sb, i
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+constexpr int kQuarterRegs = 32;  // edges per lane kept in registers (rows up to 128)
+
+// the four lanes of a row exchange their two smallest magnitudes and sign
+// products: the two smallest of the row are the two smallest of the four pairs
+__device__ __forceinline__ void quarter_combine(uint32_t& min1, uint32_t& min2, uint32_t& sgn) {
+#pragma unroll
+    for (int d = 1; d <= 2; d <<= 1) {
+        const uint32_t b1 = (uint32_t)__shfl_xor((int)min1, d, 64);
+        const uint32_t b2 = (uint32_t)__shfl_xor((int)min2, d, 64);
+        sgn ^= (uint32_t)__shfl_xor((int)sgn, d, 64);
+        const uint32_t hi = min1 < b1 ? b1 : min1;
+        const uint32_t lo2 = min2 < b2 ? min2 : b2;
+        min1 = min1 < b1 ? min1 : b1;
+        min2 = hi < lo2 ? hi : lo2;
+    }
+}
+
+// A quarter of a row group of stored degree D > 32 (multiple of 8): rows
+// q*16 + (lane >> 2) of the group, four lanes per row, lane k of a row taking
+// the edges k, k + 4, ...  The lanes combine their two smallest magnitudes and
+// sign products (quarter_combine), so every message equals the one-lane
+// update's.
+template <bool MIXED, bool LDS, bool KEEP = true, int REGS = kQuarterRegs>
+__device__ __forceinline__ void check_quarter(const State<LDS> X, const int32_t* rp, const int32_t* wp,
+                                              const float* mp, int lane, int q, int D, uint32_t sbit, bool first) {
+    const int k = lane & 3;
+    const uint32_t o = (uint32_t)(q * 16 + (lane >> 2)) * (uint32_t)D;
+    const int32_t* r = rp + o;
+    const int32_t* w = (MIXED ? wp : rp) + o;
+    if (first) {
+        const float* mm = mp + o;
+        for (int p = k; p < D; p += 4) X.st((uint32_t)w[p], __uint_as_float(__float_as_uint(mm[p]) | sbit));
+        return;
+    }
+    uint32_t min1 = 0x7f800000u, min2 = 0x7f800000u, sgn = 0u;
+    if (D <= 4 * REGS) {
+        // rows of up to 128 edges: the lane's messages are gathered at once and
+        // kept in registers for the write pass
+        uint32_t pos[KEEP ? REGS : 1], nv[REGS];
+        if constexpr (KEEP) {
+#pragma unroll
+            for (int i = 0; i < REGS; ++i) pos[i] = k + 4 * i < D ? (uint32_t)r[k + 4 * i] : 0u;
+#pragma unroll
+            for (int i = 0; i < REGS; ++i)
+                nv[i] = k + 4 * i < D ? __float_as_uint(X.ld(pos[i])) : 0x7f800000u;
+        } else {
+#pragma unroll
+            for (int i = 0; i < REGS; ++i)
+                nv[i] = k + 4 * i < D ? __float_as_uint(X.ld((uint32_t)r[k + 4 * i])) : 0x7f800000u;
+        }
+#pragma unroll
+        for (int i = 0; i < REGS; ++i) {
+            const uint32_t av = nv[i] & 0x7fffffffu;
+            sgn ^= nv[i];
+            min2 = umed3(min1, min2, av);
+            min1 = min1 < av ? min1 : av;
+        }
+        quarter_combine(min1, min2, sgn);
+        sgn ^= sbit;
+#pragma unroll
+        for (int i = 0; i < REGS; ++i) {
+            if (k + 4 * i < D) {
+                const uint32_t mag = ((nv[i] & 0x7fffffffu) == min1) ? min2 : min1;
+                const uint32_t at = MIXED ? (uint32_t)w[k + 4 * i] : (KEEP ? pos[KEEP ? i : 0] : (uint32_t)r[k + 4 * i]);
+                X.st(at, __uint_as_float(mag | ((sgn ^ nv[i]) & 0x80000000u)));
+            }
+        }
+        return;
+    }
+    for (int p = k; p < D; p += 4) {
+        const uint32_t n = __float_as_uint(X.ld((uint32_t)r[p]));
+        const uint32_t av = n & 0x7fffffffu;
+        sgn ^= n;
+        min2 = umed3(min1, min2, av);
+        min1 = min1 < av ? min1 : av;
+    }
+    quarter_combine(min1, min2, sgn);
+    sgn ^= sbit;
+    for (int p = k; p < D; p += 4) {
+        const uint32_t n = __float_as_uint(X.ld((uint32_t)r[p]));
+        const uint32_t mag = ((n & 0x7fffffffu) == min1) ? min2 : min1;
+        X.st((uint32_t)w[p], __uint_as_float(mag | ((sgn ^ n) & 0x80000000u)));
+    }
+}
+
+// Rows over 32 edges go in quarters (check_quarter: one gather pass, half the
+// cache lines of the rolled update) in the build with state in device memory
+// and 128 VGPRs (room for a lane's 26 messages).  Circuit-level ZSZ-LP-320 and
+// -550 decode 1.5-1.7x the shots/s of the rolled update.
+template <int RD, bool LDS_STATE, int MINW>
+constexpr bool kQuarterRows = RD > 12 && !LDS_STATE && MINW == 4;
+
 // MINW: waves per SIMD the register allocation must allow (4: up to 128
 // VGPRs; 8: up to 64, for launch shapes whose LDS permits 8 waves per SIMD).
 template <int RD, bool LDS_STATE, int MINW>
@@ -823,12 +915,40 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                         const bool first_plain = t == 1 && !lp;
                         if (!(first_plain && x_mu1)) {
                             // ---- check sweep: one row group per wave at a time
-                            for (int g = wid; g < m.GR; g += nw) {
-                                const int4 gi = m.rgrp[g];
-                                const uint32_t off = (uint32_t)uniform(gi.x);
-                                const uint32_t sbit = ((sigp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u) << 31;
-                                check_dispatch<RD>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane, uniform(gi.y),
-                                                   uniform(gi.z) != 0, sbit, first_plain);
+                            if constexpr (kQuarterRows<RD, LDS_STATE, MINW>) {
+                                // device-memory state, 128-VGPR build: rows over 32 edges in
+                                // quarters of 16 rows, four lanes per row (one gather pass)
+                                for (int u = wid; u < 4 * m.GR; u += nw) {
+                                    const int g = u >> 2, qq = u & 3;
+                                    const int4 gi = m.rgrp[g];
+                                    const int dg = uniform(gi.y);
+                                    const uint32_t off = (uint32_t)uniform(gi.x);
+                                    if (dg > 32) {
+                                        const int rl = qq * 16 + (lane >> 2);
+                                        const uint32_t sbit = ((sigp[2 * g + (rl >> 5)] >> (rl & 31)) & 1u) << 31;
+                                        if (uniform(gi.z) != 0)
+                                            check_quarter<true, LDS_STATE, false, 26>(X, m.rposp + off, m.rposw + off,
+                                                                           m.m1pp + off, lane, qq, dg, sbit,
+                                                                           first_plain);
+                                        else
+                                            check_quarter<false, LDS_STATE, false, 26>(X, m.rposp + off, m.rposw + off,
+                                                                            m.m1pp + off, lane, qq, dg, sbit,
+                                                                            first_plain);
+                                    } else if (qq == 0) {
+                                        const uint32_t sbit = ((sigp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u)
+                                                              << 31;
+                                        check_dispatch<RD>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane, dg,
+                                                           uniform(gi.z) != 0, sbit, first_plain);
+                                    }
+                                }
+                            } else {
+                                for (int g = wid; g < m.GR; g += nw) {
+                                    const int4 gi = m.rgrp[g];
+                                    const uint32_t off = (uint32_t)uniform(gi.x);
+                                    const uint32_t sbit = ((sigp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u) << 31;
+                                    check_dispatch<RD>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane,
+                                                       uniform(gi.y), uniform(gi.z) != 0, sbit, first_plain);
+                                }
                             }
                             __syncthreads();
                             x_mu1 = first_plain;
@@ -1107,83 +1227,6 @@ __device__ __forceinline__ T coop_total(const T* v, int n, int lane) {
     return acc;
 }
 
-constexpr int kQuarterRegs = 32;  // edges per lane kept in registers (rows up to 128)
-
-// the four lanes of a row exchange their two smallest magnitudes and sign
-// products: the two smallest of the row are the two smallest of the four pairs
-__device__ __forceinline__ void quarter_combine(uint32_t& min1, uint32_t& min2, uint32_t& sgn) {
-#pragma unroll
-    for (int d = 1; d <= 2; d <<= 1) {
-        const uint32_t b1 = (uint32_t)__shfl_xor((int)min1, d, 64);
-        const uint32_t b2 = (uint32_t)__shfl_xor((int)min2, d, 64);
-        sgn ^= (uint32_t)__shfl_xor((int)sgn, d, 64);
-        const uint32_t hi = min1 < b1 ? b1 : min1;
-        const uint32_t lo2 = min2 < b2 ? min2 : b2;
-        min1 = min1 < b1 ? min1 : b1;
-        min2 = hi < lo2 ? hi : lo2;
-    }
-}
-
-// A quarter of a row group of stored degree D > 32 (multiple of 8): rows
-// q*16 + (lane >> 2) of the group, four lanes per row, lane k of a row taking
-// the edges k, k + 4, ...  The lanes combine their two smallest magnitudes and
-// sign products (quarter_combine), so every message equals the one-lane
-// update's.
-template <bool MIXED>
-__device__ __forceinline__ void check_quarter(const State<false> X, const int32_t* rp, const int32_t* wp,
-                                              const float* mp, int lane, int q, int D, uint32_t sbit, bool first) {
-    const int k = lane & 3;
-    const uint32_t o = (uint32_t)(q * 16 + (lane >> 2)) * (uint32_t)D;
-    const int32_t* r = rp + o;
-    const int32_t* w = (MIXED ? wp : rp) + o;
-    if (first) {
-        const float* mm = mp + o;
-        for (int p = k; p < D; p += 4) X.st((uint32_t)w[p], __uint_as_float(__float_as_uint(mm[p]) | sbit));
-        return;
-    }
-    uint32_t min1 = 0x7f800000u, min2 = 0x7f800000u, sgn = 0u;
-    if (D <= 4 * kQuarterRegs) {
-        // rows of up to 128 edges: the lane's messages are gathered at once and
-        // kept in registers for the write pass
-        uint32_t pos[kQuarterRegs], nv[kQuarterRegs];
-#pragma unroll
-        for (int i = 0; i < kQuarterRegs; ++i) pos[i] = k + 4 * i < D ? (uint32_t)r[k + 4 * i] : 0u;
-#pragma unroll
-        for (int i = 0; i < kQuarterRegs; ++i) nv[i] = k + 4 * i < D ? __float_as_uint(X.ld(pos[i])) : 0x7f800000u;
-#pragma unroll
-        for (int i = 0; i < kQuarterRegs; ++i) {
-            const uint32_t av = nv[i] & 0x7fffffffu;
-            sgn ^= nv[i];
-            min2 = umed3(min1, min2, av);
-            min1 = min1 < av ? min1 : av;
-        }
-        quarter_combine(min1, min2, sgn);
-        sgn ^= sbit;
-#pragma unroll
-        for (int i = 0; i < kQuarterRegs; ++i) {
-            if (k + 4 * i < D) {
-                const uint32_t mag = ((nv[i] & 0x7fffffffu) == min1) ? min2 : min1;
-                X.st(MIXED ? (uint32_t)w[k + 4 * i] : pos[i], __uint_as_float(mag | ((sgn ^ nv[i]) & 0x80000000u)));
-            }
-        }
-        return;
-    }
-    for (int p = k; p < D; p += 4) {
-        const uint32_t n = __float_as_uint(X.ld((uint32_t)r[p]));
-        const uint32_t av = n & 0x7fffffffu;
-        sgn ^= n;
-        min2 = umed3(min1, min2, av);
-        min1 = min1 < av ? min1 : av;
-    }
-    quarter_combine(min1, min2, sgn);
-    sgn ^= sbit;
-    for (int p = k; p < D; p += 4) {
-        const uint32_t n = __float_as_uint(X.ld((uint32_t)r[p]));
-        const uint32_t mag = ((n & 0x7fffffffu) == min1) ? min2 : min1;
-        X.st((uint32_t)w[p], __uint_as_float(mag | ((sgn ^ n) & 0x80000000u)));
-    }
-}
-
 template <int RD>
 __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1275,10 +1318,10 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
                                 const int rl = qq * 16 + (lane >> 2);
                                 const uint32_t sbit = ((sigp[2 * g + (rl >> 5)] >> (rl & 31)) & 1u) << 31;
                                 if (uniform(gi.z) != 0)
-                                    check_quarter<true>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane, qq, dg,
+                                    check_quarter<true, false>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane, qq, dg,
                                                         sbit, first_plain);
                                 else
-                                    check_quarter<false>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane, qq, dg,
+                                    check_quarter<false, false>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane, qq, dg,
                                                          sbit, first_plain);
                             } else if (qq == 0) {
                                 const uint32_t sbit = ((sigp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u) << 31;
@@ -1691,6 +1734,22 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
         }
     }
     per_cu = std::max(per_cu, 1);
+    if (!lds && cfg.max_slots <= 0 && rdmax > 12) {
+        // rows over 12 edges with device-memory state: the 128-VGPR build (the
+        // 64-VGPR one spills the unrolled 16- to 32-edge rows) when the cache
+        // cap below leaves no more slots than it fits
+        DecodeKernel k4 = decode_kernel(rdmax, lds, 4);
+        int pc4 = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc4, reinterpret_cast<const void*>(k4),
+                                                                    64 * waves, L.lds_bytes);
+        if (e != hipSuccess) return fail(RBP_ERR_HIP, std::string("occupancy query: ") + hipGetErrorString(e));
+        const int cus = std::max(cs[0]->num_cus, 1);
+        const int64_t cap = std::max<int64_t>(kStateCacheBytes / (4 * L.gstride), cus);
+        if ((int64_t)pc4 * cus >= std::min<int64_t>((int64_t)per_cu * cus, cap)) {
+            L.kernel = k4;
+            per_cu = std::max(pc4, 1);
+        }
+    }
     int64_t slots = (int64_t)per_cu * std::max(cs[0]->num_cus, 1);
     if (cfg.max_slots > 0) {
         slots = std::min<int64_t>(slots, cfg.max_slots);
