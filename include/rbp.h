@@ -291,7 +291,7 @@ rbp_status rbp_window_residual(const uint32_t* syn_dev, int32_t words, uint64_t 
  * channel, y_j = 1 + sigma z_j, and decoded by flooding sum-product BP with the
  * phi-domain ("boxplus-phi") check update and single-precision messages.  A
  * handle for this use is made by rbp_code_create from the parity-check matrix
- * with k = 0; rows of degree 2..32 (0 allowed). */
+ * with k = 0; rows of degree 2..32 (0 allowed; UNSUPPORTED otherwise). */
 
 /* Channel LLRs of the all-zero codeword: llr_dev float[shots][N] =
  * 2 y / sigma^2 with y = 1 + sigma z (log P(bit 0 | y) / P(bit 1 | y)).
