@@ -164,7 +164,7 @@ rbp_status rbp_set_launch_config(rbp_code_t code, const rbp_launch_config* cfg);
 rbp_status rbp_get_launch_config(rbp_code_t code, rbp_launch_config* cfg, int32_t* slots, int32_t* lds_bytes);
 
 /* Latency mode: decode shots one after another, each by several workgroups
- * together (the paper's sequential single-shot decoding, Sec. 7.1 Table
+ * together (the paper's sequential single-shot decoding, Sec. 6.1 Table
  * "decoding latency").  The row and variable groups of every sweep are spread
  * over all participating wavefronts; the sweeps are separated by grid
  * barriers.  Results are those of rbp_decode without a prior delta

@@ -4,7 +4,7 @@ Input generator (like ``workloads``): it builds the matrices H, O and the
 priors the decoder is given, and holds none of the sampling or decoding
 arithmetic.
 
-Circuit (Sec. 7.1, quantum circuit-level memory; App. "greedy AOD" scheduling,
+Circuit (Sec. 6.1, quantum circuit-level memory; App. "greedy AOD" scheduling,
 Table "greedy-aod-gate-schedule"):
 
 * qubits: five data blocks Q_1..Q_5 and the check blocks C^X_1, C^X_2,
@@ -22,7 +22,7 @@ Table "greedy-aod-gate-schedule"):
   sum of the disjoint permutations of its three monomials, so the table's
   layers cover H_X and H_Z edge for edge (checked when the layers are built).
 
-Noise (Sec. 7.1): two-qubit depolarizing with probability p after every CNOT,
+Noise (Sec. 6.1): two-qubit depolarizing with probability p after every CNOT,
 preparations flipped with probability p, measurement results flipped with
 probability p; no single-qubit or idle noise.
 

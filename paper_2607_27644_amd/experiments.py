@@ -24,7 +24,7 @@ names:
              memory experiment against one global decode: LER, throughput and
              the single-shot latency of one window (Sec. 6.1 latency discussion)
   circuit    circuit-level memory experiments (d rounds of the greedy-AOD
-             syndrome extraction, Sec. 7.1 noise model, DEM sizes of Table
+             syndrome extraction, Sec. 6.1 noise model, DEM sizes of Table
              "decoding latency") with the relay intervals of Table "relay gamma
              intervals": batched throughput and service times, sequential
              single-shot latency, the all-legs worst case, block LER, per code
