@@ -123,49 +123,63 @@ class PWindow:
     fix_map: torch.Tensor   # int32: the column each of them fixes
 
 
+def parallel_layout(H: np.ndarray, m: int, core: int, buffer: int, gap: int):
+    """The two layers of parallel windows (host only): [layer A, layer B], each
+    a list of (rows, columns, commit mask, fixing rows, fixed columns) as numpy
+    arrays, rows and columns ascending within their parts."""
+    H = np.asarray(H, dtype=np.uint8)
+    M, N = H.shape
+    if M % m:
+        raise ValueError("the detector count must be a multiple of the detectors per round")
+    if core < 1 or buffer < 0 or gap < 1:
+        raise ValueError("need core >= 1, buffer >= 0, gap >= 1")
+    has = H.any(axis=0)
+    first = np.where(has, H.argmax(axis=0) // m, -1)
+    last = np.where(has, (M - 1 - H[::-1].argmax(axis=0)) // m, -1)
+    L, P = M // m, core + gap
+    none = np.zeros(0, dtype=np.int64)
+    A, B = [], []
+    for c0 in range(0, L, P):
+        c1 = min(c0 + core, L)
+        r0, r1 = max(0, c0 - buffer), min(L, c1 + buffer)
+        cols = np.flatnonzero(has & (first < r1) & (last >= r0))
+        commit = (first[cols] >= c0) & (first[cols] < c1)
+        A.append((np.arange(r0 * m, r1 * m), cols, commit, none, none))
+        g0, g1 = c1, min(c0 + P, L)
+        if g0 >= g1:
+            continue
+        cols = np.flatnonzero(has & (first >= g0) & (first < g1))
+        arows = np.flatnonzero(H[g1 * m:, cols].any(axis=1)) + g1 * m
+        fixed_r, fixed_c = [], []
+        for i in arows:
+            hit = cols[H[i, cols] == 1]
+            if hit.size == 1 and hit[0] not in fixed_c:
+                fixed_r.append(i)
+                fixed_c.append(hit[0])
+        cols = np.setdiff1d(cols, np.array(fixed_c, dtype=np.int64))
+        keep = [i for i in arows if int(H[i, cols].sum()) >= 2]
+        rows = np.concatenate([np.arange(g0 * m, g1 * m), np.array(keep, dtype=np.int64)])
+        B.append((rows, cols, np.ones(cols.size, dtype=bool), np.array(fixed_r, dtype=np.int64),
+                  np.array(fixed_c, dtype=np.int64)))
+    return [A, B]
+
+
 class ParallelWindowDecoder:
     def __init__(self, H: np.ndarray, O: np.ndarray, m: int, core: int, buffer: int, gap: int):
         H = np.asarray(H, dtype=np.uint8)
         O = np.asarray(O, dtype=np.uint8)
         M, N = H.shape
-        if M % m:
-            raise ValueError("the detector count must be a multiple of the detectors per round")
-        if core < 1 or buffer < 0 or gap < 1:
-            raise ValueError("need core >= 1, buffer >= 0, gap >= 1")
+        layout = parallel_layout(H, m, core, buffer, gap)
         self.H, self.M, self.N, self.m, self.k = H, M, N, m, O.shape[0]
         self.full = rbp.Code(H, O)
-        has = H.any(axis=0)
-        first = np.where(has, H.argmax(axis=0) // m, -1)
-        last = np.where(has, (M - 1 - H[::-1].argmax(axis=0)) // m, -1)
-        L, P = M // m, core + gap
         self.codes = {}
         self.layers: List[List[PWindow]] = [[], []]
         dev = torch.device("cuda")
-        empty = torch.zeros(0, dtype=torch.int32, device=dev)
-        for c0 in range(0, L, P):
-            c1 = min(c0 + core, L)
-            r0, r1 = max(0, c0 - buffer), min(L, c1 + buffer)
-            cols = np.flatnonzero(has & (first < r1) & (last >= r0))
-            commit = (first[cols] >= c0) & (first[cols] < c1)
-            self.layers[0].append(self._window(np.arange(r0 * m, r1 * m), cols, commit, empty, empty))
-            g0, g1 = c1, min(c0 + P, L)
-            if g0 >= g1:
-                continue
-            cols = np.flatnonzero(has & (first >= g0) & (first < g1))
-            above = H[g1 * m:, cols]
-            arows = np.flatnonzero(above.any(axis=1)) + g1 * m
-            fixed_r, fixed_c = [], []
-            for i in arows:
-                hit = cols[H[i, cols] == 1]
-                if hit.size == 1 and hit[0] not in fixed_c:
-                    fixed_r.append(i)
-                    fixed_c.append(hit[0])
-            cols = np.setdiff1d(cols, np.array(fixed_c, dtype=np.int64))
-            keep = [i for i in arows if int(H[i, cols].sum()) >= 2]
-            rows = np.concatenate([np.arange(g0 * m, g1 * m), np.array(keep, dtype=np.int64)])
-            fr = torch.tensor(fixed_r, dtype=torch.int32, device=dev) if fixed_r else empty
-            fc = torch.tensor(fixed_c, dtype=torch.int32, device=dev) if fixed_c else empty
-            self.layers[1].append(self._window(rows, cols, np.ones(cols.size, dtype=bool), fr, fc))
+        for li, layer in enumerate(layout):
+            for rows, cols, commit, fixed_r, fixed_c in layer:
+                fr = torch.from_numpy(fixed_r.astype(np.int32)).to(dev)
+                fc = torch.from_numpy(fixed_c.astype(np.int32)).to(dev)
+                self.layers[li].append(self._window(rows, cols, commit, fr, fc))
 
     def _window(self, rows, cols, commit, fix_rows, fix_map) -> PWindow:
         Hw = np.ascontiguousarray(self.H[rows][:, cols])

@@ -113,3 +113,27 @@ def test_parallel_converged_shots_explain_the_syndrome(model, core, buffer, gap)
     e = owin._unpack(r["corrections"], dem.N)
     s = (e.astype(np.int64) @ dem.H.T.astype(np.int64)) % 2
     np.testing.assert_array_equal(owin._pack(s.astype(np.uint8))[conv], syn[conv])
+
+
+@pytest.mark.parametrize("core,buffer,gap", [(3, 2, 2), (2, 1, 1), (4, 3, 2)])
+def test_product_parallel_layout_equals_the_oracles(model, core, buffer, gap):
+    """The GPU path's window layout (host code) against the oracle's own
+    construction of the same definition, on a phenomenological and a
+    circuit-level model."""
+    from paper_2607_27644_amd import circuits
+    from paper_2607_27644_amd.window import parallel_layout
+    dem, m, _, _ = model
+    circ = circuits.memory_dem("ZSZ-LP-160", "Z", 2e-3, rounds=4)
+    for H, mm in ((dem.H, m), (circ.H, 64)):
+        prod = parallel_layout(H, mm, core, buffer, gap)
+        orc = owin.parallel_windows(H, mm, core, buffer, gap)
+        assert len(prod[0]) == len(orc[0]) and len(prod[1]) == len(orc[1])
+        for (rows, cols, cm, _, _), (orows, ocols, ocm) in zip(prod[0], orc[0]):
+            np.testing.assert_array_equal(rows, orows)
+            np.testing.assert_array_equal(cols, ocols)
+            np.testing.assert_array_equal(cm, ocm)
+        for (rows, cols, cm, fr, fc), (orows, ocols, ocm, ofixed) in zip(prod[1], orc[1]):
+            np.testing.assert_array_equal(rows, orows)
+            np.testing.assert_array_equal(cols, ocols)
+            np.testing.assert_array_equal(fr, [i for i, _ in ofixed])
+            np.testing.assert_array_equal(fc, [j for _, j in ofixed])
