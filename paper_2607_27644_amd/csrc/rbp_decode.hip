@@ -766,12 +766,16 @@ __device__ __forceinline__ void check_quarter(const State<LDS> X, const int32_t*
     }
 }
 
-// Rows over 32 edges go in quarters (check_quarter: one gather pass, half the
-// cache lines of the rolled update) in the build with state in device memory
-// and 128 VGPRs (room for a lane's 26 messages).  Circuit-level ZSZ-LP-320 and
-// -550 decode 1.5-1.7x the shots/s of the rolled update.
+// Rows over 32 edges go in parts of a group, several lanes per row
+// (check_quarter: one gather pass, half the cache lines of the rolled update),
+// in the build with state in device memory and 128 VGPRs.  Circuit-level
+// ZSZ-LP-320 and -550 decode 1.5-1.7x the shots/s of the rolled update with
+// four lanes per row.
 template <int RD, bool LDS_STATE, int MINW>
 constexpr bool kQuarterRows = RD > 12 && !LDS_STATE && MINW == 4;
+// lanes per wide row there: 8 (13 messages per lane for rows up to 104
+// edges) measured 8-17 % more shots/s than 4 on circuit-level ZSZ-LP-320/-550
+constexpr int kPersLpr = 8;
 
 // MINW: waves per SIMD the register allocation must allow (4: up to 128
 // VGPRs; 8: up to 64, for launch shapes whose LDS permits 8 waves per SIMD).
@@ -919,20 +923,20 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                             if constexpr (kQuarterRows<RD, LDS_STATE, MINW>) {
                                 // device-memory state, 128-VGPR build: rows over 32 edges in
                                 // quarters of 16 rows, four lanes per row (one gather pass)
-                                for (int u = wid; u < 4 * m.GR; u += nw) {
-                                    const int g = u >> 2, qq = u & 3;
+                                for (int u = wid; u < kPersLpr * m.GR; u += nw) {
+                                    const int g = u / kPersLpr, qq = u % kPersLpr;
                                     const int4 gi = m.rgrp[g];
                                     const int dg = uniform(gi.y);
                                     const uint32_t off = (uint32_t)uniform(gi.x);
                                     if (dg > 32) {
-                                        const int rl = qq * 16 + (lane >> 2);
+                                        const int rl = qq * (64 / kPersLpr) + lane / kPersLpr;
                                         const uint32_t sbit = ((sigp[2 * g + (rl >> 5)] >> (rl & 31)) & 1u) << 31;
                                         if (uniform(gi.z) != 0)
-                                            check_quarter<true, LDS_STATE, false, 26>(X, m.rposp + off, m.rposw + off,
+                                            check_quarter<true, LDS_STATE, false, 104 / kPersLpr, kPersLpr>(X, m.rposp + off, m.rposw + off,
                                                                            m.m1pp + off, lane, qq, dg, sbit,
                                                                            first_plain);
                                         else
-                                            check_quarter<false, LDS_STATE, false, 26>(X, m.rposp + off, m.rposw + off,
+                                            check_quarter<false, LDS_STATE, false, 104 / kPersLpr, kPersLpr>(X, m.rposp + off, m.rposw + off,
                                                                             m.m1pp + off, lane, qq, dg, sbit,
                                                                             first_plain);
                                     } else if (qq == 0) {
