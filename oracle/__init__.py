@@ -60,6 +60,9 @@ def lib():
         L.orc_sample.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, i32p, ctypes.c_int32, i32p, i32p, f64p,
                                  ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, u32p, u32p, u32p]
         L.orc_sample.restype = ctypes.c_int
+        L.orc_sample_plain.argtypes = [ctypes.c_int32, f64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                       u32p]
+        L.orc_sample_plain.restype = ctypes.c_int
         L.orc_syndrome.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, i32p, ctypes.c_uint64, u32p, u32p]
         L.orc_decode.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, i32p, ctypes.c_int32, i32p, i32p, f64p,
                                  u32p, ctypes.c_uint64, ctypes.c_void_p, f32p, u32p, u32p, u8p, u8p, u8p, i32p,
@@ -181,6 +184,19 @@ def sample(g: Graph, priors: np.ndarray, shots: int, seed: int, shot_offset: int
     if rc:
         raise RuntimeError(f"orc_sample failed: {rc}")
     return syn, obs, err
+
+
+def sample_plain(N: int, priors: np.ndarray, shots: int, seed: int, shot_offset: int = 0) -> np.ndarray:
+    """Fault words uint32 [shots][ceil(N/32)] from the plain per-mechanism
+    Bernoulli definition (one Philox word per mechanism, e_j = [word < thr_j]):
+    the reference law the gap sampler is checked against."""
+    pr = np.ascontiguousarray(priors, dtype=np.float64)
+    assert pr.size == N
+    err = np.zeros((shots, (N + 31) // 32), dtype=np.uint32)
+    rc = lib().orc_sample_plain(N, _p(pr, ctypes.c_double), shots, seed, shot_offset, _p(err, ctypes.c_uint32))
+    if rc:
+        raise RuntimeError(f"orc_sample_plain failed: {rc}")
+    return err
 
 
 def syndrome(g: Graph, err_words: np.ndarray) -> np.ndarray:

@@ -204,6 +204,39 @@ int orc_sample(int32_t M, int32_t N, const int32_t* col_ptr, const int32_t* row_
     return 0;
 }
 
+/* The plain definition of the fault law, kept beside the gap sampler as the
+   reference its law is pinned against: each mechanism j draws its own word,
+   word (j mod 4) of Philox4x32-10 with key = seed and counter
+   (j / 4, shot lo, shot hi, 0), and faults iff that word is below
+   thr_j = min(floor(p_j 2^32), 2^32 - 1).  One Philox call per four
+   mechanisms, so P(fault) = thr_j / 2^32 exactly, independently over j and
+   shots.  (A different stream from the gap sampler's: the two draw different
+   faults, with the same law.) */
+int orc_sample_plain(int32_t N, const double* priors, uint64_t shots, uint64_t seed, uint64_t shot_offset,
+                     uint32_t* err) {
+    int64_t wn = (N + 31) / 32;
+    uint32_t* thr = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(N > 0 ? N : 1));
+    if (!thr) return -4;
+    for (int32_t j = 0; j < N; ++j) {
+        double t = floor(priors[j] * 4294967296.0);
+        thr[j] = t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t;
+    }
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (uint64_t s = 0; s < shots; ++s) {
+        const uint64_t sid = shot_offset + s;
+        uint32_t* e = err + s * wn;
+        memset(e, 0, sizeof(uint32_t) * (size_t)wn);
+        for (int32_t j = 0; j < N; ++j) {
+            uint32_t w[4];
+            const uint32_t ctr[4] = {(uint32_t)(j / 4), (uint32_t)sid, (uint32_t)(sid >> 32), 0u};
+            orc_philox4x32_10(ctr, key, w);
+            if (w[j % 4] < thr[j]) set_bit(e, j);
+        }
+    }
+    free(thr);
+    return 0;
+}
+
 /* sigma = H e and o = O e for given error words (used to pin the syndrome map). */
 void orc_syndrome(int32_t M, int32_t N, const int32_t* col_ptr, const int32_t* row_idx, uint64_t shots,
                   const uint32_t* err, uint32_t* synd) {

@@ -115,5 +115,11 @@ struct rbp_code {
     rbp::DevBuf spa_queue;              // work counter of the sum-product decoder
     rbp::DevBuf gstate;                 // per-slot state when it does not fit in LDS
     rbp::DevBuf trace_hit;
+    // compact row-record state (rows of at most 16 edges)
+    bool compact_ok = false;
+    int32_t coff_M = 0;                 // LDS offset of the marginals: 16 * 64 GR + 16
+    rbp::DevBuf cvar;                   // int32, layout of rposp: LDS address of each row edge's marginal
+    rbp::DevBuf vrec;                   // uint32[S]: 16 * row position + edge index in the row, per edge slot
+    rbp::DevBuf r1rec;                  // uint4[64 GR]: first-iteration records of a plain leg (per priors)
     rbp::LaunchCfg cfg;
 };

@@ -336,6 +336,11 @@ struct DecodeModel {
     const float2* lg;      // [R+1][Np] {Lambda, gamma} by leg and position
     const int32_t* ocol_ptr;  // [N+1] observables, CSC
     const int32_t* orow_idx;
+    // compact state (rows of at most 16 edges; null otherwise)
+    const int32_t* cvar;      // layout of rposp: LDS byte address of the marginal of each edge's variable
+    const uint32_t* vrec;     // [S] 16 * (row position) + (edge index in the row) of each edge slot
+    const uint4* r1rec;       // [64 GR] first-iteration row records of a plain leg
+    int32_t coff_M;           // LDS offset of the marginals in the compact layout (16 * 64 GR + 16)
     const uint32_t* syn;
     uint32_t* corr;
     uint32_t* obsp;
@@ -1108,6 +1113,452 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
 }
 
 // ---------------------------------------------------------------------------
+// Compact Relay-BP state
+//
+// With min-sum, every message a check sends is fixed by a few numbers of its
+// row: the least and second least |nu_{j->i}| over the row, an edge that
+// attains the least, and the sign of each outgoing message,
+//   mu_{i->j_p} = (p == p* ? m2 : m1) with sign sigma_i xor prod_{p' != p} s(nu_{j_p'->i}).
+// One 16-byte record per row instead of one float per edge cuts a slot's
+// state to 16 bytes per row and 4 per variable, so models such as the
+// 12-round [[840,168]] one (43,680 edges, 13,776 variables) keep it in LDS.
+// nu is not stored: the check sweep forms nu_{j->i}(t-1) = M_j(t-1) -
+// mu_{i->j}(t-1) from the marginals and the previous record -- the subtraction
+// of the extrinsic step on the same FP32 operands -- so every message and
+// marginal equals the per-edge form's bit for bit.
+//
+// Record of the row at position rp (LDS byte address 16 rp):
+//   .x m1   least |nu| of the row (float bits, sign clear)
+//   .y m2   second least (equal to m1 on a tie)
+//   .z sg   bit p (p < 16): sign bit of mu_{i->j_p}; bits 16..31 repeat 0..15
+//   .w ax   16 rp + p*, p* an edge attaining m1
+// Per edge slot the variable sweep holds x = 16 rp + p (vrec): the record is
+// at x & ~15, the message sign is bit (x mod 32) of sg (the repeat makes the
+// low bit of rp that falls into x mod 32 harmless) and the magnitude is m2 iff
+// x == ax.  The marginals follow the records at LDS offset coff_M =
+// 16 * 64 GR + 16; the word at 16 * 64 GR holds +inf, the padding target of
+// mixed row groups (neutral for both minima and the signs).
+// ---------------------------------------------------------------------------
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) u32x4 lds_u32x4;
+
+__device__ __forceinline__ uint4 lds_rec(uint32_t addr) {
+    const u32x4 v = *reinterpret_cast<const lds_u32x4*>((size_t)addr);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void lds_rec_st(uint32_t addr, uint4 v) {
+    u32x4 w;
+    w.x = v.x;
+    w.y = v.y;
+    w.z = v.z;
+    w.w = v.w;
+    *reinterpret_cast<lds_u32x4*>((size_t)addr) = w;
+}
+__device__ __forceinline__ float lds_f(uint32_t addr) { return *reinterpret_cast<const lds_float*>((size_t)addr); }
+
+// the message of edge slot x from its row's record
+__device__ __forceinline__ float rec_mu(uint4 r, uint32_t x) {
+    const uint32_t mag = x == r.w ? r.y : r.x;
+    return __uint_as_float(mag | ((r.z >> (x & 31u)) << 31));
+}
+
+// One row of the compact check update with D stored edges (entries of the
+// lane's cvar block, 16-byte loads).  first: nu = M, the first iteration of a
+// proposal leg (its nu(0) equals its M(0)); otherwise nu = M - mu(old record).
+template <int D>
+__device__ __forceinline__ void compact_row(const int32_t* cp, uint32_t rpx, uint32_t sigma, bool first) {
+    constexpr int Q = (D + 3) / 4;
+    uint32_t pos[4 * Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const int4 v = reinterpret_cast<const int4*>(cp)[k];
+        pos[4 * k] = (uint32_t)v.x;
+        pos[4 * k + 1] = (uint32_t)v.y;
+        pos[4 * k + 2] = (uint32_t)v.z;
+        pos[4 * k + 3] = (uint32_t)v.w;
+    }
+    const uint4 old = lds_rec(rpx);
+    const uint32_t pa = old.w - rpx;
+    uint32_t m1 = 0x7f800000u, m2 = 0x7f800000u, nb = 0u, am = 0u;
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+        const float M = lds_f(pos[p]);
+        uint32_t nu;
+        if (first) {
+            nu = __float_as_uint(M);
+        } else {
+            const uint32_t mag = pa == (uint32_t)p ? old.y : old.x;
+            const float mu = __uint_as_float(mag | ((old.z << (31 - p)) & 0x80000000u));
+            nu = __float_as_uint(M - mu);
+        }
+        const uint32_t av = nu & 0x7fffffffu;
+        nb |= (nu >> 31) << p;
+        m2 = umed3(m1, m2, av);
+        const bool lt = av < m1;
+        m1 = lt ? av : m1;
+        am = lt ? (uint32_t)p : am;
+    }
+    // sign of mu_p = sigma xor (parity of all signs) xor sign(nu_p)
+    const uint32_t flip = 0u - ((((uint32_t)__popc(nb)) ^ sigma) & 1u);
+    const uint32_t sg = (nb ^ flip) & 0xFFFFu;
+    lds_rec_st(rpx, make_uint4(m1, m2, sg | (sg << 16), rpx + am));
+}
+
+// stored row degrees of the compact form: 2..12 exactly, 13..16 padded to 16
+__device__ __forceinline__ void compact_row_dispatch(int dg, const int32_t* cp, uint32_t rpx, uint32_t sigma,
+                                                     bool first) {
+    switch (dg) {
+#define RBP_CROW(D) \
+    case D: compact_row<D>(cp, rpx, sigma, first); break;
+        RBP_CROW(2) RBP_CROW(3) RBP_CROW(4) RBP_CROW(5) RBP_CROW(6) RBP_CROW(7)
+        RBP_CROW(8) RBP_CROW(9) RBP_CROW(10) RBP_CROW(11) RBP_CROW(12) RBP_CROW(16)
+#undef RBP_CROW
+        default: break;
+    }
+}
+
+// One variable with D edge slots (vrec entries slot + 64 q): the marginal
+// Lambda~ + sum_q mu_q in ascending check order.  In a mixed group only the
+// member's own vd edges enter the sum (unused slots hold x = 0, a valid read).
+template <int D, bool MIXED>
+__device__ __forceinline__ float compact_var(const uint32_t* vrec, uint32_t slot, int vd, float acc) {
+    uint32_t x[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) x[q] = ldg(vrec, slot + 64u * q);
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        const float mu = rec_mu(lds_rec(x[q] & ~15u), x[q]);
+        acc = (!MIXED || q < vd) ? acc + mu : acc;
+    }
+    return acc;
+}
+
+// rolled form for larger degrees and traced iterations (then also writes each
+// mu at its CSC edge index)
+__device__ __forceinline__ float compact_var_rolled(const uint32_t* vrec, uint32_t slot, int vd, float acc,
+                                                   float* trace_mu, const int32_t* scsc) {
+    for (int q = 0; q < vd; ++q) {
+        const uint32_t s = slot + 64u * (uint32_t)q;
+        const uint32_t x = ldg(vrec, s);
+        const float mu = rec_mu(lds_rec(x & ~15u), x);
+        acc = acc + mu;
+        if (trace_mu) trace_mu[ldg(scsc, s)] = mu;
+    }
+    return acc;
+}
+
+__device__ __forceinline__ float compact_var_dispatch(const uint32_t* vrec, uint32_t slot, int dg, bool mixed, int vd,
+                                                      float acc) {
+    switch (dg) {
+        case 0: return acc;
+#define RBP_CVAR(D) \
+    case D: return mixed ? compact_var<D, true>(vrec, slot, vd, acc) : compact_var<D, false>(vrec, slot, vd, acc);
+        RBP_CVAR(1) RBP_CVAR(2) RBP_CVAR(3) RBP_CVAR(4) RBP_CVAR(5) RBP_CVAR(6) RBP_CVAR(7) RBP_CVAR(8)
+#undef RBP_CVAR
+        default: return compact_var_rolled(vrec, slot, vd, acc, nullptr, nullptr);
+    }
+}
+
+// a flipped hard decision toggles the parity bits (by row position) of the
+// variable's checks
+__device__ __forceinline__ void compact_flip(const uint32_t* vrec, uint32_t slot, int vd, uint32_t* par,
+                                             int& dcount) {
+    for (int q = 0; q < vd; ++q) {
+        const uint32_t rp = ldg(vrec, slot + 64u * (uint32_t)q) >> 4;
+        const uint32_t bit = 1u << (rp & 31u);
+        const uint32_t old = atomicXor(par + (rp >> 5), bit);
+        dcount += (old & bit) ? -1 : 1;
+    }
+}
+
+// Persistent Relay-BP on the compact state (always in LDS); the shot queue,
+// phases, legs, stop rule, statistics and outputs are those of
+// relay_bp_kernel.  The parity bits of the hard decision are kept by row
+// position (initialised from the syndrome's row-position ballots).
+template <int MINW>
+__global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const DecodeLaunch a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63;
+    const int wid = uniform(tid >> 6), nw = nth >> 6;
+    uint32_t* sig = reinterpret_cast<uint32_t*>(smem + a.off_sig);
+    uint32_t* sigp = reinterpret_cast<uint32_t*>(smem + a.off_sigp);
+    uint32_t* par = reinterpret_cast<uint32_t*>(smem + a.off_par);
+    uint32_t* bestp = reinterpret_cast<uint32_t*>(smem + a.off_bestp);
+    uint32_t* best = reinterpret_cast<uint32_t*>(smem + a.off_best);
+    uint32_t* obw = reinterpret_cast<uint32_t*>(smem + a.off_obs);
+    SlotMisc* ms = reinterpret_cast<SlotMisc*>(smem + a.off_misc);
+
+    unsigned long long run_next = 0, run_end = 0, last_ticket = 0;
+    for (;;) {
+        if (tid == 0) {
+            if (run_next == run_end) {
+                const unsigned long long k =
+                    last_ticket + 8ull * kShotRun * gridDim.x < a.shots ? (unsigned long long)kShotRun : 1ull;
+                run_next = atomicAdd(a.queue, k);
+                run_end = run_next + k;
+                last_ticket = run_next;
+            }
+            ms->shot = run_next++;
+            ms->count = 0;
+            ms->W = 0.0;
+            ms->red[0] = 0;
+        }
+        __syncthreads();
+        const unsigned long long s = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(ms->shot >> 32))
+                                      << 32) |
+                                     __builtin_amdgcn_readfirstlane((uint32_t)ms->shot);
+        if (s >= a.shots) break;
+        const uint64_t t_start = wall_clock64();
+        const int mi = a.shot_code ? uniform((int)a.shot_code[s]) : 0;
+        const DecodeModel& m = a.m[mi < a.n_models ? mi : 0];
+        const uint64_t row =
+            a.shot_index ? (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(a.shot_index[s]) : (uint64_t)s;
+        const int N = m.N, WM = m.WM, WN = m.WN;
+        const float* dlt = a.delta ? a.delta + row * (uint64_t)N : nullptr;
+        float* Mg = reinterpret_cast<float*>(smem + m.coff_M);
+        if (tid == 0) Mg[-4] = INFINITY;  // the padding cell at 16 * 64 GR
+        int pc = 0;
+        for (int w = tid; w < WM; w += nth) {
+            const uint32_t v = m.syn[row * WM + w];
+            sig[w] = v;
+            pc += __popc(v);
+        }
+        for (int w = tid; w < m.WK; w += nth) obw[w] = 0u;
+        for (int w = tid; w < WN; w += nth) best[w] = 0u;
+        if (pc) atomicAdd(&ms->red[0], pc);
+        __syncthreads();
+        const int base = uniform(ms->red[0]);
+
+        int nconv = 0, legs = 0, iters = 0, path = 0;
+        bool have_best = false;
+        double bestW = 0.0;
+        bool traced = false;
+
+        if (base == 0) {
+            path = 3;
+            have_best = true;
+        } else {
+            // syndrome bits by row position (one ballot per row group)
+            for (int g = wid; g < m.GR; g += nw) {
+                const int i = m.rord[g * 64 + lane];
+                const bool b = i >= 0 && ((sig[i >> 5] >> (i & 31)) & 1u);
+                const unsigned long long bb = __ballot(b);
+                if (lane == 0) {
+                    sigp[2 * g] = (uint32_t)bb;
+                    sigp[2 * g + 1] = (uint32_t)(bb >> 32);
+                }
+            }
+            const int first_phase = dlt ? 1 : 0;
+            for (int phase = first_phase; phase >= 0; --phase) {
+                const bool prop = phase == 1;
+                __syncthreads();  // sigp complete; the previous phase's counters read
+                if (tid == 0) {
+                    ms->count = 0;
+                    ms->W = 0.0;
+                }
+                for (int w = tid; w < 2 * m.GR; w += nth) par[w] = sigp[w];
+                __syncthreads();
+                {
+                    // M(0) = Lambda (or Lambda + delta, whose negative entries are the
+                    // starting hard decision)
+                    int dc = 0;
+                    double dW = 0.0;
+                    for (int pp = tid; pp < m.Np; pp += nth) {
+                        const float l = ldg(m.lamp, pp);
+                        float x = l;
+                        if (prop) {
+                            const int j = ldg(m.vord, pp);
+                            x = j >= 0 ? l + dlt[j] : 0.0f;
+                            if (x < 0.0f) {
+                                const uint32_t slot = (uint32_t)ldg(m.vgrp, pp >> 6).x + (uint32_t)(pp & 63);
+                                compact_flip(m.vrec, slot, ldg(m.vdeg, pp), par, dc);
+                                dW += (double)l;
+                            }
+                        }
+                        Mg[pp] = x;
+                    }
+                    if (dc) atomicAdd(&ms->count, dc);
+                    if (dW != 0.0) atomicAdd(&ms->W, dW);
+                    __syncthreads();
+                }
+
+                const int nlegs = prop ? 0 : a.R;
+                for (int leg = 0; leg <= nlegs; ++leg) {
+                    const bool lp = prop && leg == 0;
+                    const int T = leg == 0 ? a.T0 : a.Tr;
+                    const float2* lgl = m.lg + (int64_t)leg * m.Np;
+                    bool conv = false;
+                    ++legs;
+                    for (int t = 1; t <= T; ++t) {
+                        // ---- check sweep: one row group per wave at a time
+                        const bool first_plain = t == 1 && !lp;
+                        for (int g = wid; g < m.GR; g += nw) {
+                            const uint32_t rp = (uint32_t)(g * 64 + lane);
+                            const uint32_t sigma = (sigp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u;
+                            if (first_plain) {
+                                // nu(0) = Lambda > 0: the model's first records, signs = sigma
+                                const uint4 r = ldg(m.r1rec, rp);
+                                lds_rec_st(16u * rp, make_uint4(r.x, r.y, 0u - sigma, r.w));
+                            } else {
+                                const int4 gi = m.rgrp[g];
+                                const uint32_t off = (uint32_t)uniform(gi.x) + (uint32_t)lane * (uint32_t)uniform(gi.w);
+                                compact_row_dispatch(uniform(gi.y), m.cvar + off, 16u * rp, sigma, t == 1);
+                            }
+                        }
+                        __syncthreads();
+                        // ---- variable sweep
+                        const bool tr = a.trace_on && phase == a.trace_phase && leg == a.trace_leg && t == a.trace_t;
+                        int dcount = 0;
+                        double dW = 0.0;
+                        for (int g = wid; g < m.GV; g += nw) {
+                            const int4 gi = m.vgrp[g];
+                            const int dg = uniform(gi.y);
+                            const bool mixed = uniform(gi.z) != 0;
+                            const uint32_t pp = (uint32_t)(g * 64 + lane);
+                            const float2 lgv = ldg(lgl, pp);
+                            const float l = lgv.x, gm = lgv.y;
+                            float lt = l;
+                            if (lp) {
+                                const int j = ldg(m.vord, pp);
+                                if (j >= 0) lt = l + dlt[j];
+                            }
+                            const float mo = Mg[pp];
+                            float acc = __builtin_fmaf(gm, mo - lt, lt);
+                            const uint32_t slot = (uint32_t)uniform(gi.x) + (uint32_t)lane;
+                            const int vd = mixed ? ldg(m.vdeg, pp) : dg;
+                            if (!tr) {
+                                acc = compact_var_dispatch(m.vrec, slot, dg, mixed, vd, acc);
+                            } else {
+                                acc = compact_var_rolled(m.vrec, slot, vd, acc, a.trace_mu, m.scsc);
+                                const int j = ldg(m.vord, pp);
+                                if (j >= 0) a.trace_M[j] = acc;
+                            }
+                            Mg[pp] = acc;
+                            if ((acc < 0.0f) != (mo < 0.0f)) {
+                                compact_flip(m.vrec, slot, vd, par, dcount);
+                                dW += acc < 0.0f ? (double)l : -(double)l;
+                            }
+                        }
+                        if (dcount) atomicAdd(&ms->count, dcount);
+                        if (dW != 0.0) atomicAdd(&ms->W, dW);
+                        __syncthreads();
+                        ++iters;
+                        if (tr) {
+                            if (tid == 0) *a.trace_hit = 1;
+                            traced = true;
+                            break;
+                        }
+                        // (the next check sweep's barrier orders this read before the
+                        // next variable sweep's atomics)
+                        if (base + uniform(ms->count) == 0) {
+                            conv = true;
+                            break;
+                        }
+                    }
+                    if (traced) break;
+                    if (conv) {
+                        const double W = ms->W;
+                        if (!have_best || W < bestW) {
+                            bestW = W;
+                            have_best = true;
+                            for (int g = wid; g < m.GV; g += nw) {
+                                const unsigned long long b = __ballot(Mg[g * 64 + lane] < 0.0f);
+                                if (lane == 0) {
+                                    bestp[2 * g] = (uint32_t)b;
+                                    bestp[2 * g + 1] = (uint32_t)(b >> 32);
+                                }
+                            }
+                        }
+                        ++nconv;
+                        if (a.crit == 0 && nconv >= a.S) break;
+                    }
+                }
+                if (traced) break;
+                if (prop) {
+                    if (nconv > 0) {
+                        path = 1;
+                        break;
+                    }
+                    path = 2;
+                }
+            }
+            if (!have_best) {
+                for (int g = wid; g < m.GV; g += nw) {
+                    const unsigned long long b = __ballot(Mg[g * 64 + lane] < 0.0f);
+                    if (lane == 0) {
+                        bestp[2 * g] = (uint32_t)b;
+                        bestp[2 * g + 1] = (uint32_t)(b >> 32);
+                    }
+                }
+            }
+            for (int g = wid; g < m.GV; g += nw) {
+                if ((bestp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u) {
+                    const int j = ldg(m.vord, (uint32_t)(g * 64 + lane));
+                    atomicOr(best + (j >> 5), 1u << (j & 31));
+                }
+            }
+            __syncthreads();
+        }
+        if (!a.trace_on) {
+            for (int w = tid; w < WN; w += nth) {
+                const uint32_t bits = best[w];
+                m.corr[row * WN + w] = bits;
+                uint32_t b = bits;
+                while (b) {
+                    const int j = w * 32 + __builtin_ctz(b);
+                    b &= b - 1u;
+                    for (int e = m.ocol_ptr[j]; e < m.ocol_ptr[j + 1]; ++e) {
+                        const int r = m.orow_idx[e];
+                        atomicXor(obw + (r >> 5), 1u << (r & 31));
+                    }
+                }
+            }
+            __syncthreads();
+            if (m.obsp)
+                for (int w = tid; w < m.WK; w += nth) m.obsp[row * m.WK + w] = obw[w];
+            if (a.stats && tid == 0) {
+                rbp_shot_stats st;
+                st.converged = have_best ? 1 : 0;
+                st.nconv = (uint8_t)(nconv > 255 ? 255 : nconv);
+                st.path = (uint8_t)path;
+                st.reserved = 0;
+                st.legs = (uint16_t)(legs > 65535 ? 65535 : legs);
+                st.reserved2 = 0;
+                st.iters = (uint32_t)iters;
+                st.reserved3 = 0;
+                st.t_start = t_start;
+                st.t_end = wall_clock64();
+                a.stats[a.stats_by_row ? row : s] = st;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// First-iteration records of a plain leg (nu(0) = Lambda > 0): per row
+// position, the two least Lambda of the row and the edge of the least; sg = 0
+// (the kernel inserts sigma); padding positions get +inf magnitudes.
+__global__ void first_record_kernel(const int32_t* row_ptr, const int32_t* col_idx, const int32_t* rord,
+                                    const float* lam, uint4* r1rec, int32_t npos) {
+    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= npos) return;
+    const int i = rord[pos];
+    uint32_t m1 = 0x7f800000u, m2 = 0x7f800000u, am = 0u;
+    if (i >= 0) {
+        const int rs = row_ptr[i], re = row_ptr[i + 1];
+        for (int e = rs; e < re; ++e) {
+            const uint32_t av = __float_as_uint(lam[col_idx[e]]) & 0x7fffffffu;
+            m2 = umed3(m1, m2, av);
+            if (av < m1) {
+                m1 = av;
+                am = (uint32_t)(e - rs);
+            }
+        }
+    }
+    r1rec[pos] = make_uint4(m1, m2, 0u, 16u * (uint32_t)pos + am);
+}
+
+// ---------------------------------------------------------------------------
 // Cooperative single-shot Relay-BP (latency mode)
 //
 // One shot at a time, decoded by G workgroups together: the row and variable
@@ -1506,6 +1957,14 @@ static rbp_status ensure_llr(rbp_code* c, const double* priors, hipStream_t stre
                        c->col_idx.as<int32_t>(), c->rord.as<int32_t>(), c->rgrp.as<int4>(), c->lam.as<float>(),
                        c->m1.as<float>(), npos);
     RBP_HIP_CHECK(hipGetLastError());
+    if (c->compact_ok) {
+        st = c->r1rec.reserve(sizeof(uint4) * (size_t)npos);
+        if (st) return st;
+        hipLaunchKernelGGL(first_record_kernel, dim3(ceil_div(npos, 256)), dim3(256), 0, stream,
+                           c->row_ptr.as<int32_t>(), c->col_idx.as<int32_t>(), c->rord.as<int32_t>(),
+                           c->lam.as<float>(), c->r1rec.as<uint4>(), npos);
+        RBP_HIP_CHECK(hipGetLastError());
+    }
     c->lam_key.assign(priors, priors + c->N);
     ++c->lam_gen;
     return RBP_OK;
@@ -1628,6 +2087,10 @@ static DecodeModel model_of(const rbp_code* c, const uint32_t* syn, uint32_t* co
     m.lg = c->lg.as<float2>();
     m.ocol_ptr = c->ocol_ptr.as<int32_t>();
     m.orow_idx = c->orow_idx.as<int32_t>();
+    m.cvar = c->cvar.as<int32_t>();
+    m.vrec = c->vrec.as<uint32_t>();
+    m.r1rec = c->r1rec.as<uint4>();
+    m.coff_M = c->coff_M;
     m.syn = syn;
     m.corr = corr;
     m.obsp = c->k > 0 ? obsp : nullptr;
@@ -1635,6 +2098,10 @@ static DecodeModel model_of(const rbp_code* c, const uint32_t* syn, uint32_t* co
 }
 
 typedef void (*DecodeKernel)(const DecodeLaunch);
+
+static DecodeKernel compact_kernel(int minw) {
+    return minw >= 8 ? relay_bp_compact_kernel<8> : relay_bp_compact_kernel<4>;
+}
 
 static DecodeKernel decode_kernel(int max_stored_row_deg, bool lds, int minw) {
     if (max_stored_row_deg <= 12) {
@@ -1653,6 +2120,7 @@ static constexpr int64_t kStateCacheBytes = 192ll << 20;
 struct LaunchShape {
     int waves = 1;
     bool lds_state = true;
+    bool compact = false;  // compact row-record state (always in LDS)
     DecodeKernel kernel = nullptr;
     int lds_bytes = 0;
     int slots = 1;
@@ -1681,15 +2149,35 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
                       align16(4 * (int64_t)(Npmax / 32)) + align16(4 * (int64_t)WNmax) + align16(4 * (int64_t)WKmax) +
                       align16(sizeof(SlotMisc));
     const int64_t state_bytes = align16(4 * ((int64_t)Smax + 2)) + align16(4 * (int64_t)Npmax);
+    // compact row-record state: every model's rows within 16 edges; the
+    // records and marginals of each model at its own offsets, the small arrays
+    // after the largest
+    bool compact_ok = true;
+    int64_t compact_bytes = 0;
+    for (int i = 0; i < n; ++i) {
+        compact_ok = compact_ok && cs[i]->compact_ok;
+        compact_bytes = std::max<int64_t>(compact_bytes, (int64_t)cs[i]->coff_M + 4 * (int64_t)cs[i]->Np);
+    }
+    compact_bytes = align16(compact_bytes);
+    const bool compact_fits = compact_ok && compact_bytes + small <= kMaxLds;
     bool lds = state_bytes + small <= kMaxLds;
+    bool compact = false;
     if (cfg.state == 1 && !lds) return fail(RBP_ERR_UNSUPPORTED, "per-shot state does not fit in LDS");
+    if (cfg.state == 3 && !compact_fits)
+        return fail(RBP_ERR_UNSUPPORTED, "compact state needs rows of at most 16 edges and must fit in LDS");
     if (cfg.state == 2) lds = false;
+    if (cfg.state == 3 || (cfg.state == 0 && !lds && compact_fits)) {
+        // the per-edge state does not fit in LDS but the row records do
+        compact = true;
+        lds = true;
+    }
     int waves = cfg.waves_per_shot;
     if (waves <= 0) {
         if (lds) {
             // about 8 waves per SIMD (32 per CU) over the slots that fit in LDS, and
             // at least min(4, groups) waves so that a slow shot is not left to one wave
-            const int per_cu_lds = (int)std::max<int64_t>(kMaxLds / (state_bytes + small), 1);
+            const int64_t per_slot = (compact ? compact_bytes : state_bytes) + small;
+            const int per_cu_lds = (int)std::max<int64_t>(kMaxLds / per_slot, 1);
             int groups = 0;
             for (int i = 0; i < n; ++i) groups = std::max(groups, std::max(cs[i]->GR, cs[i]->GV));
             waves = 1;
@@ -1705,9 +2193,12 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
     LaunchShape L;
     L.waves = waves;
     L.lds_state = lds;
+    L.compact = compact;
     L.Smax = Smax;
     int64_t off = 0;
-    if (lds) {
+    if (compact) {
+        off = compact_bytes;
+    } else if (lds) {
         off = align16(4 * ((int64_t)Smax + 2));
         L.off_M = (int)off;
         off += align16(4 * (int64_t)Npmax);
@@ -1733,7 +2224,7 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
     // tie the larger budget (no spills)
     int per_cu = 0;
     for (int minw : {4, 8}) {
-        DecodeKernel k = decode_kernel(rdmax, lds, minw);
+        DecodeKernel k = compact ? compact_kernel(minw) : decode_kernel(rdmax, lds, minw);
         int pc = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, reinterpret_cast<const void*>(k), 64 * waves,
                                                                     L.lds_bytes);
@@ -1971,13 +2462,28 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
     if (RB > (int64_t)INT32_MAX) return fail(RBP_ERR_UNSUPPORTED, "too many edges");
     std::vector<int32_t> rposp(std::max<int64_t>(RB, 1), (int32_t)(4 * S)),
         rposw(std::max<int64_t>(RB, 1), (int32_t)(4 * (S + 1))), rfill(M, 0);
+    // compact state (rows of at most 16 edges): LDS address of each row edge's
+    // marginal (records first, then the +inf cell, then the marginals), and
+    // 16 * row position + edge index for each edge slot
+    const bool compact_ok = maxstored <= 16;
+    const int64_t crec = 16 * 64 * (int64_t)GR;
+    const int32_t coff_M = (int32_t)(crec + 16);
+    std::vector<int32_t> vinv(N), cvar(compact_ok ? std::max<int64_t>(RB, 1) : 1, (int32_t)crec);
+    std::vector<uint32_t> vrec(compact_ok ? std::max<int64_t>(S, 1) : 1, 0u);
+    for (int p = 0; p < N; ++p) vinv[vord[p]] = p;
     for (int j = 0; j < N; ++j)
         for (int e = col_ptr[j]; e < col_ptr[j + 1]; ++e) {
             const int i = row_idx[e], p = rfill[i]++, pos = rinv[i];
             const size_t at = (size_t)rgrp[4 * (pos >> 6)] + (size_t)(pos & 63) * rgrp[4 * (pos >> 6) + 3] + p;
             rposp[at] = 4 * slot_of[e];
             rposw[at] = 4 * slot_of[e];
+            if (compact_ok) {
+                cvar[at] = coff_M + 4 * vinv[j];
+                vrec[slot_of[e]] = 16u * (uint32_t)pos + (uint32_t)p;
+            }
         }
+    if (compact_ok && (int64_t)coff_M + 4 * (int64_t)Np > (int64_t)INT32_MAX)
+        return fail(RBP_ERR_UNSUPPORTED, "too many rows");
     // CSR of O
     std::vector<int32_t> orp(k + 1, 0), oci(std::max(nnzO, 1)), ofill(std::max(k, 1), 0);
     if (k > 0) {
@@ -2003,6 +2509,8 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
     c->Np = Np;
     c->RB = (int32_t)RB;
     c->max_stored_row_deg = maxstored;
+    c->compact_ok = compact_ok;
+    c->coff_M = coff_M;
     c->h_vord = vord;
     hipError_t he = hipGetDevice(&c->device);
     if (he == hipSuccess) he = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device);
@@ -2035,6 +2543,8 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
     if (!st) st = upload(c->ocol_idx, oci);
     if (!st) st = upload(c->ocol_ptr, ocp);
     if (!st) st = upload(c->orow_idx, ori);
+    if (!st && compact_ok) st = upload(c->cvar, cvar);
+    if (!st && compact_ok) st = upload(c->vrec, vrec);
     if (st) {
         rbp_code_destroy(c);
         return st;
@@ -2049,7 +2559,8 @@ rbp_status rbp_code_destroy(rbp_code_t c) {
     for (DevBuf* b : {&c->row_ptr, &c->col_idx, &c->col_ptr, &c->csc_row, &c->rgrp, &c->rposp, &c->rposw, &c->rord, &c->vgrp,
                       &c->vord, &c->vdeg, &c->scheck, &c->scsc, &c->orow_ptr, &c->ocol_idx, &c->ocol_ptr,
                       &c->orow_idx, &c->thr, &c->lam, &c->lamp, &c->m1, &c->gtab, &c->lg, &c->queue, &c->gstate,
-                      &c->trace_hit, &c->spa_queue, &c->gapt, &c->order, &c->ohist, &c->coop})
+                      &c->trace_hit, &c->spa_queue, &c->gapt, &c->order, &c->ohist, &c->coop, &c->cvar, &c->vrec,
+                      &c->r1rec})
         b->release();
     delete c;
     return RBP_OK;
@@ -2315,7 +2826,7 @@ rbp_status rbp_code_llr(rbp_code_t c, const double* priors, float* llr, void* st
 
 rbp_status rbp_set_launch_config(rbp_code_t c, const rbp_launch_config* cfg) {
     if (!c || !cfg) return fail(RBP_ERR_INVALID_ARG, "NULL argument");
-    if (cfg->waves_per_shot < 0 || cfg->waves_per_shot > 16 || cfg->state < 0 || cfg->state > 2 ||
+    if (cfg->waves_per_shot < 0 || cfg->waves_per_shot > 16 || cfg->state < 0 || cfg->state > 3 ||
         cfg->max_slots < 0)
         return fail(RBP_ERR_INVALID_ARG, "launch config out of range");
     c->cfg.waves_per_shot = cfg->waves_per_shot;
@@ -2332,7 +2843,7 @@ rbp_status rbp_get_launch_config(rbp_code_t c, rbp_launch_config* cfg, int32_t* 
     if (st) return st;
     if (cfg) {
         cfg->waves_per_shot = L.waves;
-        cfg->state = L.lds_state ? 1 : 2;
+        cfg->state = L.compact ? 3 : L.lds_state ? 1 : 2;
         cfg->max_slots = c->cfg.max_slots;
     }
     if (slots) *slots = L.slots;

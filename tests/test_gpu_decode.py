@@ -391,12 +391,14 @@ def test_full_size_decode_sampled(rbp):
 
 
 # ----------------------------------------------------------------- largest models, sampled check
-@pytest.mark.parametrize("name,shots,checked", [("phen840", 20000, 300), ("hgp56", 4000, 60)])
+@pytest.mark.parametrize("name,shots,checked", [("phen840", 20000, 3000), ("hgp56", 4000, 1000)])
 def test_largest_models_sampled(rbp, name, shots, checked):
-    """Full-size launches on the largest models (per-slot state in device
-    memory); the oracle decodes a spread sample of the same shots."""
+    """Full-size launches on the largest models with the per-slot state in
+    device memory; the oracle decodes a spread sample of the same shots, and
+    the corrections must be identical on >= 99.9 % of them."""
     dem = dem_of(name)
     code = rbp.Code.from_dem(dem)
+    code.set_launch_config(0, 2, 0)
     params = rbp.RelayParams()
     syn, obs, _ = code.sample(dem.priors, shots, seed=4242)
     corr, obsp, st = code.decode(dem.priors, syn, params)
@@ -406,7 +408,7 @@ def test_largest_models_sampled(rbp, name, shots, checked):
     syn_np = u32(syn)[idx]
     ref = oracle.decode(oracle.Graph(dem.H, dem.O), dem.priors, syn_np, oparams(params), nthreads=16)
     same = (u32(corr)[idx] == ref["corrections"]).all(axis=1)
-    assert same.mean() >= 0.99, same.mean()
+    assert same.mean() >= 0.999, same.mean()
     s = rbp.stats_to_numpy(st)
     assert np.array_equal(s["iters"][idx][same], ref["iters"][same])
     # converged corrections reproduce their syndromes (checked on the sample)
