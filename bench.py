@@ -1,15 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the Monte-Carlo Relay-BP path on one MI355X.
 
-One step = sample a batch of shots of the phenomenological ZSZ-LP-160 model
-(9 rounds, 576 detectors x 1952 mechanisms, priors 1e-3) on the GPU, decode it
-with Relay-BP (gamma0 0.125, pre_iter 80, max_iterations 60, 100 relay legs,
-stop_nconv 5, gamma in [-0.24, 0.66]) and count block failures on the GPU; the
-failure count comes back to the host at the end of the timed steps.  The
-learned path adds the proposal network's forward pass before decoding.
-Beside the headline: the classical AWGN benchmark, sequential single-shot
-latency, and the paper's latency-table workload (circuit-level ZSZ-LP-320
-memory decoded one shot at a time in latency mode).  Prints one JSON line.
+Workload: the largest single-GPU configuration, the 12-round phenomenological
+detector error model of the [[840,168]] ZSZ-LP code (Table "more ZSZ-LP
+codes"; 4032 detectors x 13776 mechanisms, nnz 43680), all priors 1e-3,
+Relay-BP with gamma0 0.125, pre_iter 80, max_iterations 60, 100 relay legs,
+stop_nconv 5, gamma in [-0.24, 0.66], FP32 messages.  One step = sample a
+batch of shots on the GPU, decode it, count block failures on the GPU; the
+failure count comes back to the host after the timed steps.
+
+Paths, each timed the same way on the same shots:
+  plain           Relay-BP (the headline `value`)
+  first_solution  Relay-BP stopping at its first solution (stop_nconv 1): the
+                  stop rule of the proposal path without a proposal
+  learned         proposal network (trained in-run on decoder-generated pairs)
+                  -> proposal leg, plain Relay-BP as the fallback
+  proposal_zero   the same proposal leg with delta = 0 (no network)
+A p = 5e-3 point decodes the same syndromes with every path so that the
+logical-error comparison has failures.  Beside the headline: sequential
+single-shot latency, the batched uneven decode of four codes, the paper's
+latency-table workload (circuit-level ZSZ-LP-320 memory), the classical AWGN
+benchmark and the earlier ZSZ-LP-160 workload.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -24,25 +35,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "decoded shots/s + p50/p99 latency at fixed LER: Relay-BP vs learned proposal"
-LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
+LDS_NOMINAL_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz (a CDNA3-style figure)
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--shots", type=int, default=100000)
-    ap.add_argument("--workload", default="phen160")
+    ap.add_argument("--workload", default="phen840")
     ap.add_argument("--seed", type=int, default=20260101)
+    ap.add_argument("--ler-p", type=float, default=5e-3)
+    ap.add_argument("--ler-shots", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sequential", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--train-pairs", type=int, default=1_000_000)
-    ap.add_argument("--no-awgn", action="store_true")
-    ap.add_argument("--no-circuit", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates rocprof byte counters)")
     return ap.parse_args()
@@ -67,7 +80,19 @@ def load_traffic(workload: str, launch_shots: int):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(dem, shots_total: int, seed: int, params, target_s: float):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(dem, seed: int, params, target_s: float):
+    """The oracle (sampler + Relay-BP) on the host's cores, on the first shots
+    of the timed steps' seed."""
     import numpy as np
 
     import oracle
@@ -81,73 +106,25 @@ def cpu_baseline(dem, shots_total: int, seed: int, params, target_s: float):
         r = oracle.decode(g, dem.priors, syn, op, nthreads=threads, timing=True)
         return time.perf_counter() - t0, r
 
-    dt, _ = run(2000)
-    # about target_s of work, at most 10 steps' worth of shots
-    n = int(min(10 * shots_total, max(2000, 2000 * target_s / max(dt, 1e-3))))
+    dt, _ = run(1000)
+    n = int(max(1000, 1000 * target_s / max(dt, 1e-3)))
     dt, r = run(n)
     return {"value": n / dt, "unit": "shots/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} shots of the same model and seed (the first {min(n, shots_total)} are the first "
-                      f"timed step's shots): oracle sampling + Relay-BP decode on {threads} threads, {dt:.1f} s",
+            "sample": f"the first {n} shots of the first timed step (same model, seed and relay settings): "
+                      f"oracle sampling + Relay-BP decode on {threads} threads, {dt:.1f} s",
             "mean_iters_per_shot": float(np.mean(r["iters"])),
-            # each shot runs on one thread: its decode time is single-core latency
             "single_core_latency_us": {"p50": float(np.percentile(r["seconds"], 50) * 1e6),
                                        "p99": float(np.percentile(r["seconds"], 99) * 1e6)},
             "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
-def cpu_model() -> str:
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
-    except OSError:
-        pass
-    return "unknown"
-
-
-def circuit_latency(seed: int, shots: int = 100, batch: int = 4000) -> dict:
-    """The paper's latency table workload: circuit-level d-round memory of
-    ZSZ-LP-320 (DEM 1920 x 28992), p = 1e-3, num_sets 1000, gamma in
-    [-0.16, 0.66]; single shots in latency mode (one XCD's CUs per shot, host
-    clock around each call) and one batched launch, X and Z memory."""
-    import numpy as np
-    import torch
-    from paper_2607_27644_amd import circuits, experiments, rbp, stats
-    gmin, gmax = experiments.CIRCUIT_GAMMA["ZSZ-LP-320"]
-    params = rbp.RelayParams(num_sets=1000, gamma_min=gmin, gamma_max=gmax)
-    res = {"code": "ZSZ-LP-320", "p": 1e-3, "relay": {"num_sets": 1000, "gamma": [gmin, gmax]}}
-    lat_all = []
-    for basis in "XZ":
-        dem = circuits.memory_dem("ZSZ-LP-320", basis, 1e-3)
-        code = rbp.Code.from_dem(dem)
-        syn, obs, _ = code.sample(dem.priors, batch, seed)
-        out = code.decode_coop(dem.priors, syn[:1], params)
-        torch.cuda.synchronize()
-        lat = []
-        for i in range(shots):
-            t0 = time.perf_counter()
-            code.decode_coop(dem.priors, syn[i:i + 1], params, out=out)
-            torch.cuda.synchronize()
-            lat.append(1e6 * (time.perf_counter() - t0))
-        if code.coop_aborted():
-            raise RuntimeError("latency-mode launch stopped on an expired barrier wait")
-        code.set_launch_config(8, 2, 0)
-        corr, obsp, st = code.decode(dem.priors, syn, params)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        code.decode(dem.priors, syn, params, out=(corr, obsp, st))
-        e1.record()
-        torch.cuda.synchronize()
-        s = rbp.stats_to_numpy(st)
-        res[f"{basis}_memory"] = {"dem": [dem.M, dem.N], "latency_mode_us": stats.percentiles(np.array(lat)),
-                                  "batched_shots_per_s": batch / (e0.elapsed_time(e1) * 1e-3),
-                                  "mean_iters": float(s["iters"].mean())}
-        lat_all += lat
-        code.close()
-    res["latency_mode_us_xz"] = stats.percentiles(np.array(lat_all))
-    res["paper_l40s_ms"] = {"mean": 1.2, "p99": 2.0, "p99.9": 3.2, "note": "NVIDIA L40S, Table 'decoding latency'"}
-    return res
+def lds_peak():
+    """Measured aggregate LDS read bandwidth (GB/s): the best of 4-, 8- and
+    16-byte reads."""
+    from paper_2607_27644_amd import rbp
+    m = {w: rbp.measure_lds_bandwidth(w) / 1e9 for w in (4, 8, 16)}
+    best = max(m, key=m.get)
+    return m[best], {f"b{8 * w}": v for w, v in m.items()}
 
 
 def main():
@@ -155,8 +132,9 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; shots shard across GPUs by "
-                                   "shot_offset with no communication, so run one process per GPU "
-                                   "(multi-GPU launch is not part of this build)", "n_gpus": args.gpus}))
+                                   "shot_offset with no communication, so one process per GPU would each "
+                                   "run it on its own shot range (multi-GPU launch is not part of this build)",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
@@ -176,6 +154,7 @@ def main():
     obsp = torch.empty_like(obs)
     st = torch.empty((S, 32), dtype=torch.uint8, device=dev)
     fail_count = torch.zeros(1, dtype=torch.int64, device=dev)
+    B_it = 8 * dem.nnz + 8 * dem.N  # algorithmic bytes of one flooding iteration of one shot
 
     if args.calib_copy_mb:
         n = args.calib_copy_mb * (1 << 20) // 4
@@ -186,11 +165,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    lds_gbs, lds_all = lds_peak()
     ev = []
-    net = None
-    delta_buf = None
+    state = {"net": None, "delta": None}
 
-    def step(i: int, record: bool, path: str = "plain"):
+    def step(i: int, record: bool, path: str, prm):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
         if record:
             e[0].record()
@@ -199,73 +178,81 @@ def main():
             e[1].record()
         delta = None
         if path == "learned":
-            delta = net.forward(syn, out=delta_buf)
+            delta = state["net"].forward(syn, out=state["delta"])
         elif path == "proposal_zero":
-            delta = delta_buf
+            delta = state["delta"]
         if record:
             e[2].record()
-        code.decode(dem.priors, syn, params, delta=delta, out=(corr, obsp, st))
+        code.decode(dem.priors, syn, prm, delta=delta, out=(corr, obsp, st))
         if record:
             e[3].record()
             ev.append(e)
         rbp.count_failures(obsp, obs, st, fail_count)
-        return None
 
-    def timed(path: str):
+    def timed(path: str, prm):
         ev.clear()
         for i in range(args.warmup):
-            step(1000 + i, False, path)
+            step(1000 + i, False, path, prm)
         torch.cuda.synchronize()
         fail_count.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(args.steps):
-            step(i, True, path)
-        fail_total = int(fail_count.item())  # synchronizes: the steps' work is inside the window
+            step(i, True, path, prm)
+        fails = int(fail_count.item())  # synchronizes: the steps' work is inside the window
         wall = time.perf_counter() - t0
         last = rbp.stats_to_numpy(st).copy()
-        ms = lambda a, b: float(np.mean([e[a].elapsed_time(e[b]) for e in ev]))
-        return {"wall": wall, "fails": fail_total, "last": last, "sample_ms": ms(0, 1), "mlp_ms": ms(1, 2),
-                "decode_ms": ms(2, 3)}
+        ms = lambda a, b: float(np.mean([x[a].elapsed_time(x[b]) for x in ev]))
+        it = last["iters"].astype(np.float64)
+        dec_ms = ms(2, 3)
+        svc = (last["t_end"] - last["t_start"]).astype(np.float64) * 0.01  # 100 MHz device clock
+        achieved = float(it.sum()) * B_it / (dec_ms * 1e-3) / 1e9
+        return {
+            "value": S * args.steps / wall, "unit": "shots/s", "ms_per_step": 1e3 * wall / args.steps,
+            "wall_s": wall, "decode_kernel_ms": dec_ms, "sample_kernel_ms": ms(0, 1), "mlp_ms": ms(1, 2),
+            "decode_only_shots_per_s": S / (dec_ms * 1e-3),
+            "ler": stats.ler_summary(fails, S * args.steps, dem.rounds, dem.k),
+            "mean_iters_per_shot": float(it.mean()), "mean_legs_per_shot": float(last["legs"].mean()),
+            "path_counts": {str(k): int((last["path"] == k).sum()) for k in range(4)},
+            "latency_us": {"batched_service_time": stats.percentiles(svc)},
+            "roofline_decode": {"bound": "lds", "achieved": achieved, "peak": lds_gbs, "unit": "GB/s",
+                                "frac": achieved / lds_gbs, "shot_iterations_per_launch": int(it.sum())},
+        }
 
-    P = timed("plain")
-    wall, fail_total, last = P["wall"], P["fails"], P["last"]
-    ms_step = 1e3 * wall / args.steps
-    value = S * args.steps / wall
-
-    dec_ms, smp_ms = P["decode_ms"], P["sample_ms"]
-    iters = last["iters"].astype(np.int64)
-    B_it = 8 * dem.nnz + 8 * dem.N  # algorithmic bytes of one flooding iteration of one shot
-    alg_bytes = float(iters.sum()) * B_it
-    achieved = alg_bytes / (dec_ms * 1e-3) / 1e9
+    P = timed("plain", params)
+    launch = code.launch_config()
+    kern = "relay_bp_compact_kernel" if launch["state"] == 3 else "relay_bp_kernel"
     traffic = load_traffic(args.workload, S)
-
-    ticks = (last["t_end"] - last["t_start"]).astype(np.float64)
-    service_us = ticks * 0.01  # 100 MHz device wall clock
-    nz = last["path"] != 3
     out = {
-        "metric": METRIC, "value": value, "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": P["value"], "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": P["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {
-            "workload": f"phenomenological DEM of ZSZ-LP-160 [[160,32,10]] over 9 rounds "
-                        f"({dem.M} detectors x {dem.N} mechanisms, nnz {dem.nnz}), priors 1e-3, "
-                        f"{S} shots per step, Relay-BP gamma0=0.125 pre_iter=80 max_iterations=60 "
-                        f"num_sets=100 stop_nconv=5 gamma_dist=[-0.24,0.66], FP32 messages",
-            "shots_per_step": S, "path": "plain Relay-BP (value); learned proposal and delta=0 control below",
+            "workload": f"12-round phenomenological DEM of the [[840,168]] ZSZ-LP code ({dem.M} detectors x "
+                        f"{dem.N} mechanisms, nnz {dem.nnz}), priors 1e-3, {S} shots per step, Relay-BP "
+                        f"gamma0=0.125 pre_iter=80 max_iterations=60 num_sets=100 stop_nconv=5 "
+                        f"gamma_dist=[-0.24,0.66], FP32 messages" if args.workload == "phen840" else
+                        f"{dem.name} ({dem.M} x {dem.N}, nnz {dem.nnz}), {S} shots per step",
+            "shots_per_step": S, "total_timed_shots": S * args.steps,
+            "path": "plain Relay-BP (value); first-solution Relay-BP, learned proposal and delta=0 control below",
         },
-        "decode_only_shots_per_s": S / (dec_ms * 1e-3),
-        "decode_kernel_ms": dec_ms, "sample_kernel_ms": smp_ms,
-        "latency_us": {"batched_service_time": stats.percentiles(service_us),
-                       "batched_service_time_nonzero_syndrome": stats.percentiles(service_us[nz])},
-        "ler": stats.ler_summary(fail_total, S * args.steps, dem.rounds, dem.k),
-        "mean_iters_per_shot": float(iters.mean()), "mean_legs_per_shot": float(last["legs"].mean()),
-        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / LDS_PEAK_GBS, "traffic": traffic,
-                     "kernel": "relay_bp_kernel", "algorithmic_bytes_per_shot_iteration": B_it,
-                     "shot_iterations_per_launch": int(iters.sum())},
-        "launch": code.launch_config(),
+        "decode_only_shots_per_s": P["decode_only_shots_per_s"],
+        "decode_kernel_ms": P["decode_kernel_ms"], "sample_kernel_ms": P["sample_kernel_ms"],
+        "latency_us": P["latency_us"], "ler": P["ler"],
+        "mean_iters_per_shot": P["mean_iters_per_shot"], "mean_legs_per_shot": P["mean_legs_per_shot"],
+        "roofline": {"bound": "lds", "achieved": P["roofline_decode"]["achieved"], "peak": lds_gbs, "unit": "GB/s",
+                     "frac": P["roofline_decode"]["frac"], "traffic": traffic, "kernel": kern,
+                     "algorithmic_bytes_per_shot_iteration": B_it,
+                     "shot_iterations_per_launch": P["roofline_decode"]["shot_iterations_per_launch"],
+                     "peak_measured_GBps": lds_all, "peak_nominal_GBps": LDS_NOMINAL_GBS,
+                     "note": "decode launch timed with HIP events on the decode stream (includes the ~20 us "
+                             "heaviest-first ordering kernels before it)"},
+        "launch": launch,
     }
+    paths = {}
+    fs = rbp.RelayParams(stop_nconv=1)
+    paths["first_solution"] = timed("plain", fs)
+    paths["first_solution"]["note"] = "Relay-BP with stop_nconv = 1: the proposal path's stop rule, no proposal"
 
     if not args.no_learned:
         from paper_2607_27644_amd import learned
@@ -279,64 +266,141 @@ def main():
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         del chunks
-        delta_buf = torch.empty((S, dem.N), dtype=torch.float32, device=dev)
-        paths = {}
-        for path in ("learned", "proposal_zero"):
-            if path == "proposal_zero":
-                delta_buf.zero_()
-            R = timed(path)
-            it = R["last"]["iters"].astype(np.float64)
-            sv = (R["last"]["t_end"] - R["last"]["t_start"]).astype(np.float64) * 0.01
-            paths[path] = {
-                "value": S * args.steps / R["wall"], "unit": "shots/s", "ms_per_step": 1e3 * R["wall"] / args.steps,
-                "mlp_ms": R["mlp_ms"], "decode_kernel_ms": R["decode_ms"],
-                "ler": stats.ler_summary(R["fails"], S * args.steps, dem.rounds, dem.k),
-                "mean_iters_per_shot": float(it.mean()),
-                "path_counts": {str(k): int((R["last"]["path"] == k).sum()) for k in range(4)},
-                "latency_us": {"batched_service_time": stats.percentiles(sv)}}
-        paths["learned"]["training"] = {"pairs": cfg.pairs, "p_range": [cfg.p_lo, cfg.p_hi], "epochs": cfg.epochs,
-                                        "batch": cfg.batch, "hidden": cfg.hidden, "params": net.n_params,
-                                        "delta_scale": cfg.delta_scale,
-                                        "generate_s": t1 - t0, "train_s": t2 - t1, "final_loss": hist[-1][1]}
-        paths["learned"]["vs_plain"] = paths["learned"]["value"] / value
+        state["net"] = net
+        state["delta"] = torch.empty((S, dem.N), dtype=torch.float32, device=dev)
+        paths["learned"] = timed("learned", params)
+        state["delta"].zero_()
+        paths["proposal_zero"] = timed("proposal_zero", params)
+        L = paths["learned"]
+        flops = 2.0 * net.n_params * S
+        L["roofline_mlp"] = {"bound": "mfma", "achieved": flops / (L["mlp_ms"] * 1e-3) / 1e12,
+                             "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": flops / (L["mlp_ms"] * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
+                             "algorithmic_flops_per_shot": 2.0 * net.n_params}
+        L["training"] = {"pairs": cfg.pairs, "p_range": [cfg.p_lo, cfg.p_hi], "epochs": cfg.epochs,
+                         "batch": cfg.batch, "hidden": cfg.hidden, "params": net.n_params,
+                         "delta_scale": cfg.delta_scale, "generate_s": t1 - t0, "train_s": t2 - t1,
+                         "final_loss": hist[-1][1]}
+        L["vs_proposal_zero"] = L["value"] / paths["proposal_zero"]["value"]
+        L["vs_first_solution"] = L["value"] / paths["first_solution"]["value"]
+        L["vs_plain"] = L["value"] / P["value"]
         paths["proposal_zero"]["note"] = "control: the same proposal leg with delta = 0 (no network)"
-        out["learned"] = paths["learned"]
-        out["proposal_zero"] = paths["proposal_zero"]
+    out.update(paths)
 
-    if not args.no_awgn:
-        # the classical benchmark beside the headline: the [310,155] ZSZ-2BGA code
-        # over BPSK-AWGN at 2.5 dB, sum-product BP (num_iter 100, llr_max 20)
-        from paper_2607_27644_amd import experiments
-        experiments.awgn_fer(["ZSZ-2BGA-310"], [2.5], max_frames=100_000, min_errors=10 ** 12, chunk=100_000)
-        r = experiments.awgn_fer(["ZSZ-2BGA-310"], [2.5], max_frames=4_000_000, min_errors=10 ** 12,
-                                 chunk=1_000_000)
-        pt = r["codes"]["ZSZ-2BGA-310"]["points"][0]
-        out["awgn"] = {"code": "ZSZ-2BGA-310 [310,155]", "ebn0_db": pt["ebn0_db"], "frames": pt["frames"],
-                       "fer": pt["fer"], "ci95": pt["ci95"], "undetected": pt["undetected"],
-                       "mean_iters": pt["mean_iters"], "decode_frames_per_s": pt["decode_frames_per_s"],
-                       "frames_per_s_with_sampling": pt["frames_per_s"],
-                       "shannon_limit_db": r["shannon_limit_db"]}
+    # logical error rates at a higher p, every path on the same syndromes
+    if args.ler_p > 0:
+        pri = np.full(dem.N, args.ler_p)
+        n = args.ler_shots
+        hsyn, hobs, _ = code.sample(pri, n, args.seed + 777)
+        res = {"p": args.ler_p, "shots": n}
+        masks = {}
+        runs = [("plain", params, None), ("first_solution", fs, None)]
+        if state["net"] is not None:
+            runs += [("learned", params, "net"), ("proposal_zero", params, "zero")]
+        for name, prm, dk in runs:
+            d = None
+            if dk == "net":
+                d = state["net"].forward(hsyn)
+            elif dk == "zero":
+                d = torch.zeros((n, dem.N), dtype=torch.float32, device=dev)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            c, o, s = code.decode(pri, hsyn, prm, delta=d)
+            e1.record()
+            torch.cuda.synchronize()
+            sn = rbp.stats_to_numpy(s)
+            f = stats.block_failures(rbp.to_u32(o), rbp.to_u32(hobs), sn["converged"])
+            masks[name] = f
+            res[name] = {"ler": stats.ler_summary(int(f.sum()), n, dem.rounds, dem.k),
+                         "decode_shots_per_s": n / (e0.elapsed_time(e1) * 1e-3),
+                         "mean_iters_per_shot": float(sn["iters"].mean()),
+                         "non_converged": int((sn["converged"] == 0).sum())}
+            del d, c, o, s
+        for name in masks:
+            if name != "plain":
+                a, b = masks["plain"], masks[name]
+                res[name]["paired_vs_plain"] = {"plain_only": int((a & ~b).sum()), "this_only": int((b & ~a).sum()),
+                                                "both": int((a & b).sum())}
+        out["ler_high_p"] = res
 
     if not args.no_sequential:
-        # the paper's latency mode: one shot per decode call, host clock around each
-        one_syn = syn[:1]
+        # the paper's sequential mode: one shot per decode call, host clock around each
         lat = []
         c1, o1, s1 = corr[:1], obsp[:1], st[:1]
-        for i in range(400):
+        for i in range(200):
             torch.cuda.synchronize()
             ta = time.perf_counter()
             code.decode(dem.priors, syn[i:i + 1], params, out=(c1, o1, s1))
             torch.cuda.synchronize()
             lat.append(1e6 * (time.perf_counter() - ta))
-        del one_syn
         out["latency_us"]["sequential_single_shot"] = stats.percentiles(np.array(lat))
 
-    if not args.no_circuit:
-        out["circuit_latency"] = circuit_latency(args.seed)
+    if not args.no_extras:
+        out["extras"] = extras(args.seed)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(dem, S, args.seed, params, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(dem, args.seed, params, args.cpu_seconds)
+    code.close()
+    if state["net"] is not None:
+        state["net"].close()
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
+
+
+def extras(seed: int) -> dict:
+    """Secondary workloads: the earlier ZSZ-LP-160 headline, the batched uneven
+    decode of four codes, the paper's latency-table workload and the classical
+    AWGN benchmark."""
+    import numpy as np
+    import torch
+
+    from paper_2607_27644_amd import circuits, experiments, rbp, stats, workloads
+    res = {}
+    # phenomenological ZSZ-LP-160 (576 x 1952), 10^5 shots per launch
+    dem = workloads.workload("phen160")
+    code = rbp.Code.from_dem(dem)
+    params = rbp.RelayParams()
+    syn, obs, _ = code.sample(dem.priors, 100000, seed)
+    ms, out = experiments._timed(lambda: code.decode(dem.priors, syn, params))
+    it = rbp.stats_to_numpy(out[2])["iters"].astype(np.float64).sum()
+    res["phen160"] = {"decode_ms": ms, "decode_shots_per_s": 1e5 / (ms * 1e-3),
+                      "algorithmic_GBps": it * (8 * dem.nnz + 8 * dem.N) / (ms * 1e-3) / 1e9,
+                      "launch": code.launch_config()}
+    code.close()
+    # batched uneven decode: 4 codes (ZSZ-LP-160/320/550/775, 9 rounds), shots interleaved
+    res["uneven_batch"] = experiments.multi(["phen160", "phen320", "phen550", "phen775"], 50000, seed=seed)
+    # the paper's latency-table workload: circuit-level ZSZ-LP-320 memory (1920 x 28992), p = 1e-3
+    gmin, gmax = experiments.CIRCUIT_GAMMA["ZSZ-LP-320"]
+    prm = rbp.RelayParams(num_sets=1000, gamma_min=gmin, gamma_max=gmax)
+    cl = {"code": "ZSZ-LP-320", "p": 1e-3, "relay": {"num_sets": 1000, "gamma": [gmin, gmax]}}
+    lat_all = []
+    for basis in "XZ":
+        d = circuits.memory_dem("ZSZ-LP-320", basis, 1e-3)
+        c = rbp.Code.from_dem(d)
+        s, _, _ = c.sample(d.priors, 4000, seed)
+        o = c.decode_coop(d.priors, s[:1], prm)
+        torch.cuda.synchronize()
+        lat = []
+        for i in range(100):
+            t0 = time.perf_counter()
+            c.decode_coop(d.priors, s[i:i + 1], prm, out=o)
+            torch.cuda.synchronize()
+            lat.append(1e6 * (time.perf_counter() - t0))
+        ms, out = experiments._timed(lambda: c.decode(d.priors, s, prm), repeats=2)
+        cl[f"{basis}_memory"] = {"dem": [d.M, d.N], "latency_mode_us": stats.percentiles(np.array(lat)),
+                                 "batched_shots_per_s": 4000 / (ms * 1e-3),
+                                 "mean_iters": float(rbp.stats_to_numpy(out[2])["iters"].mean())}
+        lat_all += lat
+        c.close()
+    cl["latency_mode_us_xz"] = stats.percentiles(np.array(lat_all))
+    cl["paper_l40s_ms"] = {"mean": 1.2, "p99": 2.0, "p99.9": 3.2, "note": "NVIDIA L40S, Table 'decoding latency'"}
+    res["circuit_latency"] = cl
+    # classical ZSZ-2BGA [310,155] code over BPSK-AWGN at 2.5 dB, sum-product BP
+    r = experiments.awgn_fer(["ZSZ-2BGA-310"], [2.5], max_frames=2_000_000, min_errors=10 ** 12, chunk=1_000_000)
+    pt = r["codes"]["ZSZ-2BGA-310"]["points"][0]
+    res["awgn"] = {"code": "ZSZ-2BGA-310 [310,155]", "ebn0_db": pt["ebn0_db"], "frames": pt["frames"],
+                   "fer": pt["fer"], "decode_frames_per_s": pt["decode_frames_per_s"]}
+    return res
 
 
 if __name__ == "__main__":

@@ -152,7 +152,12 @@ rbp_status rbp_code_llr(rbp_code_t code, const double* priors, float* llr_dev, v
 
 /* Launch shape of the persistent decoder for one handle (chosen by the
  * autotuner; 0 = library default).  waves_per_shot: wavefronts that share one
- * shot (1..16).  state: 0 auto, 1 per-shot state in LDS, 2 in device memory.
+ * shot (1..16).  state: 0 auto, 1 per-shot state in LDS (one float per edge
+ * and per variable), 2 the same state in device memory, 3 compact state in LDS
+ * (one 16-byte record per check row -- its two least |nu|, the edge attaining
+ * the least and the outgoing message signs -- and one float per variable;
+ * rows of at most 16 edges; the messages are those of the per-edge form bit
+ * for bit).  Auto takes 1 when it fits in LDS, else 3 when it fits, else 2.
  * max_slots: cap on the resident shot slots (0 = as many as fit). */
 typedef struct {
     int32_t waves_per_shot;
@@ -327,6 +332,15 @@ typedef struct {
 rbp_status rbp_decode_spa(rbp_code_t code, const float* llr_dev, uint64_t shots, const rbp_spa_params* params,
                           uint32_t* bits_dev, float* marginals_dev, rbp_shot_stats* stats_dev,
                           unsigned long long* counts_dev, void* stream);
+
+/* ---- device ceilings ---------------------------------------------------- *
+ * Aggregate LDS read bandwidth of the current device, measured: two
+ * 1024-thread workgroups per compute unit read a 64 KB LDS buffer with
+ * width_bytes (4, 8 or 16) per lane and instruction, every wave on 64
+ * consecutive cells (no bank conflicts); *bytes_per_s (host) receives the best
+ * of three timed launches.  The denominator of the decoder's LDS roofline.
+ * Synchronous; allocates and frees a small device buffer. */
+rbp_status rbp_measure_lds_bandwidth(int32_t width_bytes, double* bytes_per_s);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* rbp_last_error(void);

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librbp.so")
-SOURCES = ["rbp_decode.hip", "rbp_mlp.hip", "rbp_spa.hip", "rbp_window.hip"]
+SOURCES = ["rbp_decode.hip", "rbp_mlp.hip", "rbp_spa.hip", "rbp_window.hip", "rbp_probe.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -119,7 +119,7 @@ struct rbp_code {
     bool compact_ok = false;
     int32_t coff_M = 0;                 // LDS offset of the marginals: 16 * 64 GR + 16
     rbp::DevBuf cvar;                   // int32, layout of rposp: LDS address of each row edge's marginal
-    rbp::DevBuf vrec;                   // uint32[S]: 16 * row position + edge index in the row, per edge slot
+    rbp::DevBuf vrec;                   // uint32[S]: 16 * row position + edge code in the row, per edge slot
     rbp::DevBuf r1rec;                  // uint4[64 GR]: first-iteration records of a plain leg (per priors)
     rbp::LaunchCfg cfg;
 };

@@ -338,7 +338,7 @@ struct DecodeModel {
     const int32_t* orow_idx;
     // compact state (rows of at most 16 edges; null otherwise)
     const int32_t* cvar;      // layout of rposp: LDS byte address of the marginal of each edge's variable
-    const uint32_t* vrec;     // [S] 16 * (row position) + (edge index in the row) of each edge slot
+    const uint32_t* vrec;     // [S] 16 * (row position) + (edge code in the row) of each edge slot
     const uint4* r1rec;       // [64 GR] first-iteration row records of a plain leg
     int32_t coff_M;           // LDS offset of the marginals in the compact layout (16 * 64 GR + 16)
     const uint32_t* syn;
@@ -1127,12 +1127,15 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
 // of the extrinsic step on the same FP32 operands -- so every message and
 // marginal equals the per-edge form's bit for bit.
 //
-// Record of the row at position rp (LDS byte address 16 rp):
+// Edge p of a row stored with D slots has the code c = D - 1 - p (the order in
+// which one funnel shift per edge collects the signs).  Record of the row at
+// position rp (LDS byte address 16 rp):
 //   .x m1   least |nu| of the row (float bits, sign clear)
 //   .y m2   second least (equal to m1 on a tie)
-//   .z sg   bit p (p < 16): sign bit of mu_{i->j_p}; bits 16..31 repeat 0..15
-//   .w ax   16 rp + p*, p* an edge attaining m1
-// Per edge slot the variable sweep holds x = 16 rp + p (vrec): the record is
+//   .z sg   bit c (c < 16): sign bit of mu_{i->j} for the edge of code c;
+//           bits 16..31 repeat 0..15
+//   .w ax   16 rp + c*, c* the code of an edge attaining m1
+// Per edge slot the variable sweep holds x = 16 rp + c (vrec): the record is
 // at x & ~15, the message sign is bit (x mod 32) of sg (the repeat makes the
 // low bit of rp that falls into x mod 32 harmless) and the magnitude is m2 iff
 // x == ax.  The marginals follow the records at LDS offset coff_M =
@@ -1163,10 +1166,10 @@ __device__ __forceinline__ float rec_mu(uint4 r, uint32_t x) {
 }
 
 // One row of the compact check update with D stored edges (entries of the
-// lane's cvar block, 16-byte loads).  first: nu = M, the first iteration of a
+// lane's cvar block, 16-byte loads).  FIRST: nu = M, the first iteration of a
 // proposal leg (its nu(0) equals its M(0)); otherwise nu = M - mu(old record).
-template <int D>
-__device__ __forceinline__ void compact_row(const int32_t* cp, uint32_t rpx, uint32_t sigma, bool first) {
+template <int D, bool FIRST>
+__device__ __forceinline__ void compact_row(const int32_t* cp, uint32_t rpx, uint32_t sigma) {
     constexpr int Q = (D + 3) / 4;
     uint32_t pos[4 * Q];
 #pragma unroll
@@ -1177,39 +1180,41 @@ __device__ __forceinline__ void compact_row(const int32_t* cp, uint32_t rpx, uin
         pos[4 * k + 2] = (uint32_t)v.z;
         pos[4 * k + 3] = (uint32_t)v.w;
     }
-    const uint4 old = lds_rec(rpx);
+    uint4 old = make_uint4(0u, 0u, 0u, 0u);
+    if (!FIRST) old = lds_rec(rpx);
     const uint32_t pa = old.w - rpx;
     uint32_t m1 = 0x7f800000u, m2 = 0x7f800000u, nb = 0u, am = 0u;
 #pragma unroll
     for (int p = 0; p < D; ++p) {
+        const int c = D - 1 - p;  // the edge's code
         const float M = lds_f(pos[p]);
         uint32_t nu;
-        if (first) {
+        if (FIRST) {
             nu = __float_as_uint(M);
         } else {
-            const uint32_t mag = pa == (uint32_t)p ? old.y : old.x;
-            const float mu = __uint_as_float(mag | ((old.z << (31 - p)) & 0x80000000u));
+            const uint32_t mag = pa == (uint32_t)c ? old.y : old.x;
+            const float mu = __uint_as_float(mag | ((old.z << (31 - c)) & 0x80000000u));
             nu = __float_as_uint(M - mu);
         }
         const uint32_t av = nu & 0x7fffffffu;
-        nb |= (nu >> 31) << p;
+        nb = __builtin_amdgcn_alignbit(nb, nu, 31);  // (nb << 1) | sign: edge p lands on bit c
         m2 = umed3(m1, m2, av);
         const bool lt = av < m1;
         m1 = lt ? av : m1;
-        am = lt ? (uint32_t)p : am;
+        am = lt ? (uint32_t)c : am;
     }
-    // sign of mu_p = sigma xor (parity of all signs) xor sign(nu_p)
+    // sign of mu = sigma xor (parity of all signs) xor sign(nu)
     const uint32_t flip = 0u - ((((uint32_t)__popc(nb)) ^ sigma) & 1u);
     const uint32_t sg = (nb ^ flip) & 0xFFFFu;
     lds_rec_st(rpx, make_uint4(m1, m2, sg | (sg << 16), rpx + am));
 }
 
 // stored row degrees of the compact form: 2..12 exactly, 13..16 padded to 16
-__device__ __forceinline__ void compact_row_dispatch(int dg, const int32_t* cp, uint32_t rpx, uint32_t sigma,
-                                                     bool first) {
+template <bool FIRST>
+__device__ __forceinline__ void compact_row_dispatch(int dg, const int32_t* cp, uint32_t rpx, uint32_t sigma) {
     switch (dg) {
 #define RBP_CROW(D) \
-    case D: compact_row<D>(cp, rpx, sigma, first); break;
+    case D: compact_row<D, FIRST>(cp, rpx, sigma); break;
         RBP_CROW(2) RBP_CROW(3) RBP_CROW(4) RBP_CROW(5) RBP_CROW(6) RBP_CROW(7)
         RBP_CROW(8) RBP_CROW(9) RBP_CROW(10) RBP_CROW(11) RBP_CROW(12) RBP_CROW(16)
 #undef RBP_CROW
@@ -1402,7 +1407,10 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
                             } else {
                                 const int4 gi = m.rgrp[g];
                                 const uint32_t off = (uint32_t)uniform(gi.x) + (uint32_t)lane * (uint32_t)uniform(gi.w);
-                                compact_row_dispatch(uniform(gi.y), m.cvar + off, 16u * rp, sigma, t == 1);
+                                if (t == 1)
+                                    compact_row_dispatch<true>(uniform(gi.y), m.cvar + off, 16u * rp, sigma);
+                                else
+                                    compact_row_dispatch<false>(uniform(gi.y), m.cvar + off, 16u * rp, sigma);
                             }
                         }
                         __syncthreads();
@@ -1539,10 +1547,11 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
 // position, the two least Lambda of the row and the edge of the least; sg = 0
 // (the kernel inserts sigma); padding positions get +inf magnitudes.
 __global__ void first_record_kernel(const int32_t* row_ptr, const int32_t* col_idx, const int32_t* rord,
-                                    const float* lam, uint4* r1rec, int32_t npos) {
+                                    const int4* rgrp, const float* lam, uint4* r1rec, int32_t npos) {
     const int pos = blockIdx.x * blockDim.x + threadIdx.x;
     if (pos >= npos) return;
     const int i = rord[pos];
+    const int D = rgrp[pos >> 6].y;  // stored degree: edge p has the code D - 1 - p
     uint32_t m1 = 0x7f800000u, m2 = 0x7f800000u, am = 0u;
     if (i >= 0) {
         const int rs = row_ptr[i], re = row_ptr[i + 1];
@@ -1551,7 +1560,7 @@ __global__ void first_record_kernel(const int32_t* row_ptr, const int32_t* col_i
             m2 = umed3(m1, m2, av);
             if (av < m1) {
                 m1 = av;
-                am = (uint32_t)(e - rs);
+                am = (uint32_t)(D - 1 - (e - rs));
             }
         }
     }
@@ -1962,7 +1971,7 @@ static rbp_status ensure_llr(rbp_code* c, const double* priors, hipStream_t stre
         if (st) return st;
         hipLaunchKernelGGL(first_record_kernel, dim3(ceil_div(npos, 256)), dim3(256), 0, stream,
                            c->row_ptr.as<int32_t>(), c->col_idx.as<int32_t>(), c->rord.as<int32_t>(),
-                           c->lam.as<float>(), c->r1rec.as<uint4>(), npos);
+                           c->rgrp.as<int4>(), c->lam.as<float>(), c->r1rec.as<uint4>(), npos);
         RBP_HIP_CHECK(hipGetLastError());
     }
     c->lam_key.assign(priors, priors + c->N);
@@ -2464,7 +2473,7 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
         rposw(std::max<int64_t>(RB, 1), (int32_t)(4 * (S + 1))), rfill(M, 0);
     // compact state (rows of at most 16 edges): LDS address of each row edge's
     // marginal (records first, then the +inf cell, then the marginals), and
-    // 16 * row position + edge index for each edge slot
+    // 16 * row position + edge code (stored degree - 1 - index) for each edge slot
     const bool compact_ok = maxstored <= 16;
     const int64_t crec = 16 * 64 * (int64_t)GR;
     const int32_t coff_M = (int32_t)(crec + 16);
@@ -2479,7 +2488,7 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
             rposw[at] = 4 * slot_of[e];
             if (compact_ok) {
                 cvar[at] = coff_M + 4 * vinv[j];
-                vrec[slot_of[e]] = 16u * (uint32_t)pos + (uint32_t)p;
+                vrec[slot_of[e]] = 16u * (uint32_t)pos + (uint32_t)(rgrp[4 * (pos >> 6) + 1] - 1 - p);
             }
         }
     if (compact_ok && (int64_t)coff_M + 4 * (int64_t)Np > (int64_t)INT32_MAX)

@@ -146,6 +146,8 @@ def lib():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = ctypes.c_int32
+    L.rbp_measure_lds_bandwidth.argtypes = [i32, ctypes.POINTER(ctypes.c_double)]
+    L.rbp_measure_lds_bandwidth.restype = ctypes.c_int32
     L.rbp_last_error.argtypes = []
     L.rbp_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -399,6 +401,13 @@ def window_commit(code: "Code", win_corr: torch.Tensor, cmap: torch.Tensor, n_wi
     check(lib().rbp_window_commit(code.h, shots, _ptr(win_corr), win_corr.shape[1], _ptr(cmap), n_win,
                                   _ptr(syndromes), _ptr(obs_pred), _ptr(corrections), _ptr(win_stats),
                                   _ptr(acc_stats), 1 if first else 0, _stream(stream)))
+
+
+def measure_lds_bandwidth(width_bytes: int = 16) -> float:
+    """Aggregate LDS read bandwidth of the current GPU in bytes/s (rbp_measure_lds_bandwidth)."""
+    v = ctypes.c_double()
+    check(lib().rbp_measure_lds_bandwidth(width_bytes, ctypes.byref(v)))
+    return v.value
 
 
 def stats_to_numpy(st: torch.Tensor) -> np.ndarray:
