@@ -44,6 +44,7 @@ typedef int32_t rbp_status;
 #define RBP_ERR_UNSUPPORTED (-3) /* row degree outside [2, 1024] (0 allowed), p outside (0, 0.5] */
 #define RBP_ERR_OOM (-4)         /* device or host allocation failed */
 #define RBP_ERR_HIP (-5)         /* HIP runtime error (message in rbp_last_error) */
+#define RBP_ERR_ABORTED (-6)     /* a latency-mode launch stopped on an expired barrier wait */
 
 typedef struct rbp_code* rbp_code_t;
 
@@ -179,14 +180,15 @@ rbp_status rbp_get_launch_config(rbp_code_t code, rbp_launch_config* cfg, int32_
  * (0: 8 while workgroups * 8 <= CUs, which keeps them on one XCD, else 1).
  * waves: wavefronts per workgroup, 1..8 (0: 8).  spin_limit: bound on the polls of
  * one barrier wait (0: 2^21, about 2 s); when a wait expires the launch stops
- * at the next barrier, leaving later shots unwritten, and rbp_coop_aborted
- * reports it.  phantom (tests of that path only, else 0): the barriers wait
- * for this many extra workgroups that never arrive, so every wait expires.
+ * at the next barrier, leaving later shots unwritten.
  * When all participants run on one XCD (checked at the start of each launch
  * from the hardware XCD id) the barriers only wait for stores and invalidate
  * the L1, since the participants share one L2; otherwise, or with
  * device_fences = 1, they use device-scope fences (L2 write-back and
  * invalidation).
+ * The call returns when the launch has ended (it synchronizes the stream, as
+ * a latency measurement needs): RBP_ERR_ABORTED if a barrier wait expired
+ * (the outputs of the shots not reached are not written), else RBP_OK.
  * Uses per-handle scratch (one shot's state, bit arrays and barrier words).
  * Returns UNSUPPORTED when the workgroups cannot all be resident (cooperative
  * launch). */
@@ -195,14 +197,14 @@ typedef struct {
     int32_t stride;
     int32_t waves;
     uint32_t spin_limit;
-    int32_t phantom;
     int32_t device_fences;
 } rbp_coop_params;
 rbp_status rbp_decode_coop(rbp_code_t code, const double* priors, const uint32_t* syndromes_dev, uint64_t shots,
                            const rbp_relay_params* params, const rbp_coop_params* coop, uint32_t* corrections_dev,
                            uint32_t* obs_pred_dev, rbp_shot_stats* stats_dev, void* stream);
 /* 1 in *aborted if the last rbp_decode_coop launch on this handle stopped on an
- * expired barrier wait, else 0.  Synchronizes the stream. */
+ * expired barrier wait, else 0 (the same fact rbp_decode_coop returns as
+ * RBP_ERR_ABORTED).  Synchronizes the stream. */
 rbp_status rbp_coop_aborted(rbp_code_t code, void* stream, int32_t* aborted);
 
 /* Debug trace of one shot: the marginals M (float[N]) and check-to-variable
@@ -245,6 +247,17 @@ rbp_status rbp_mlp_gradients(rbp_mlp_t mlp, const uint32_t* syndromes_dev, const
 rbp_status rbp_mlp_num_params(rbp_mlp_t mlp, int64_t* n);
 rbp_status rbp_mlp_get_params(rbp_mlp_t mlp, float* host_out);
 rbp_status rbp_mlp_set_params(rbp_mlp_t mlp, const float* host_in);
+/* Checkpoint of the training state, for an exact resume: save writes to the
+ * file at `path` the dimensions, the Adam step count, the FP32 master weights
+ * and both Adam moment vectors (layout of rbp_mlp_get_params); load reads such
+ * a file into a handle of the same dimensions (SHAPE otherwise; INVALID_ARG
+ * for a file that is not a checkpoint) and refreshes the BF16 copies, so that
+ * training continued after a load takes exactly the steps it would have
+ * taken without the save.  File format (little-endian): "RBPMLP01", int32 in,
+ * hidden, out, 0, int64 number of parameters, int64 step, then float32
+ * masters, first moments, second moments.  Both synchronize the device. */
+rbp_status rbp_mlp_save(rbp_mlp_t mlp, const char* path);
+rbp_status rbp_mlp_load(rbp_mlp_t mlp, const char* path);
 
 /* ---- sliding-window decoding --------------------------------------------- *
  * The paper's latency discussion (Sec. 6.1) argues for sliding-window decoding

@@ -81,6 +81,7 @@ struct rbp_code {
     // wave-group layout of the decoder (64 rows or variables per group)
     int32_t S = 0;                      // edge slots (>= E)
     int32_t GR = 0, GV = 0, Np = 0;     // row groups, variable groups, 64 GV
+    int32_t GRw = 0;                    // leading row groups stored with more than 32 edges
     int32_t RB = 0;                     // length of the row position table
     int32_t max_stored_row_deg = 0;     // largest stored row degree (<= 12, 16, 24, 32, then multiples of 8)
     std::vector<int32_t> h_vord;        // host copy of vord
@@ -121,5 +122,6 @@ struct rbp_code {
     rbp::DevBuf cvar;                   // int32, layout of rposp: LDS address of each row edge's marginal
     rbp::DevBuf vrec;                   // uint32[S]: 16 * row position + edge code in the row, per edge slot
     rbp::DevBuf r1rec;                  // uint4[64 GR]: first-iteration records of a plain leg (per priors)
+    int32_t coop_phantom = 0;           // test hook: extra barrier arrivals that never come
     rbp::LaunchCfg cfg;
 };

@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "rbp_common.h"
+#include "../../include/rbp_test.h"
 
 namespace rbp {
 
@@ -321,6 +322,7 @@ struct DecodeModel {
     int32_t M, N, E, k, WM, WN, WK;
     int32_t S;             // edge slots; X[S] = +inf (read-only padding cell), X[S+1] write-only cell
     int32_t GR, GV, Np;    // row groups, variable groups, Np = 64 GV variable positions
+    int32_t GRw;           // leading row groups stored with more than 32 edges (rows sorted by degree)
     const int4* rgrp;      // [GR] {offset in rposp, stored degree, mixed, lane stride}
     const int32_t* rposp;  // byte offsets 4 x slot of the edges of each row (lane-major per group), 4 S padding
     const int32_t* rposw;  // the same for writes, 4 (S + 1) for padding
@@ -831,8 +833,9 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
         if (s >= a.shots) break;
         const uint64_t t_start = wall_clock64();
         const int mi = a.shot_code ? uniform((int)a.shot_code[s]) : 0;
-        const DecodeModel m = a.m[mi];
-        const uint64_t row = a.shot_index ? (uint64_t)uniform((int)a.shot_index[s]) : (uint64_t)s;
+        const DecodeModel m = a.m[mi < a.n_models ? mi : 0];  // the host checks shot codes; never read past
+        const uint64_t row =
+            a.shot_index ? (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(a.shot_index[s]) : (uint64_t)s;
         const int N = m.N, WM = m.WM, WN = m.WN;
         const float* dlt = a.delta ? a.delta + row * (uint64_t)N : nullptr;
         if (tid == 0) X.st(4u * (uint32_t)m.S, INFINITY);  // read-only padding cell
@@ -928,8 +931,13 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                             if constexpr (kQuarterRows<RD, LDS_STATE, MINW>) {
                                 // device-memory state, 128-VGPR build: rows over 32 edges in
                                 // quarters of 16 rows, four lanes per row (one gather pass)
-                                for (int u = wid; u < kPersLpr * m.GR; u += nw) {
-                                    const int g = u / kPersLpr, qq = u % kPersLpr;
+                                // units: the kPersLpr parts of each wide group (they come
+                                // first), then every narrower group whole
+                                const int wide_units = kPersLpr * m.GRw;
+                                for (int u = wid; u < wide_units + m.GR - m.GRw; u += nw) {
+                                    const bool wide = u < wide_units;
+                                    const int g = wide ? u / kPersLpr : m.GRw + (u - wide_units);
+                                    const int qq = wide ? u % kPersLpr : 0;
                                     const int4 gi = m.rgrp[g];
                                     const int dg = uniform(gi.y);
                                     const uint32_t off = (uint32_t)uniform(gi.x);
@@ -944,7 +952,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                                             check_quarter<false, LDS_STATE, false, 104 / kPersLpr, kPersLpr>(X, m.rposp + off, m.rposw + off,
                                                                             m.m1pp + off, lane, qq, dg, sbit,
                                                                             first_plain);
-                                    } else if (qq == 0) {
+                                    } else {
                                         const uint32_t sbit = ((sigp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u)
                                                               << 31;
                                         check_dispatch<RD>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane, dg,
@@ -1779,8 +1787,11 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
                     if (!(first_plain && x_mu1)) {
                         // units: 1/kCoopLpr of a group of rows over 32 edges (kCoopLpr
                         // lanes per row), else a whole group
-                        for (int u = gw; u < kCoopLpr * m.GR; u += GW) {
-                            const int g = u / kCoopLpr, qq = u % kCoopLpr;
+                        const int wide_units = kCoopLpr * m.GRw;
+                        for (int u = gw; u < wide_units + m.GR - m.GRw; u += GW) {
+                            const bool wide = u < wide_units;
+                            const int g = wide ? u / kCoopLpr : m.GRw + (u - wide_units);
+                            const int qq = wide ? u % kCoopLpr : 0;
                             const int4 gi = m.rgrp[g];
                             const int dg = uniform(gi.y);
                             const uint32_t off = (uint32_t)uniform(gi.x);
@@ -1793,7 +1804,7 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
                                 else
                                     check_quarter<false, false, true, 128 / kCoopLpr, kCoopLpr>(
                                         X, m.rposp + off, m.rposw + off, m.m1pp + off, lane, qq, dg, sbit, first_plain);
-                            } else if (qq == 0) {
+                            } else {
                                 const uint32_t sbit = ((sigp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u) << 31;
                                 check_dispatch<RD>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane, dg,
                                                    uniform(gi.z) != 0, sbit, first_plain);
@@ -2079,6 +2090,7 @@ static DecodeModel model_of(const rbp_code* c, const uint32_t* syn, uint32_t* co
     m.WK = ceil_div(c->k, 32);
     m.S = c->S;
     m.GR = c->GR;
+    m.GRw = c->GRw;
     m.GV = c->GV;
     m.Np = c->Np;
     m.rgrp = c->rgrp.as<int4>();
@@ -2518,6 +2530,8 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
     c->Np = Np;
     c->RB = (int32_t)RB;
     c->max_stored_row_deg = maxstored;
+    c->GRw = 0;
+    while (c->GRw < GR && rgrp[4 * c->GRw + 1] > 32) ++c->GRw;
     c->compact_ok = compact_ok;
     c->coff_M = coff_M;
     c->h_vord = vord;
@@ -2678,10 +2692,10 @@ rbp_status rbp_decode_coop(rbp_code_t c, const double* priors, const uint32_t* s
     if (c->k > 0 && !obs_pred) return fail(RBP_ERR_INVALID_ARG, "obs_pred is NULL");
     st = check_priors(priors, c->N);
     if (st) return st;
-    rbp_coop_params cp = {0, 0, 0, 0u, 0, 0};
+    rbp_coop_params cp = {0, 0, 0, 0u, 0};
     if (coop) cp = *coop;
-    if (cp.workgroups < 0 || cp.stride < 0 || cp.waves < 0 || cp.waves > 8 || cp.phantom < 0 || cp.phantom > 1024)
-        return fail(RBP_ERR_INVALID_ARG, "coop: workgroups, stride >= 0, waves in 0..8, phantom in 0..1024");
+    if (cp.workgroups < 0 || cp.stride < 0 || cp.waves < 0 || cp.waves > 8)
+        return fail(RBP_ERR_INVALID_ARG, "coop: workgroups, stride >= 0, waves in 0..8");
     if (shots == 0) return RBP_OK;
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
     st = ensure_llr(c, priors, stream);
@@ -2702,7 +2716,7 @@ rbp_status rbp_decode_coop(rbp_code_t c, const double* priors, const uint32_t* s
     a.Smax = c->S;
     a.nwg = nwg;
     a.stride = stride;
-    a.arrivals = (unsigned)(nwg + cp.phantom);
+    a.arrivals = (unsigned)(nwg + c->coop_phantom);
     a.force_device = cp.device_fences != 0;
     a.spin_limit = cp.spin_limit > 0 ? cp.spin_limit : (1u << 21);
     a.T0 = params->pre_iter;
@@ -2754,6 +2768,18 @@ rbp_status rbp_decode_coop(rbp_code_t c, const double* priors, const uint32_t* s
     void* args[] = {&a};
     RBP_HIP_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3((unsigned)grid),
                                              dim3(64 * waves), args, (unsigned)lds, stream));
+    // the launch's end: an expired barrier wait is reported as ABORTED
+    unsigned int aborted = 0;
+    RBP_HIP_CHECK(hipMemcpyAsync(&aborted, &a.sh->abort, sizeof(aborted), hipMemcpyDeviceToHost, stream));
+    RBP_HIP_CHECK(hipStreamSynchronize(stream));
+    if (aborted) return fail(RBP_ERR_ABORTED, "latency mode: a barrier wait expired; later shots were not decoded");
+    return RBP_OK;
+}
+
+rbp_status rbp_test_set_coop_phantom(rbp_code_t c, int32_t phantom) {
+    if (!c) return fail(RBP_ERR_INVALID_ARG, "code is NULL");
+    if (phantom < 0 || phantom > 1024) return fail(RBP_ERR_INVALID_ARG, "phantom must be 0..1024");
+    c->coop_phantom = phantom;
     return RBP_OK;
 }
 

@@ -20,6 +20,7 @@
 // mask of the backward pass and the BF16/FP32 stores.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -676,6 +677,61 @@ rbp_status rbp_mlp_get_params(rbp_mlp_t p, float* host_out) {
     if (!p || !host_out) return fail(RBP_ERR_INVALID_ARG, "NULL argument");
     RBP_HIP_CHECK(hipDeviceSynchronize());
     RBP_HIP_CHECK(hipMemcpy(host_out, p->w.p, sizeof(float) * p->n_params, hipMemcpyDeviceToHost));
+    return RBP_OK;
+}
+
+static const char kMlpMagic[8] = {'R', 'B', 'P', 'M', 'L', 'P', '0', '1'};
+
+rbp_status rbp_mlp_save(rbp_mlp_t p, const char* path) {
+    if (!p || !path) return fail(RBP_ERR_INVALID_ARG, "NULL argument");
+    RBP_HIP_CHECK(hipDeviceSynchronize());
+    const size_t n = (size_t)p->n_params;
+    std::vector<float> buf(3 * n);
+    RBP_HIP_CHECK(hipMemcpy(buf.data(), p->w.p, sizeof(float) * n, hipMemcpyDeviceToHost));
+    RBP_HIP_CHECK(hipMemcpy(buf.data() + n, p->m.p, sizeof(float) * n, hipMemcpyDeviceToHost));
+    RBP_HIP_CHECK(hipMemcpy(buf.data() + 2 * n, p->v.p, sizeof(float) * n, hipMemcpyDeviceToHost));
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(RBP_ERR_INVALID_ARG, std::string("cannot open for writing: ") + path);
+    const int32_t dims[4] = {p->in, p->hid, p->out, 0};
+    const int64_t counts[2] = {p->n_params, p->step};
+    bool ok = std::fwrite(kMlpMagic, 1, 8, f) == 8 && std::fwrite(dims, sizeof(int32_t), 4, f) == 4 &&
+              std::fwrite(counts, sizeof(int64_t), 2, f) == 2 &&
+              std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(RBP_ERR_INVALID_ARG, std::string("write failed: ") + path);
+    return RBP_OK;
+}
+
+rbp_status rbp_mlp_load(rbp_mlp_t p, const char* path) {
+    if (!p || !path) return fail(RBP_ERR_INVALID_ARG, "NULL argument");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(RBP_ERR_INVALID_ARG, std::string("cannot open: ") + path);
+    char magic[8];
+    int32_t dims[4];
+    int64_t counts[2];
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMlpMagic, 8) == 0 &&
+              std::fread(dims, sizeof(int32_t), 4, f) == 4 && std::fread(counts, sizeof(int64_t), 2, f) == 2;
+    if (!ok) {
+        std::fclose(f);
+        return fail(RBP_ERR_INVALID_ARG, std::string("not a network checkpoint: ") + path);
+    }
+    if (dims[0] != p->in || dims[1] != p->hid || dims[2] != p->out || counts[0] != p->n_params) {
+        std::fclose(f);
+        return fail(RBP_ERR_SHAPE, "checkpoint dimensions differ from the handle's");
+    }
+    const size_t n = (size_t)p->n_params;
+    std::vector<float> buf(3 * n);
+    ok = std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    std::fclose(f);
+    if (!ok || counts[1] < 0) return fail(RBP_ERR_INVALID_ARG, std::string("truncated checkpoint: ") + path);
+    RBP_HIP_CHECK(hipDeviceSynchronize());
+    RBP_HIP_CHECK(hipMemcpy(p->w.p, buf.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+    RBP_HIP_CHECK(hipMemcpy(p->m.p, buf.data() + n, sizeof(float) * n, hipMemcpyHostToDevice));
+    RBP_HIP_CHECK(hipMemcpy(p->v.p, buf.data() + 2 * n, sizeof(float) * n, hipMemcpyHostToDevice));
+    p->step = counts[1];
+    rbp_status st = refresh_bf16(p, nullptr);
+    if (st) return st;
+    RBP_HIP_CHECK(hipDeviceSynchronize());
     return RBP_OK;
 }
 

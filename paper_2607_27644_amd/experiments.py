@@ -509,6 +509,9 @@ def main():
                       params=rbp.RelayParams(gamma_min=gmin, gamma_max=gmax, num_sets=a.num_sets_grid))
     else:
         raise SystemExit(__doc__)
+    # every handle closed and the device idle before the interpreter exits
+    rbp._close_all()
+    torch.cuda.synchronize()
     print(json.dumps(r, default=float), flush=True)
 
 

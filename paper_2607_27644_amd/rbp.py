@@ -7,9 +7,11 @@ If librbp.so is missing this module raises: there is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import dataclasses
 import os
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -19,7 +21,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librbp.so")
 
 RBP_OK = 0
-_ERRNAMES = {-1: "INVALID_ARG", -2: "SHAPE", -3: "UNSUPPORTED", -4: "OOM", -5: "HIP"}
+RBP_ERR_ABORTED = -6
+_ERRNAMES = {-1: "INVALID_ARG", -2: "SHAPE", -3: "UNSUPPORTED", -4: "OOM", -5: "HIP", -6: "ABORTED"}
 
 
 class RbpError(RuntimeError):
@@ -83,7 +86,7 @@ class RelayParams:
 
 class CoopParamsC(ctypes.Structure):
     _fields_ = [("workgroups", ctypes.c_int32), ("stride", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("spin_limit", ctypes.c_uint32), ("phantom", ctypes.c_int32), ("device_fences", ctypes.c_int32)]
+                ("spin_limit", ctypes.c_uint32), ("device_fences", ctypes.c_int32)]
 
 
 @dataclasses.dataclass
@@ -93,15 +96,30 @@ class CoopParams:
     stride: int = 0
     waves: int = 0
     spin_limit: int = 0
-    phantom: int = 0  # tests of the barrier-expiry path only
     device_fences: int = 0  # device-scope fences even when the participants share one XCD
 
     def c(self) -> CoopParamsC:
-        return CoopParamsC(self.workgroups, self.stride, self.waves, self.spin_limit, self.phantom,
-                           self.device_fences)
+        return CoopParamsC(self.workgroups, self.stride, self.waves, self.spin_limit, self.device_fences)
 
 
 _lib = None
+# Handles not yet closed.  They are closed by an exit hook that runs before the
+# interpreter tears down its modules (exit hooks run last-registered first, and
+# this module is imported after torch), so no HIP call is left to a finalizer
+# that might run after the HIP runtime has shut down.
+_live = weakref.WeakSet()
+_finalized = False
+
+
+@atexit.register
+def _close_all():
+    global _finalized
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
+    _finalized = True
 
 
 def lib():
@@ -141,6 +159,9 @@ def lib():
         "rbp_bits_gather": [vp, i32, u64, vp, i32, vp, i32, vp],
         "rbp_window_residual": [vp, i32, u64, vp, vp],
         "rbp_coop_aborted": [vp, vp, P(i32)],
+        "rbp_mlp_save": [vp, ctypes.c_char_p],
+        "rbp_mlp_load": [vp, ctypes.c_char_p],
+        "rbp_test_set_coop_phantom": [vp, i32],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -177,6 +198,26 @@ def words(nbits: int) -> int:
     return (nbits + 31) // 32
 
 
+def _need(t, name: str, dtype, shape=None, optional: bool = False):
+    """Raise unless t is a contiguous CUDA tensor of this dtype (and shape):
+    the library takes device pointers, so a host tensor or a wrong layout
+    must never reach it."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+
+
 def csc_of(A: np.ndarray):
     A = np.asarray(A, dtype=np.uint8)
     rows, cols = np.nonzero(A.T)
@@ -198,6 +239,7 @@ class Code:
         check(lib().rbp_code_create(self.M, self.N, cp.ctypes.data, ri.ctypes.data, self.k, ocp.ctypes.data,
                                     ori.ctypes.data, ctypes.byref(h)))
         self.h = h
+        _live.add(self)
 
     @classmethod
     def from_dem(cls, dem) -> "Code":
@@ -205,7 +247,8 @@ class Code:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().rbp_code_destroy(self.h)
+            if not _finalized:
+                lib().rbp_code_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -229,27 +272,42 @@ class Code:
             err = torch.empty((shots, words(self.N)), dtype=torch.int32, device=dev) if errors else None
         else:
             syn, obs, err = out
-        pr = _f64(priors)
+            _need(syn, "syndromes", torch.int32, (shots, words(self.M)))
+            _need(obs, "obs", torch.int32, (shots, max(words(self.k), 1)))
+            _need(err, "errors", torch.int32, (shots, words(self.N)), optional=True)
+        pr = self._priors(priors)
         check(lib().rbp_sample(self.h, pr.ctypes.data, shots, seed, shot_offset, _ptr(syn), _ptr(obs), _ptr(err),
                                _stream(stream)))
         return syn, obs, err
 
     # -- decoding ---------------------------------------------------------
-    def decode(self, priors, syndromes: torch.Tensor, params: RelayParams, delta: Optional[torch.Tensor] = None,
-               stats: bool = True, stream=None, out=None):
-        shots = syndromes.shape[0]
-        assert syndromes.dtype == torch.int32 and syndromes.is_contiguous()
-        assert syndromes.shape[1] == words(self.M)
-        if delta is not None:
-            assert delta.dtype == torch.float32 and delta.shape == (shots, self.N) and delta.is_contiguous()
-        dev = syndromes.device
+    def _priors(self, priors) -> np.ndarray:
+        pr = _f64(priors)
+        if pr.shape != (self.N,):
+            raise ValueError(f"priors must have shape ({self.N},) (got {pr.shape})")
+        return pr
+
+    def _outputs(self, shots: int, dev, stats: bool, out):
         if out is None:
             corr = torch.empty((shots, words(self.N)), dtype=torch.int32, device=dev)
             obsp = torch.empty((shots, max(words(self.k), 1)), dtype=torch.int32, device=dev)
             st = torch.empty((shots, 32), dtype=torch.uint8, device=dev) if stats else None
         else:
             corr, obsp, st = out
-        pr = _f64(priors)
+            _need(corr, "corrections", torch.int32, (shots, words(self.N)))
+            _need(obsp, "obs_pred", torch.int32, (shots, max(words(self.k), 1)))
+            _need(st, "stats", torch.uint8, (shots, 32), optional=True)
+        return corr, obsp, st
+
+    def decode(self, priors, syndromes: torch.Tensor, params: RelayParams, delta: Optional[torch.Tensor] = None,
+               stats: bool = True, stream=None, out=None):
+        _need(syndromes, "syndromes", torch.int32)
+        shots = syndromes.shape[0]
+        _need(syndromes, "syndromes", torch.int32, (shots, words(self.M)))
+        _need(delta, "delta", torch.float32, (shots, self.N), optional=True)
+        dev = syndromes.device
+        corr, obsp, st = self._outputs(shots, dev, stats, out)
+        pr = self._priors(priors)
         prm = params.c()
         check(lib().rbp_decode(self.h, pr.ctypes.data, _ptr(syndromes), shots, ctypes.byref(prm), _ptr(delta),
                                _ptr(corr), _ptr(obsp), _ptr(st), _stream(stream)))
@@ -257,23 +315,25 @@ class Code:
 
     def decode_coop(self, priors, syndromes: torch.Tensor, params: RelayParams, coop: Optional[CoopParams] = None,
                     stats: bool = True, stream=None, out=None):
-        """Latency mode: shots one after another, each by several workgroups."""
+        """Latency mode: shots one after another, each by several workgroups.
+        Returns when the shots are decoded; raises RbpError (status ABORTED)
+        if a barrier wait expired."""
+        _need(syndromes, "syndromes", torch.int32)
         shots = syndromes.shape[0]
-        assert syndromes.dtype == torch.int32 and syndromes.is_contiguous()
-        assert syndromes.shape[1] == words(self.M)
+        _need(syndromes, "syndromes", torch.int32, (shots, words(self.M)))
         dev = syndromes.device
-        if out is None:
-            corr = torch.empty((shots, words(self.N)), dtype=torch.int32, device=dev)
-            obsp = torch.empty((shots, max(words(self.k), 1)), dtype=torch.int32, device=dev)
-            st = torch.empty((shots, 32), dtype=torch.uint8, device=dev) if stats else None
-        else:
-            corr, obsp, st = out
-        pr = _f64(priors)
+        corr, obsp, st = self._outputs(shots, dev, stats, out)
+        pr = self._priors(priors)
         prm = params.c()
         cp = (coop or CoopParams()).c()
         check(lib().rbp_decode_coop(self.h, pr.ctypes.data, _ptr(syndromes), shots, ctypes.byref(prm),
                                     ctypes.byref(cp), _ptr(corr), _ptr(obsp), _ptr(st), _stream(stream)))
         return corr, obsp, st
+
+    def set_coop_phantom(self, phantom: int):
+        """Test hook (rbp_test_set_coop_phantom): latency-mode barriers also wait for
+        `phantom` workgroups that never arrive, so every launch stops with ABORTED."""
+        check(lib().rbp_test_set_coop_phantom(self.h, phantom))
 
     def coop_aborted(self, stream=None) -> bool:
         v = ctypes.c_int32()
@@ -282,11 +342,13 @@ class Code:
 
     def trace(self, priors, syndrome: torch.Tensor, params: RelayParams, leg: int, t: int, phase: int = 0,
               delta: Optional[torch.Tensor] = None, stream=None):
+        _need(syndrome, "syndrome", torch.int32, (words(self.M),))
+        _need(delta, "delta", torch.float32, (self.N,), optional=True)
         dev = syndrome.device
         Mo = torch.empty(self.N, dtype=torch.float32, device=dev)
         mu = torch.empty(max(self.nnz, 1), dtype=torch.float32, device=dev)
         reached = ctypes.c_int32()
-        pr = _f64(priors)
+        pr = self._priors(priors)
         prm = params.c()
         check(lib().rbp_trace(self.h, pr.ctypes.data, _ptr(syndrome), ctypes.byref(prm), _ptr(delta), phase, leg, t,
                               _ptr(Mo), _ptr(mu), ctypes.byref(reached), _stream(stream)))
@@ -307,7 +369,7 @@ class Code:
         """Channel LLRs of the all-zero codeword, float32 [shots][N] (rbp_sample_awgn)."""
         if out is None:
             out = torch.empty((shots, self.N), dtype=torch.float32, device="cuda")
-        assert out.dtype == torch.float32 and out.shape == (shots, self.N) and out.is_contiguous()
+        _need(out, "out", torch.float32, (shots, self.N))
         check(lib().rbp_sample_awgn(self.h, shots, float(sigma), seed, shot_offset, _ptr(out), _stream(stream)))
         return out
 
@@ -317,8 +379,9 @@ class Code:
         counts (int64[3], device) accumulates block errors, undetected errors and
         non-converged shots with respect to the all-zero codeword."""
         params = params or SpaParams()
+        _need(llr, "llr", torch.float32)
         shots = llr.shape[0]
-        assert llr.dtype == torch.float32 and llr.is_contiguous() and llr.shape == (shots, self.N)
+        _need(llr, "llr", torch.float32, (shots, self.N))
         dev = llr.device
         if out is None:
             bits = torch.empty((shots, words(self.N)), dtype=torch.int32, device=dev)
@@ -326,8 +389,12 @@ class Code:
             st = torch.empty((shots, 32), dtype=torch.uint8, device=dev) if stats else None
         else:
             bits, marg, st = out
-        if counts is not None:
-            assert counts.dtype == torch.int64 and counts.numel() >= 3 and counts.is_contiguous()
+            _need(bits, "bits", torch.int32, (shots, words(self.N)))
+            _need(marg, "marginals", torch.float32, (shots, self.N), optional=True)
+            _need(st, "stats", torch.uint8, (shots, 32), optional=True)
+        _need(counts, "counts", torch.int64, optional=True)
+        if counts is not None and counts.numel() < 3:
+            raise ValueError("counts needs 3 entries")
         prm = params.c()
         check(lib().rbp_decode_spa(self.h, _ptr(llr), shots, ctypes.byref(prm), _ptr(bits), _ptr(marg), _ptr(st),
                                    _ptr(counts), _stream(stream)))
@@ -347,12 +414,39 @@ class Code:
 
 def decode_multi(codes: Sequence[Code], priors: Sequence, shot_code: torch.Tensor, shot_index: torch.Tensor,
                  syndromes: Sequence[torch.Tensor], params: RelayParams, corrections: Sequence[torch.Tensor],
-                 obs_pred: Sequence[torch.Tensor], stats: Optional[torch.Tensor] = None, stream=None):
+                 obs_pred: Sequence[torch.Tensor], stats: Optional[torch.Tensor] = None, stream=None,
+                 check_indices: bool = True):
+    """One persistent launch over several models: shot s is row shot_index[s]
+    of model shot_code[s].  With check_indices (default) every code and row
+    index is checked against the models and their arrays before the launch
+    (one device reduction and a synchronization)."""
     n = len(codes)
-    VP = ctypes.c_void_p * n
-    prs = [_f64(p) for p in priors]
-    pr_arr = VP(*[p.ctypes.data for p in prs])
+    if not 1 <= n <= 8 or not (len(priors) == len(syndromes) == len(corrections) == len(obs_pred) == n):
+        raise ValueError("decode_multi needs 1..8 models and one priors/syndromes/corrections/obs_pred entry each")
+    _need(shot_code, "shot_code", torch.uint8)
     shots = shot_code.shape[0]
+    _need(shot_code, "shot_code", torch.uint8, (shots,))
+    _need(shot_index, "shot_index", torch.int32, (shots,))
+    _need(stats, "stats", torch.uint8, (shots, 32), optional=True)
+    rows = []
+    for i, c in enumerate(codes):
+        _need(syndromes[i], f"syndromes[{i}]", torch.int32)
+        r = syndromes[i].shape[0]
+        rows.append(r)
+        _need(syndromes[i], f"syndromes[{i}]", torch.int32, (r, words(c.M)))
+        _need(corrections[i], f"corrections[{i}]", torch.int32, (r, words(c.N)))
+        _need(obs_pred[i], f"obs_pred[{i}]", torch.int32, (r, max(words(c.k), 1)))
+    if check_indices and shots > 0:
+        code_l = shot_code.to(torch.int64)
+        if int(code_l.max().item()) >= n:
+            raise ValueError("shot_code has a value >= the number of models")
+        idx = shot_index.to(torch.int64)  # int32 rows; negative values are out of range
+        lim = torch.tensor(rows, dtype=torch.int64, device=shot_code.device)[code_l]
+        if bool(((idx < 0) | (idx >= lim)).any().item()):
+            raise ValueError("shot_index has a row outside its model's arrays")
+    VP = ctypes.c_void_p * n
+    prs = [c._priors(p) for c, p in zip(codes, priors)]
+    pr_arr = VP(*[p.ctypes.data for p in prs])
     prm = params.c()
     check(lib().rbp_decode_multi(n, VP(*[c.h.value for c in codes]), pr_arr, _ptr(shot_code), _ptr(shot_index),
                                  shots, VP(*[s.data_ptr() for s in syndromes]), ctypes.byref(prm),
@@ -363,13 +457,20 @@ def decode_multi(codes: Sequence[Code], priors: Sequence, shot_code: torch.Tenso
 def count_failures(obs_pred: torch.Tensor, obs: torch.Tensor, stats: torch.Tensor, count: torch.Tensor,
                    stream=None):
     """count (int64[1] on the device) += block failures of the batch (GPU reduction)."""
+    _need(obs, "obs", torch.int32)
+    _need(obs_pred, "obs_pred", torch.int32, tuple(obs.shape))
+    _need(stats, "stats", torch.uint8, (obs.shape[0], 32))
+    _need(count, "count", torch.int64)
     check(lib().rbp_count_failures(_ptr(obs_pred), _ptr(obs), _ptr(stats), obs.shape[0], obs.shape[1], _ptr(count),
                                    _stream(stream)))
 
 
 def bits_extract(src: torch.Tensor, bit_offset: int, nbits: int, out: torch.Tensor, stream=None) -> torch.Tensor:
     """out[s] = bits [bit_offset, bit_offset + nbits) of src[s] (rbp_bits_extract)."""
-    assert src.dtype == torch.int32 and out.dtype == torch.int32 and src.is_contiguous() and out.is_contiguous()
+    _need(src, "src", torch.int32)
+    _need(out, "out", torch.int32)
+    if out.shape[0] != src.shape[0]:
+        raise ValueError("src and out need the same number of rows")
     check(lib().rbp_bits_extract(_ptr(src), src.shape[1], src.shape[0], bit_offset, nbits, _ptr(out), out.shape[1],
                                  _stream(stream)))
     return out
@@ -377,8 +478,11 @@ def bits_extract(src: torch.Tensor, bit_offset: int, nbits: int, out: torch.Tens
 
 def bits_gather(src: torch.Tensor, rows: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
     """out[s] bit t = src[s] bit rows[t] (rbp_bits_gather); rows int32 on the device."""
-    assert src.dtype == torch.int32 and out.dtype == torch.int32 and rows.dtype == torch.int32
-    assert src.is_contiguous() and out.is_contiguous() and rows.is_contiguous()
+    _need(src, "src", torch.int32)
+    _need(out, "out", torch.int32)
+    _need(rows, "rows", torch.int32)
+    if out.shape[0] != src.shape[0]:
+        raise ValueError("src and out need the same number of rows")
     check(lib().rbp_bits_gather(_ptr(src), src.shape[1], src.shape[0], _ptr(rows), rows.numel(), _ptr(out),
                                 out.shape[1], _stream(stream)))
     return out
@@ -386,7 +490,8 @@ def bits_gather(src: torch.Tensor, rows: torch.Tensor, out: torch.Tensor, stream
 
 def window_residual(syndromes: torch.Tensor, acc_stats: torch.Tensor, stream=None):
     """Clear `converged` of the shots whose running syndrome is not zero (rbp_window_residual)."""
-    assert syndromes.dtype == torch.int32 and syndromes.is_contiguous()
+    _need(syndromes, "syndromes", torch.int32)
+    _need(acc_stats, "acc_stats", torch.uint8, (syndromes.shape[0], 32))
     check(lib().rbp_window_residual(_ptr(syndromes), syndromes.shape[1], syndromes.shape[0], _ptr(acc_stats),
                                     _stream(stream)))
 
@@ -396,8 +501,14 @@ def window_commit(code: "Code", win_corr: torch.Tensor, cmap: torch.Tensor, n_wi
                   acc_stats: Optional[torch.Tensor] = None, first: bool = False, stream=None):
     """Commit a window's decoded mechanisms to the full model (rbp_window_commit)."""
     shots = win_corr.shape[0]
-    for t in (win_corr, cmap, syndromes, obs_pred, corrections):
-        assert t.dtype == torch.int32 and t.is_contiguous()
+    for name, t in (("win_corr", win_corr), ("cmap", cmap), ("syndromes", syndromes), ("obs_pred", obs_pred),
+                    ("corrections", corrections)):
+        _need(t, name, torch.int32)
+    for name, t in (("syndromes", syndromes), ("obs_pred", obs_pred), ("corrections", corrections)):
+        if t.shape[0] != shots:
+            raise ValueError(f"{name} needs {shots} rows")
+    _need(win_stats, "win_stats", torch.uint8, (shots, 32), optional=True)
+    _need(acc_stats, "acc_stats", torch.uint8, (shots, 32), optional=True)
     check(lib().rbp_window_commit(code.h, shots, _ptr(win_corr), win_corr.shape[1], _ptr(cmap), n_win,
                                   _ptr(syndromes), _ptr(obs_pred), _ptr(corrections), _ptr(win_stats),
                                   _ptr(acc_stats), 1 if first else 0, _stream(stream)))
@@ -427,13 +538,15 @@ class MLP:
         h = ctypes.c_void_p()
         check(lib().rbp_mlp_create(in_dim, hidden, out_dim, seed, ctypes.byref(h)))
         self.h = h
+        _live.add(self)
         n = ctypes.c_int64()
         check(lib().rbp_mlp_num_params(self.h, ctypes.byref(n)))
         self.n_params = n.value
 
     def close(self):
         if getattr(self, "h", None):
-            lib().rbp_mlp_destroy(self.h)
+            if not _finalized:
+                lib().rbp_mlp_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -443,22 +556,32 @@ class MLP:
             pass
 
     def forward(self, syndromes: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        _need(syndromes, "syndromes", torch.int32)
         shots = syndromes.shape[0]
-        assert syndromes.shape[1] == words(self.in_dim) and syndromes.is_contiguous()
+        _need(syndromes, "syndromes", torch.int32, (shots, words(self.in_dim)))
         if out is None:
             out = torch.empty((shots, self.out_dim), dtype=torch.float32, device=syndromes.device)
+        _need(out, "out", torch.float32, (shots, self.out_dim))
         check(lib().rbp_mlp_forward(self.h, _ptr(syndromes), shots, _ptr(out), _stream(stream)))
         return out
 
     def train_step(self, syndromes: torch.Tensor, targets: torch.Tensor, llr: torch.Tensor, lr: float,
                    loss_out: Optional[torch.Tensor] = None, stream=None):
+        _need(syndromes, "syndromes", torch.int32)
         batch = syndromes.shape[0]
-        assert targets.shape == (batch, words(self.out_dim)) and llr.shape == (self.out_dim,)
+        _need(syndromes, "syndromes", torch.int32, (batch, words(self.in_dim)))
+        _need(targets, "targets", torch.int32, (batch, words(self.out_dim)))
+        _need(llr, "llr", torch.float32, (self.out_dim,))
+        _need(loss_out, "loss_out", torch.float32, optional=True)
         check(lib().rbp_mlp_train_step(self.h, _ptr(syndromes), _ptr(targets), _ptr(llr), batch, ctypes.c_float(lr),
                                        _ptr(loss_out), _stream(stream)))
 
     def gradients(self, syndromes: torch.Tensor, targets: torch.Tensor, llr: torch.Tensor, stream=None):
+        _need(syndromes, "syndromes", torch.int32)
         batch = syndromes.shape[0]
+        _need(syndromes, "syndromes", torch.int32, (batch, words(self.in_dim)))
+        _need(targets, "targets", torch.int32, (batch, words(self.out_dim)))
+        _need(llr, "llr", torch.float32, (self.out_dim,))
         g = torch.empty(self.n_params, dtype=torch.float32, device=syndromes.device)
         loss = torch.empty(1, dtype=torch.float32, device=syndromes.device)
         check(lib().rbp_mlp_gradients(self.h, _ptr(syndromes), _ptr(targets), _ptr(llr), batch, _ptr(g), _ptr(loss),
@@ -472,5 +595,14 @@ class MLP:
 
     def set_params(self, params: np.ndarray):
         p = np.ascontiguousarray(params, dtype=np.float32)
-        assert p.size == self.n_params
+        if p.size != self.n_params:
+            raise ValueError(f"need {self.n_params} parameters (got {p.size})")
         check(lib().rbp_mlp_set_params(self.h, p.ctypes.data))
+
+    def save(self, path: str):
+        """Checkpoint of masters, Adam moments and step (rbp_mlp_save)."""
+        check(lib().rbp_mlp_save(self.h, os.fsencode(path)))
+
+    def load(self, path: str):
+        """Restore a checkpoint written by save() into this handle (rbp_mlp_load)."""
+        check(lib().rbp_mlp_load(self.h, os.fsencode(path)))

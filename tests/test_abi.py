@@ -6,19 +6,20 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rbp.h")
+INCLUDE = os.path.join(ROOT, "include")
 PKG = os.path.join(ROOT, "paper_2607_27644_amd")
 
 
 def declared_symbols():
-    txt = open(HEADER).read()
+    """Every function declared in include/*.h."""
+    txt = "".join(open(os.path.join(INCLUDE, f)).read() for f in sorted(os.listdir(INCLUDE)) if f.endswith(".h"))
     return sorted(set(re.findall(r"\b(rbp_[a-z_0-9]+)\s*\(", txt)))
 
 
 def test_header_declares_the_boundary():
     syms = declared_symbols()
     for must in ("rbp_code_create", "rbp_sample", "rbp_decode", "rbp_decode_multi", "rbp_trace",
-                 "rbp_mlp_forward", "rbp_mlp_train_step", "rbp_last_error"):
+                 "rbp_mlp_forward", "rbp_mlp_train_step", "rbp_mlp_save", "rbp_mlp_load", "rbp_last_error"):
         assert must in syms
 
 

@@ -14,6 +14,7 @@ torch = pytest.importorskip("torch")
 import oracle  # noqa: E402
 from paper_2607_27644_amd import circuits as C  # noqa: E402
 from paper_2607_27644_amd import workloads as W  # noqa: E402
+from gf2 import gf2_product  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +58,7 @@ def compare(rbp, dem, syn_np, out, ref, max_diff):
         assert np.array_equal(s[key][same], ref[key][same]), key
     e = W.unpack_bits(u32(corr), dem.N)
     conv = s["converged"] == 1
-    resyn = (e.astype(np.int64) @ dem.H.T.astype(np.int64)) % 2
+    resyn = gf2_product(e, dem.H)
     assert np.array_equal(resyn[conv], W.unpack_bits(syn_np, dem.M)[conv])
     return same
 

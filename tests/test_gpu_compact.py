@@ -15,6 +15,7 @@ torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
 from paper_2607_27644_amd import workloads as W  # noqa: E402
+from gf2 import gf2_product  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -62,7 +63,7 @@ def _compare(rbp, dem, syn_np, out, ref, min_agree=0.999):
         assert np.array_equal(stats[key][same], ref[key][same]), key
     e = W.unpack_bits(c, dem.N)
     conv = stats["converged"] == 1
-    resyn = (e.astype(np.int64) @ dem.H.T.astype(np.int64)) % 2
+    resyn = gf2_product(e, dem.H)
     assert np.array_equal(resyn[conv], W.unpack_bits(syn_np, dem.M)[conv])
     return same.mean()
 

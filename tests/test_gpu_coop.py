@@ -104,13 +104,19 @@ def test_coop_matches_oracle(rbp):
 
 
 def test_coop_expired_barrier_is_reported(rbp):
+    """A barrier forced to expire from the host (the test hook adds a phantom
+    participant that never arrives; tiny poll bound) stops the launch, which
+    returns ABORTED; the next launch runs normally."""
     dem = dem_of("tiny60")
     code = rbp.Code.from_dem(dem)
     params = rbp.RelayParams()
     syn, _, _ = code.sample(dem.priors, 4, seed=75)
-    code.decode_coop(dem.priors, syn, params, rbp.CoopParams(workgroups=4, stride=1, spin_limit=2000, phantom=1))
-    torch.cuda.synchronize()
+    code.set_coop_phantom(1)
+    with pytest.raises(rbp.RbpError, match="ABORTED") as ex:
+        code.decode_coop(dem.priors, syn, params, rbp.CoopParams(workgroups=4, stride=1, spin_limit=2000))
+    assert ex.value.status == rbp.RBP_ERR_ABORTED
     assert code.coop_aborted()
+    code.set_coop_phantom(0)
     ref = code.decode(dem.priors, syn, params)
     got = code.decode_coop(dem.priors, syn, params)
     torch.cuda.synchronize()

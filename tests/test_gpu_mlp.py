@@ -108,3 +108,42 @@ def test_forward_chunking_and_empty(rbp):
     part = net.forward(xs[17000:17100].contiguous()).cpu().numpy()
     assert np.array_equal(full[17000:17100], part)
     net.forward(xs[:0])
+
+
+def test_checkpoint_resume_is_exact(rbp, tmp_path):
+    """Training split by a save/load (masters, Adam moments and step) equals the
+    same training without the split, bit for bit; rbp_mlp_set_params (which
+    resets the Adam state) does not."""
+    din, h, dout, B = 64, 128, 160, 256
+    rng = np.random.default_rng(12)
+    lam = torch.from_numpy(rng.uniform(2.0, 9.0, dout).astype(np.float32)).cuda()
+    batches = []
+    for _ in range(10):
+        x = (rng.random((B, din)) < 0.1).astype(np.uint8)
+        y = (rng.random((B, dout)) < 0.03).astype(np.uint8)
+        batches.append((_dev_bits(x), _dev_bits(y)))
+    whole = rbp.MLP(din, h, dout, seed=9)
+    for xs, ys in batches:
+        whole.train_step(xs, ys, lam, lr=1e-3)
+    first = rbp.MLP(din, h, dout, seed=9)
+    for xs, ys in batches[:5]:
+        first.train_step(xs, ys, lam, lr=1e-3)
+    path = str(tmp_path / "net.ckpt")
+    first.save(path)
+    resumed = rbp.MLP(din, h, dout, seed=123)  # other initial weights, overwritten by the load
+    resumed.load(path)
+    for xs, ys in batches[5:]:
+        resumed.train_step(xs, ys, lam, lr=1e-3)
+    assert np.array_equal(resumed.get_params(), whole.get_params())
+    reset = rbp.MLP(din, h, dout, seed=123)
+    reset.set_params(first.get_params())
+    for xs, ys in batches[5:]:
+        reset.train_step(xs, ys, lam, lr=1e-3)
+    assert not np.array_equal(reset.get_params(), whole.get_params())
+    # wrong dimensions and a file that is not a checkpoint are rejected
+    with pytest.raises(rbp.RbpError, match="SHAPE"):
+        rbp.MLP(din, h, dout + 1, seed=1).load(path)
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(b"not a checkpoint at all")
+    with pytest.raises(rbp.RbpError, match="INVALID_ARG"):
+        resumed.load(str(bad))

@@ -13,6 +13,7 @@ torch = pytest.importorskip("torch")
 import oracle  # noqa: E402
 from oracle import window as owin  # noqa: E402
 from paper_2607_27644_amd import workloads as W  # noqa: E402
+from gf2 import gf2_product  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -67,8 +68,8 @@ def test_window_commit(mods):
     for j in range(n_win):
         if cmap[j] >= 0:
             e[:, cmap[j]] = ew[:, j]
-    s = (owin._unpack(syn0, dem.M) + e.astype(np.int64) @ dem.H.T.astype(np.int64)) % 2
-    o = (e.astype(np.int64) @ dem.O.T.astype(np.int64)) % 2
+    s = owin._unpack(syn0, dem.M) ^ gf2_product(e, dem.H)
+    o = gf2_product(e, dem.O)
     np.testing.assert_array_equal(u32(tsyn), pack(s.astype(np.uint8)))
     np.testing.assert_array_equal(u32(tobs), pack(o.astype(np.uint8)))
     np.testing.assert_array_equal(u32(tcorr), pack(e))
