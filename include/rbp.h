@@ -126,6 +126,23 @@ rbp_status rbp_decode(rbp_code_t code, const double* priors, const uint32_t* syn
                       const rbp_relay_params* params, const float* prior_delta_dev, uint32_t* corrections_dev,
                       uint32_t* obs_pred_dev, rbp_shot_stats* stats_dev, void* stream);
 
+/* rbp_decode for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same decode, arguments, outputs and results, but its scratch -- the shot
+ * counter, the ordering histogram and the heaviest-first shot order -- lives
+ * in a fixed 4 MiB device array per GPU, so the call allocates nothing.
+ * Limits: at most 1,048,064 shots per call (UNSUPPORTED beyond); the handle's
+ * per-shot state must fit in LDS (UNSUPPORTED for models decoded with the
+ * state in device memory); the handle must already have decoded with the same
+ * priors and relay parameters through rbp_decode, which builds its tables
+ * (INVALID_ARG otherwise).  Every call on one GPU shares that array and
+ * clears what must start at zero itself, with kernels (no memset); calls
+ * that overlap on one GPU (several streams or threads) race and must not be
+ * issued. */
+rbp_status rbp_decode_noalloc(rbp_code_t code, const double* priors, const uint32_t* syndromes_dev, uint64_t shots,
+                              const rbp_relay_params* params, const float* prior_delta_dev, uint32_t* corrections_dev,
+                              uint32_t* obs_pred_dev, rbp_shot_stats* stats_dev, void* stream);
+
 /* Batched decode of several detector error models in one persistent launch.
  * Shot s belongs to model shot_code_dev[s] (uint8, < n_codes) and is the
  * shot_index_dev[s]-th row of that model's syndrome / output arrays

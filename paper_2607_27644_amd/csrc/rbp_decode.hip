@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2289,18 +2290,29 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
     return RBP_OK;
 }
 
-static rbp_status launch_decode(rbp_code* const* cs, int n, DecodeLaunch& a, uint64_t shots, hipStream_t stream) {
+// queue: the shot counter in caller-provided scratch (the launch then
+// allocates nothing and needs the per-shot state in LDS), or null for the
+// handle's own counter
+static rbp_status launch_decode(rbp_code* const* cs, int n, DecodeLaunch& a, uint64_t shots, hipStream_t stream,
+                                unsigned long long* queue = nullptr) {
     LaunchShape L;
     rbp_status st = plan_launch(cs, n, shots, &L);
     if (st) return st;
     rbp_code* c0 = cs[0];
-    st = c0->queue.reserve(64);
-    if (st) return st;
-    if (!L.lds_state) {
-        st = c0->gstate.reserve(sizeof(float) * (size_t)L.gstride * L.slots);
+    if (queue) {
+        if (!L.lds_state)
+            return fail(RBP_ERR_UNSUPPORTED, "the per-shot state of this model lives in device memory, which the "
+                                             "allocation-free decode cannot provide");
+    } else {
+        st = c0->queue.reserve(64);
         if (st) return st;
+        if (!L.lds_state) {
+            st = c0->gstate.reserve(sizeof(float) * (size_t)L.gstride * L.slots);
+            if (st) return st;
+        }
+        queue = c0->queue.as<unsigned long long>();
     }
-    a.queue = c0->queue.as<unsigned long long>();
+    a.queue = queue;
     a.gstate = L.lds_state ? nullptr : c0->gstate.as<float>();
     a.gstate_stride = L.gstride;
     a.Smax = L.Smax;
@@ -2327,22 +2339,63 @@ static rbp_status launch_decode(rbp_code* const* cs, int n, DecodeLaunch& a, uin
 // per shot) keeps its order too: it measured slower when sorted.
 constexpr uint64_t kOrderMinShots = 8192;
 
-static rbp_status order_by_weight(rbp_code* c, const uint32_t* syn, uint64_t shots, hipStream_t stream) {
+// the heaviest-first order of the batch into order[shots], with a 256-bin
+// histogram in hist (both device buffers the caller provides)
+static rbp_status order_into(const rbp_code* c, const uint32_t* syn, uint64_t shots, uint32_t* hist, uint32_t* order,
+                             hipStream_t stream) {
     const unsigned blocks = (unsigned)((shots + 255) / 256);
-    rbp_status st = c->order.reserve(sizeof(uint32_t) * shots);
-    if (!st) st = c->ohist.reserve(sizeof(uint32_t) * kOrderBins);
-    if (st) return st;
     const int words = ceil_div(c->M, 32);
-    uint32_t* hist = c->ohist.as<uint32_t>();
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, stream, hist, kOrderBins);
     RBP_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(order_hist_kernel, dim3(blocks), dim3(256), 0, stream, syn, words, shots, hist);
     RBP_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, stream, hist);
     RBP_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, stream, syn, words, shots, hist,
-                       c->order.as<uint32_t>());
+    hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, stream, syn, words, shots, hist, order);
     RBP_HIP_CHECK(hipGetLastError());
+    return RBP_OK;
+}
+
+static rbp_status order_by_weight(rbp_code* c, const uint32_t* syn, uint64_t shots, hipStream_t stream) {
+    rbp_status st = c->order.reserve(sizeof(uint32_t) * shots);
+    if (!st) st = c->ohist.reserve(sizeof(uint32_t) * kOrderBins);
+    if (st) return st;
+    return order_into(c, syn, shots, c->ohist.as<uint32_t>(), c->order.as<uint32_t>(), stream);
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of rbp_decode_noalloc: one fixed device array per GPU holding the
+// shot counter, the ordering histogram and the shot order, so that the call
+// allocates nothing.  In host code `scratch` names a host-side stand-in, never
+// the device memory: its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and only that address is
+// passed to kernels.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = 4u << 20;
+constexpr size_t kScratchOrderOff = 2048;  // counter at 0, histogram at 256, order from here
+constexpr uint64_t kScratchMaxShots = (kScratchBytes - kScratchOrderOff) / sizeof(uint32_t);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static unsigned char* g_scratch[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// the device address of this device's scratch (set up on first use)
+static rbp_status scratch_of(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(RBP_ERR_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        int cur = 0;
+        RBP_HIP_CHECK(hipGetDevice(&cur));
+        if (cur != dev) RBP_HIP_CHECK(hipSetDevice(dev));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return fail(RBP_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = g_scratch[dev];
     return RBP_OK;
 }
 
@@ -2541,6 +2594,14 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
         delete c;
         return fail(RBP_ERR_HIP, std::string("device query: ") + hipGetErrorString(he));
     }
+    {
+        unsigned char* sp = nullptr;
+        const rbp_status sst = scratch_of(c->device, &sp);
+        if (sst) {
+            delete c;
+            return sst;
+        }
+    }
     std::vector<int32_t> cp(col_ptr, col_ptr + N + 1), cr(row_idx, row_idx + E);
     std::vector<int32_t> ocp(N + 1, 0), ori;
     if (k > 0) {
@@ -2680,6 +2741,54 @@ rbp_status rbp_decode(rbp_code_t c, const double* priors, const uint32_t* syndro
     }
     rbp_code* cs[1] = {c};
     return launch_decode(cs, 1, a, shots, stream);
+}
+
+rbp_status rbp_decode_noalloc(rbp_code_t c, const double* priors, const uint32_t* syndromes, uint64_t shots,
+                              const rbp_relay_params* params, const float* prior_delta, uint32_t* corrections,
+                              uint32_t* obs_pred, rbp_shot_stats* stats, void* stream_) {
+    if (!c) return fail(RBP_ERR_INVALID_ARG, "code is NULL");
+    rbp_status st = check_params(params);
+    if (st) return st;
+    if (shots == 0) return RBP_OK;
+    if (shots > kScratchMaxShots)
+        return fail(RBP_ERR_UNSUPPORTED, "allocation-free decode: at most " + std::to_string(kScratchMaxShots) +
+                                             " shots per call (4 MiB of scratch)");
+    if (!syndromes || !corrections) return fail(RBP_ERR_INVALID_ARG, "syndromes/corrections is NULL");
+    if (c->k > 0 && !obs_pred) return fail(RBP_ERR_INVALID_ARG, "obs_pred is NULL");
+    st = check_priors(priors, c->N);
+    if (st) return st;
+    // the handle's tables must already hold these priors and parameters (an
+    // rbp_decode call builds them); rebuilding them would allocate
+    const bool ready = c->lam.p && c->lam_key.size() == (size_t)c->N &&
+                       std::memcmp(c->lam_key.data(), priors, sizeof(double) * c->N) == 0 && c->gtab.p &&
+                       c->gtab_R == params->num_sets && c->gtab_seed == params->gamma_seed &&
+                       c->gtab_lo == params->gamma_min && c->gtab_hi == params->gamma_max && c->lg.p &&
+                       c->lg_lam_gen == c->lam_gen && c->lg_gtab_gen == c->gtab_gen &&
+                       c->lg_gamma0 == params->gamma0 && c->lg_R == params->num_sets;
+    if (!ready)
+        return fail(RBP_ERR_INVALID_ARG, "allocation-free decode: call rbp_decode once with these priors and relay "
+                                         "parameters first (it builds the handle's tables)");
+    unsigned char* sp = nullptr;
+    st = scratch_of(c->device, &sp);
+    if (st) return st;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    DecodeLaunch a;
+    std::memset(&a, 0, sizeof(a));
+    a.m[0] = model_of(c, syndromes, corrections, obs_pred);
+    a.n_models = 1;
+    a.delta = prior_delta;
+    a.stats = stats;
+    fill_params(a, params);
+    if (!prior_delta && shots >= kOrderMinShots) {
+        uint32_t* hist = reinterpret_cast<uint32_t*>(sp + 256);
+        uint32_t* order = reinterpret_cast<uint32_t*>(sp + kScratchOrderOff);
+        st = order_into(c, syndromes, shots, hist, order, stream);
+        if (st) return st;
+        a.shot_index = order;
+        a.stats_by_row = 1;
+    }
+    rbp_code* cs[1] = {c};
+    return launch_decode(cs, 1, a, shots, stream, reinterpret_cast<unsigned long long*>(sp));
 }
 
 rbp_status rbp_decode_coop(rbp_code_t c, const double* priors, const uint32_t* syndromes, uint64_t shots,

@@ -138,6 +138,7 @@ def lib():
         "rbp_sample": [vp, vp, u64, u64, u64, vp, vp, vp, vp],
         "rbp_decode": [vp, vp, vp, u64, P(RelayParamsC), vp, vp, vp, vp, vp],
         "rbp_decode_multi": [i32, vp, vp, vp, vp, u64, vp, P(RelayParamsC), vp, vp, vp, vp],
+        "rbp_decode_noalloc": [vp, vp, vp, u64, P(RelayParamsC), vp, vp, vp, vp, vp],
         "rbp_set_launch_config": [vp, P(LaunchConfigC)],
         "rbp_get_launch_config": [vp, P(LaunchConfigC), P(i32), P(i32)],
         "rbp_trace": [vp, vp, vp, P(RelayParamsC), vp, i32, i32, i32, vp, vp, P(i32), vp],
@@ -311,6 +312,25 @@ class Code:
         prm = params.c()
         check(lib().rbp_decode(self.h, pr.ctypes.data, _ptr(syndromes), shots, ctypes.byref(prm), _ptr(delta),
                                _ptr(corr), _ptr(obsp), _ptr(st), _stream(stream)))
+        return corr, obsp, st
+
+    def decode_noalloc(self, priors, syndromes: torch.Tensor, params: RelayParams,
+                       delta: Optional[torch.Tensor] = None, stream=None, out=None):
+        """rbp_decode_noalloc: the decode without any device allocation in the
+        library (its scratch is a fixed array per GPU).  out = (corrections,
+        obs_pred, stats or None) is required, so this call allocates nothing
+        either; decode() must have run once with the same priors and params."""
+        if out is None:
+            raise ValueError("decode_noalloc needs out=(corrections, obs_pred, stats)")
+        _need(syndromes, "syndromes", torch.int32)
+        shots = syndromes.shape[0]
+        _need(syndromes, "syndromes", torch.int32, (shots, words(self.M)))
+        _need(delta, "delta", torch.float32, (shots, self.N), optional=True)
+        corr, obsp, st = self._outputs(shots, syndromes.device, True, out)
+        pr = self._priors(priors)
+        prm = params.c()
+        check(lib().rbp_decode_noalloc(self.h, pr.ctypes.data, _ptr(syndromes), shots, ctypes.byref(prm),
+                                       _ptr(delta), _ptr(corr), _ptr(obsp), _ptr(st), _stream(stream)))
         return corr, obsp, st
 
     def decode_coop(self, priors, syndromes: torch.Tensor, params: RelayParams, coop: Optional[CoopParams] = None,
