@@ -16,8 +16,8 @@ Paths, each timed the same way on the same shots:
   learned         proposal network (trained in-run on decoder-generated pairs)
                   -> proposal leg, plain Relay-BP as the fallback
   proposal_zero   the same proposal leg with delta = 0 (no network)
-A p = 5e-3 point decodes the same syndromes with every path so that the
-logical-error comparison has failures.  Beside the headline: sequential
+Paired points at p = 5e-3 and 2.5e-2 decode the same syndromes with every
+path (the [[840,168]] model shows no failure in 10^5 shots below about 2 %).  Beside the headline: sequential
 single-shot latency, the batched uneven decode of four codes, the paper's
 latency-table workload (circuit-level ZSZ-LP-320 memory), the classical AWGN
 benchmark and the earlier ZSZ-LP-160 workload.  Prints one JSON line.
@@ -48,13 +48,15 @@ def parse():
     ap.add_argument("--shots", type=int, default=100000)
     ap.add_argument("--workload", default="phen840")
     ap.add_argument("--seed", type=int, default=20260101)
-    ap.add_argument("--ler-p", type=float, default=5e-3)
+    ap.add_argument("--ler-ps", default="5e-3,2.5e-2", help="noise strengths of the paired LER points")
     ap.add_argument("--ler-shots", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sequential", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--train-pairs", type=int, default=1_000_000)
+    ap.add_argument("--hidden", type=int, default=128, help="width of the proposal network's hidden layers")
+    ap.add_argument("--delta-scale", type=float, default=0.5, help="shrinkage of the network's output")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates rocprof byte counters)")
@@ -176,14 +178,14 @@ def main():
         code.sample(dem.priors, S, args.seed + i, out=(syn, obs, None))
         if record:
             e[1].record()
-        delta = None
         if path == "learned":
-            delta = state["net"].forward(syn, out=state["delta"])
-        elif path == "proposal_zero":
-            delta = state["delta"]
+            state["net"].forward_bf16(syn, out=state["delta"])
         if record:
             e[2].record()
-        code.decode(dem.priors, syn, prm, delta=delta, out=(corr, obsp, st))
+        if path in ("learned", "proposal_zero"):
+            code.decode_proposal(dem.priors, syn, prm, state["delta"], out=(corr, obsp, st))
+        else:
+            code.decode(dem.priors, syn, prm, out=(corr, obsp, st))
         if record:
             e[3].record()
             ev.append(e)
@@ -256,7 +258,7 @@ def main():
 
     if not args.no_learned:
         from paper_2607_27644_amd import learned
-        cfg = learned.TrainConfig(pairs=args.train_pairs)
+        cfg = learned.TrainConfig(pairs=args.train_pairs, hidden=args.hidden, delta_scale=args.delta_scale)
         t0 = time.perf_counter()
         chunks = learned.generate_pairs(code, dem.priors, cfg, params)
         t1 = time.perf_counter()
@@ -267,7 +269,7 @@ def main():
         t2 = time.perf_counter()
         del chunks
         state["net"] = net
-        state["delta"] = torch.empty((S, dem.N), dtype=torch.float32, device=dev)
+        state["delta"] = torch.empty((S, dem.N), dtype=torch.bfloat16, device=dev)
         paths["learned"] = timed("learned", params)
         state["delta"].zero_()
         paths["proposal_zero"] = timed("proposal_zero", params)
@@ -285,34 +287,40 @@ def main():
         L["vs_first_solution"] = L["value"] / paths["first_solution"]["value"]
         L["vs_plain"] = L["value"] / P["value"]
         paths["proposal_zero"]["note"] = "control: the same proposal leg with delta = 0 (no network)"
+        L["note"] = ("network -> BF16 adjustments (rbp_mlp_forward_bf16) -> proposal leg with the adjustments "
+                     "in LDS, plain Relay-BP as the fallback (rbp_decode_proposal)")
     out.update(paths)
 
-    # logical error rates at a higher p, every path on the same syndromes
-    if args.ler_p > 0:
-        pri = np.full(dem.N, args.ler_p)
+    # logical error rates at higher p, every path on the same syndromes
+    out["ler_high_p"] = []
+    for lp in [float(x) for x in args.ler_ps.split(",") if x]:
+        pri = np.full(dem.N, lp)
         n = args.ler_shots
         hsyn, hobs, _ = code.sample(pri, n, args.seed + 777)
-        res = {"p": args.ler_p, "shots": n}
+        res = {"p": lp, "shots": n}
         masks = {}
         runs = [("plain", params, None), ("first_solution", fs, None)]
         if state["net"] is not None:
             runs += [("learned", params, "net"), ("proposal_zero", params, "zero")]
         for name, prm, dk in runs:
             d = None
-            if dk == "net":
-                d = state["net"].forward(hsyn)
-            elif dk == "zero":
-                d = torch.zeros((n, dem.N), dtype=torch.float32, device=dev)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            c, o, s = code.decode(pri, hsyn, prm, delta=d)
+            if dk == "net":
+                d = state["net"].forward_bf16(hsyn)
+            elif dk == "zero":
+                d = torch.zeros((n, dem.N), dtype=torch.bfloat16, device=dev)
+            if d is not None:
+                c, o, s = code.decode_proposal(pri, hsyn, prm, d)
+            else:
+                c, o, s = code.decode(pri, hsyn, prm)
             e1.record()
             torch.cuda.synchronize()
             sn = rbp.stats_to_numpy(s)
             f = stats.block_failures(rbp.to_u32(o), rbp.to_u32(hobs), sn["converged"])
             masks[name] = f
             res[name] = {"ler": stats.ler_summary(int(f.sum()), n, dem.rounds, dem.k),
-                         "decode_shots_per_s": n / (e0.elapsed_time(e1) * 1e-3),
+                         "shots_per_s_network_and_decode": n / (e0.elapsed_time(e1) * 1e-3),
                          "mean_iters_per_shot": float(sn["iters"].mean()),
                          "non_converged": int((sn["converged"] == 0).sum())}
             del d, c, o, s
@@ -321,7 +329,7 @@ def main():
                 a, b = masks["plain"], masks[name]
                 res[name]["paired_vs_plain"] = {"plain_only": int((a & ~b).sum()), "this_only": int((b & ~a).sum()),
                                                 "both": int((a & b).sum())}
-        out["ler_high_p"] = res
+        out["ler_high_p"].append(res)
 
     if not args.no_sequential:
         # the paper's sequential mode: one shot per decode call, host clock around each

@@ -126,6 +126,18 @@ rbp_status rbp_decode(rbp_code_t code, const double* priors, const uint32_t* syn
                       const rbp_relay_params* params, const float* prior_delta_dev, uint32_t* corrections_dev,
                       uint32_t* obs_pred_dev, rbp_shot_stats* stats_dev, void* stream);
 
+/* The learned-proposal decode with BF16 adjustments, the network's own output
+ * type (rbp_mlp_forward_bf16): identical to rbp_decode with prior_delta_dev
+ * holding the same values widened to float (every BF16 value is exact in
+ * FP32), but delta_bf16_dev uint16[shots][N] (BF16 bit patterns, required)
+ * moves half the bytes, and the compact state copies a shot's adjustments to
+ * LDS once instead of reading them on every iteration of the proposal leg.
+ * Outputs as rbp_decode. */
+rbp_status rbp_decode_proposal(rbp_code_t code, const double* priors, const uint32_t* syndromes_dev, uint64_t shots,
+                               const rbp_relay_params* params, const uint16_t* delta_bf16_dev,
+                               uint32_t* corrections_dev, uint32_t* obs_pred_dev, rbp_shot_stats* stats_dev,
+                               void* stream);
+
 /* rbp_decode for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation): the
  * same decode, arguments, outputs and results, but its scratch -- the shot
@@ -246,6 +258,12 @@ rbp_status rbp_mlp_destroy(rbp_mlp_t mlp);
 /* delta_dev float[shots][out_dim] from syndromes_dev uint32[shots][ceil(in_dim/32)]. */
 rbp_status rbp_mlp_forward(rbp_mlp_t mlp, const uint32_t* syndromes_dev, uint64_t shots, float* delta_dev,
                            void* stream);
+/* The same forward pass with the output rounded to BF16 (round to nearest
+ * even, from the FP32 value rbp_mlp_forward writes): delta_dev
+ * uint16[shots][out_dim] of BF16 bit patterns, the input of
+ * rbp_decode_proposal. */
+rbp_status rbp_mlp_forward_bf16(rbp_mlp_t mlp, const uint32_t* syndromes_dev, uint64_t shots, uint16_t* delta_dev,
+                                void* stream);
 /* One Adam step on a batch: loss = mean over the batch of
  * sum_j BCEWithLogits(z_j, y_j), z_j = -(Lambda_j + delta_j), y = target bits
  * (uint32[batch][ceil(out_dim/32)]), Lambda = llr_dev float[out_dim].

@@ -1,7 +1,8 @@
 """Launch-shape autotuner for the persistent Relay-BP decoder.
 
 For one detector error model it times the decoder on a calibration batch for
-every wavefronts-per-shot count and state placement (LDS or device memory),
+every wavefronts-per-shot count and state (per-edge messages in LDS or in
+device memory, or compact row records in LDS),
 keeps the fastest, applies it to the handle (rbp_set_launch_config) and caches
 the choice by (model hash, device name, relay parameters) in a JSON file
 ($RBP_TUNE_CACHE, default ~/.cache/rbp/tune.json).  Outputs never depend on the
@@ -20,7 +21,7 @@ import torch
 from . import rbp
 
 WAVES = (1, 2, 4, 8, 16)
-STATES = (1, 2)  # 1 = per-shot state in LDS, 2 = in device memory
+STATES = (1, 2, 3)  # 1 = per-edge state in LDS, 2 = the same in device memory, 3 = compact row records in LDS
 
 
 def cache_path() -> str:

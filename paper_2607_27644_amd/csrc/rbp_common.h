@@ -91,6 +91,7 @@ struct rbp_code {
     rbp::DevBuf rgrp, rposp, rposw;     // row groups {offset, degree, mixed, 0}; slot byte offsets (read, write)
     rbp::DevBuf rord;                   // check at each row position
     rbp::DevBuf vgrp, vord, vdeg;       // variable groups {first slot, degree, mixed, 0}, order, degrees
+    rbp::DevBuf vinv;                   // position of each variable
     rbp::DevBuf scheck, scsc;           // check and CSC edge of each slot
     rbp::DevBuf orow_ptr, ocol_idx;     // CSR of O: orow_ptr[k+1], ocol_idx[nnzO]
     rbp::DevBuf ocol_ptr, orow_idx;     // CSC of O (sampler)

@@ -330,7 +330,8 @@ struct DecodeModel {
     const float* m1pp;     // first-iteration magnitudes, layout of rposp
     const int32_t* rord;   // [64 GR] check at each row position, -1 for padding
     const int4* vgrp;      // [GV] {first slot, degree, mixed, 0}
-    const int32_t* vord;   // [Np] variable at each position, -1 for padding
+    const int32_t* vord;   // [Np] variable at each position, -1 for padding (positions N.. are padding)
+    const int32_t* vinv;   // [N] position of each variable
     const int32_t* vdeg;   // [Np] degree at each position (0 for padding)
     const int32_t* scheck; // [S] check of each slot (-1 unused)
     const int32_t* scsc;   // [S] CSC edge index of each slot (-1 unused)
@@ -357,6 +358,7 @@ struct DecodeLaunch {
     int32_t stats_by_row;  // statistics at the shot's row (rbp_decode) or at its ticket (rbp_decode_multi)
     uint64_t shots;
     const float* delta;
+    const uint16_t* delta16;  // BF16 proposal adjustments (rbp_decode_proposal), else null
     rbp_shot_stats* stats;
     unsigned long long* queue;
     float* gstate;
@@ -364,6 +366,7 @@ struct DecodeLaunch {
     int32_t Smax;  // device-memory state: marginals at X + Smax + 4
     // byte offsets in dynamic LDS (X itself starts at 0 when it lives there)
     int32_t off_M, off_sig, off_sigp, off_par, off_bestp, off_best, off_obs, off_misc;
+    int32_t off_d16;  // compact state with BF16 adjustments: their LDS copy by position
     float gamma0;
     int32_t T0, Tr, R, S, crit;
     int32_t trace_on, trace_phase, trace_leg, trace_t;
@@ -688,6 +691,12 @@ __device__ __forceinline__ void flip_slots(const int32_t* scheck, uint32_t sb, i
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// the proposal's adjustment of variable j: FP32, or BF16 widened exactly
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ float delta_of(const float* dlt, const uint16_t* dl16, int j) {
+    return dl16 ? bf16_to_f32(dl16[j]) : dlt[j];
+}
+
 constexpr int kQuarterRegs = 32;  // edges per lane kept in registers (rows up to 128)
 
 // the four lanes of a row exchange their two smallest magnitudes and sign
@@ -839,6 +848,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
             a.shot_index ? (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(a.shot_index[s]) : (uint64_t)s;
         const int N = m.N, WM = m.WM, WN = m.WN;
         const float* dlt = a.delta ? a.delta + row * (uint64_t)N : nullptr;
+        const uint16_t* dl16 = a.delta16 ? a.delta16 + row * (uint64_t)N : nullptr;
         if (tid == 0) X.st(4u * (uint32_t)m.S, INFINITY);  // read-only padding cell
         int pc = 0;
         for (int w = tid; w < WM; w += nth) {
@@ -873,7 +883,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                     sigp[2 * g + 1] = (uint32_t)(bb >> 32);
                 }
             }
-            const int first_phase = dlt ? 1 : 0;
+            const int first_phase = (dlt || dl16) ? 1 : 0;
             for (int phase = first_phase; phase >= 0; --phase) {
                 const bool prop = phase == 1;
                 if (phase == 0 && first_phase == 1) {
@@ -896,7 +906,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                         float x = l;
                         if (prop) {
                             const int j = ldg(m.vord, pp);
-                            x = j >= 0 ? l + dlt[j] : 0.0f;
+                            x = j >= 0 ? l + delta_of(dlt, dl16, j) : 0.0f;
                             const int vd = ldg(m.vdeg, pp);
                             const uint32_t sb = 4u * ((uint32_t)ldg(m.vgrp, pp >> 6).x + (uint32_t)(pp & 63));
                             for (int q = 0; q < vd; ++q) X.st(sb + 256u * q, x);
@@ -990,7 +1000,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                             float lt = l;
                             if (lp) {
                                 const int j = ldg(m.vord, pp);
-                                if (j >= 0) lt = l + dlt[j];
+                                if (j >= 0) lt = l + delta_of(dlt, dl16, j);
                             }
                             const float mo = Mg[pp];
                             float acc = __builtin_fmaf(gm, mo - lt, lt);
@@ -1329,6 +1339,10 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
             a.shot_index ? (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(a.shot_index[s]) : (uint64_t)s;
         const int N = m.N, WM = m.WM, WN = m.WN;
         const float* dlt = a.delta ? a.delta + row * (uint64_t)N : nullptr;
+        const uint16_t* dl16 = a.delta16 ? a.delta16 + row * (uint64_t)N : nullptr;
+        // BF16 adjustments are copied to LDS by position once per shot and read
+        // from there by every iteration of the proposal leg
+        uint16_t* dpos = dl16 ? reinterpret_cast<uint16_t*>(smem + a.off_d16) : nullptr;
         float* Mg = reinterpret_cast<float*>(smem + m.coff_M);
         if (tid == 0) Mg[-4] = INFINITY;  // the padding cell at 16 * 64 GR
         int pc = 0;
@@ -1362,7 +1376,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
                     sigp[2 * g + 1] = (uint32_t)(bb >> 32);
                 }
             }
-            const int first_phase = dlt ? 1 : 0;
+            const int first_phase = (dlt || dl16) ? 1 : 0;
             for (int phase = first_phase; phase >= 0; --phase) {
                 const bool prop = phase == 1;
                 __syncthreads();  // sigp complete; the previous phase's counters read
@@ -1372,27 +1386,44 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
                 }
                 for (int w = tid; w < 2 * m.GR; w += nth) par[w] = sigp[w];
                 __syncthreads();
+                if (prop && dpos) {
+                    // the shot's BF16 adjustments, read in variable order (coalesced,
+                    // independent loads) and placed in LDS by position; padding 0
+                    for (int j = tid; j < N; j += nth) dpos[ldg(m.vinv, j)] = dl16[j];
+                    for (int pp = N + tid; pp < m.Np; pp += nth) dpos[pp] = 0;
+                    __syncthreads();
+                }
                 {
-                    // M(0) = Lambda (or Lambda + delta, whose negative entries are the
-                    // starting hard decision)
-                    int dc = 0;
-                    double dW = 0.0;
+                    // M(0) = Lambda (or Lambda + delta), then the starting hard decision:
+                    // the (few) negative entries flip their checks.  Two passes, so that
+                    // the first one's loads are independent of each other.
+#pragma unroll 4
                     for (int pp = tid; pp < m.Np; pp += nth) {
                         const float l = ldg(m.lamp, pp);
                         float x = l;
                         if (prop) {
-                            const int j = ldg(m.vord, pp);
-                            x = j >= 0 ? l + dlt[j] : 0.0f;
-                            if (x < 0.0f) {
-                                const uint32_t slot = (uint32_t)ldg(m.vgrp, pp >> 6).x + (uint32_t)(pp & 63);
-                                compact_flip(m.vrec, slot, ldg(m.vdeg, pp), par, dc);
-                                dW += (double)l;
+                            if (dpos) {
+                                x = pp < N ? l + bf16_to_f32(dpos[pp]) : 0.0f;
+                            } else {
+                                const int j = ldg(m.vord, pp);
+                                x = j >= 0 ? l + dlt[j] : 0.0f;
                             }
                         }
                         Mg[pp] = x;
                     }
-                    if (dc) atomicAdd(&ms->count, dc);
-                    if (dW != 0.0) atomicAdd(&ms->W, dW);
+                    if (prop) {
+                        int dc = 0;
+                        double dW = 0.0;
+                        for (int pp = tid; pp < m.Np; pp += nth) {
+                            if (Mg[pp] < 0.0f) {
+                                const uint32_t slot = (uint32_t)ldg(m.vgrp, pp >> 6).x + (uint32_t)(pp & 63);
+                                compact_flip(m.vrec, slot, ldg(m.vdeg, pp), par, dc);
+                                dW += (double)ldg(m.lamp, pp);
+                            }
+                        }
+                        if (dc) atomicAdd(&ms->count, dc);
+                        if (dW != 0.0) atomicAdd(&ms->W, dW);
+                    }
                     __syncthreads();
                 }
 
@@ -1436,8 +1467,12 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
                             const float l = lgv.x, gm = lgv.y;
                             float lt = l;
                             if (lp) {
-                                const int j = ldg(m.vord, pp);
-                                if (j >= 0) lt = l + dlt[j];
+                                if (dpos) {
+                                    lt = l + bf16_to_f32(dpos[pp]);  // 0 at padding positions, whose Lambda is 0 too
+                                } else {
+                                    const int j = ldg(m.vord, pp);
+                                    if (j >= 0) lt = l + dlt[j];
+                                }
                             }
                             const float mo = Mg[pp];
                             float acc = __builtin_fmaf(gm, mo - lt, lt);
@@ -2101,6 +2136,7 @@ static DecodeModel model_of(const rbp_code* c, const uint32_t* syn, uint32_t* co
     m.rord = c->rord.as<int32_t>();
     m.vgrp = c->vgrp.as<int4>();
     m.vord = c->vord.as<int32_t>();
+    m.vinv = c->vinv.as<int32_t>();
     m.vdeg = c->vdeg.as<int32_t>();
     m.scheck = c->scheck.as<int32_t>();
     m.scsc = c->scsc.as<int32_t>();
@@ -2149,12 +2185,15 @@ struct LaunchShape {
     int64_t gstride = 0;
     int Smax = 0;
     int off_M = 0, off_sig = 0, off_sigp = 0, off_par = 0, off_bestp = 0, off_best = 0, off_obs = 0, off_misc = 0;
+    int off_d16 = 0;
 };
 
 static int align16(int64_t x) { return (int)((x + 15) & ~(int64_t)15); }
 
 // Launch shape for a set of models decoded together (max sizes over models).
-static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, LaunchShape* out) {
+// d16: the launch carries BF16 proposal adjustments (the compact state keeps a
+// copy of a shot's adjustments in LDS, 2 bytes per variable position)
+static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, LaunchShape* out, bool d16 = false) {
     int Smax = 0, Npmax = 0, GRmax = 0, WMmax = 0, WNmax = 0, WKmax = 1, rdmax = 0;
     for (int i = 0; i < n; ++i) {
         Smax = std::max(Smax, cs[i]->S);
@@ -2181,7 +2220,8 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
         compact_bytes = std::max<int64_t>(compact_bytes, (int64_t)cs[i]->coff_M + 4 * (int64_t)cs[i]->Np);
     }
     compact_bytes = align16(compact_bytes);
-    const bool compact_fits = compact_ok && compact_bytes + small <= kMaxLds;
+    const int64_t d16_bytes = d16 ? align16(2 * (int64_t)Npmax) : 0;
+    const bool compact_fits = compact_ok && compact_bytes + d16_bytes + small <= kMaxLds;
     bool lds = state_bytes + small <= kMaxLds;
     bool compact = false;
     if (cfg.state == 1 && !lds) return fail(RBP_ERR_UNSUPPORTED, "per-shot state does not fit in LDS");
@@ -2198,7 +2238,7 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
         if (lds) {
             // about 8 waves per SIMD (32 per CU) over the slots that fit in LDS, and
             // at least min(4, groups) waves so that a slow shot is not left to one wave
-            const int64_t per_slot = (compact ? compact_bytes : state_bytes) + small;
+            const int64_t per_slot = (compact ? compact_bytes + d16_bytes : state_bytes) + small;
             const int per_cu_lds = (int)std::max<int64_t>(kMaxLds / per_slot, 1);
             int groups = 0;
             for (int i = 0; i < n; ++i) groups = std::max(groups, std::max(cs[i]->GR, cs[i]->GV));
@@ -2239,6 +2279,8 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
     off += align16(4 * (int64_t)WKmax);
     L.off_misc = (int)off;
     off += align16(sizeof(SlotMisc));
+    L.off_d16 = (int)off;
+    if (compact) off += d16_bytes;
     if (off > kMaxLds) return fail(RBP_ERR_UNSUPPORTED, "per-shot bit arrays do not fit in LDS");
     L.lds_bytes = (int)off;
     L.gstride = lds ? 0 : ((int64_t)Smax + 4 + Npmax + 63) / 64 * 64;
@@ -2296,7 +2338,7 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
 static rbp_status launch_decode(rbp_code* const* cs, int n, DecodeLaunch& a, uint64_t shots, hipStream_t stream,
                                 unsigned long long* queue = nullptr) {
     LaunchShape L;
-    rbp_status st = plan_launch(cs, n, shots, &L);
+    rbp_status st = plan_launch(cs, n, shots, &L, a.delta16 != nullptr);
     if (st) return st;
     rbp_code* c0 = cs[0];
     if (queue) {
@@ -2324,6 +2366,7 @@ static rbp_status launch_decode(rbp_code* const* cs, int n, DecodeLaunch& a, uin
     a.off_best = L.off_best;
     a.off_obs = L.off_obs;
     a.off_misc = L.off_misc;
+    a.off_d16 = L.off_d16;
     a.shots = shots;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, stream, a.queue, 1);
     RBP_HIP_CHECK(hipGetLastError());
@@ -2627,6 +2670,7 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
     if (!st) st = upload(c->ocol_idx, oci);
     if (!st) st = upload(c->ocol_ptr, ocp);
     if (!st) st = upload(c->orow_idx, ori);
+    if (!st) st = upload(c->vinv, vinv);
     if (!st && compact_ok) st = upload(c->cvar, cvar);
     if (!st && compact_ok) st = upload(c->vrec, vrec);
     if (st) {
@@ -2644,7 +2688,7 @@ rbp_status rbp_code_destroy(rbp_code_t c) {
                       &c->vord, &c->vdeg, &c->scheck, &c->scsc, &c->orow_ptr, &c->ocol_idx, &c->ocol_ptr,
                       &c->orow_idx, &c->thr, &c->lam, &c->lamp, &c->m1, &c->gtab, &c->lg, &c->queue, &c->gstate,
                       &c->trace_hit, &c->spa_queue, &c->gapt, &c->order, &c->ohist, &c->coop, &c->cvar, &c->vrec,
-                      &c->r1rec})
+                      &c->r1rec, &c->vinv})
         b->release();
     delete c;
     return RBP_OK;
@@ -2739,6 +2783,34 @@ rbp_status rbp_decode(rbp_code_t c, const double* priors, const uint32_t* syndro
         a.shot_index = c->order.as<uint32_t>();
         a.stats_by_row = 1;
     }
+    rbp_code* cs[1] = {c};
+    return launch_decode(cs, 1, a, shots, stream);
+}
+
+rbp_status rbp_decode_proposal(rbp_code_t c, const double* priors, const uint32_t* syndromes, uint64_t shots,
+                               const rbp_relay_params* params, const uint16_t* delta_bf16, uint32_t* corrections,
+                               uint32_t* obs_pred, rbp_shot_stats* stats, void* stream_) {
+    if (!c) return fail(RBP_ERR_INVALID_ARG, "code is NULL");
+    rbp_status st = check_params(params);
+    if (st) return st;
+    if (shots == 0) return RBP_OK;
+    if (!syndromes || !corrections || !delta_bf16)
+        return fail(RBP_ERR_INVALID_ARG, "syndromes/corrections/delta is NULL");
+    if (c->k > 0 && !obs_pred) return fail(RBP_ERR_INVALID_ARG, "obs_pred is NULL");
+    st = check_priors(priors, c->N);
+    if (st) return st;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    st = ensure_llr(c, priors, stream);
+    if (!st) st = ensure_gamma(c, params, stream);
+    if (!st) st = ensure_lam_gamma(c, params, stream);
+    if (st) return st;
+    DecodeLaunch a;
+    std::memset(&a, 0, sizeof(a));
+    a.m[0] = model_of(c, syndromes, corrections, obs_pred);
+    a.n_models = 1;
+    a.delta16 = delta_bf16;
+    a.stats = stats;
+    fill_params(a, params);
     rbp_code* cs[1] = {c};
     return launch_decode(cs, 1, a, shots, stream);
 }

@@ -48,6 +48,7 @@ enum Epi {
     EPI_BIAS_F32 = 1,        // out_f32 = acc + bias[n]
     EPI_MASK_BF16_F32 = 2,   // v = acc * [mask[m][n] > 0]; out_bf16 = bf16(v), out_f32 = v
     EPI_F32 = 3,             // out_f32 = acc
+    EPI_BIAS_BF16 = 4,       // out_bf16 = bf16(acc + bias[n]) (round to nearest even)
 };
 
 struct GemmArgs {
@@ -228,6 +229,8 @@ __global__ void __launch_bounds__(256, TN == 2 ? kMinWaves64 : kMinWaves128) gem
                     g.out_bf16[o] = (bf16)fmaxf(v + g.bias[n], 0.0f);
                 } else if constexpr (EPI == EPI_BIAS_F32) {
                     g.out_f32[o] = v + g.bias[n];
+                } else if constexpr (EPI == EPI_BIAS_BF16) {
+                    g.out_bf16[o] = (bf16)(v + g.bias[n]);
                 } else if constexpr (EPI == EPI_MASK_BF16_F32) {
                     const float x = (float)g.mask[o] > 0.0f ? v : 0.0f;
                     g.out_bf16[o] = (bf16)x;
@@ -441,7 +444,8 @@ rbp_status colsum(rbp_mlp* p, const float* in, int B, int N, float* out, hipStre
 // forward of B rows: x from syndromes, h1, h2 (workspace), delta into `dout`.
 // Training keeps x as BF16 (the weight gradient of layer 1 needs it); inference
 // expands the syndrome bits while staging the first product's tiles.
-rbp_status forward(rbp_mlp* p, const uint32_t* syn, int B, float* dout, hipStream_t s, bool keep_x) {
+rbp_status forward(rbp_mlp* p, const uint32_t* syn, int B, float* dout, hipStream_t s, bool keep_x,
+                   bf16* dout16 = nullptr) {
     const int words = (p->in + 31) / 32;
     bf16* xb = p->xb.as<bf16>();
     bf16* h1 = p->h1.as<bf16>();
@@ -472,6 +476,10 @@ rbp_status forward(rbp_mlp* p, const uint32_t* syn, int B, float* dout, hipStrea
     if (st) return st;
     a = ga(B, p->out, p->hid, h2, p->hid, wb + p->oW3, p->hid, p->out);
     a.bias = w + p->ob3;
+    if (dout16) {
+        a.out_bf16 = dout16;
+        return gemm<K_CONTIG, K_CONTIG, EPI_BIAS_BF16, kFwdTN>(a, s);
+    }
     a.out_f32 = dout;
     return gemm<K_CONTIG, K_CONTIG, EPI_BIAS_F32, kFwdTN>(a, s);
 }
@@ -631,6 +639,25 @@ rbp_status rbp_mlp_forward(rbp_mlp_t p, const uint32_t* syndromes, uint64_t shot
     for (uint64_t b0 = 0; b0 < shots; b0 += chunk) {
         const int B = (int)std::min<uint64_t>(chunk, shots - b0);
         st = forward(p, syndromes + b0 * words, B, delta + b0 * (uint64_t)p->out, s, false);
+        if (st) return st;
+    }
+    return RBP_OK;
+}
+
+rbp_status rbp_mlp_forward_bf16(rbp_mlp_t p, const uint32_t* syndromes, uint64_t shots, uint16_t* delta,
+                                void* stream_) {
+    if (!p) return fail(RBP_ERR_INVALID_ARG, "mlp is NULL");
+    if (shots == 0) return RBP_OK;
+    if (!syndromes || !delta) return fail(RBP_ERR_INVALID_ARG, "NULL buffer");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
+    const int chunk = 65536;
+    rbp_status st = ensure_workspace(p, (int)std::min<uint64_t>(shots, chunk), false);
+    if (st) return st;
+    const int words = (p->in + 31) / 32;
+    for (uint64_t b0 = 0; b0 < shots; b0 += chunk) {
+        const int B = (int)std::min<uint64_t>(chunk, shots - b0);
+        st = forward(p, syndromes + b0 * words, B, nullptr, s, false,
+                     reinterpret_cast<bf16*>(delta) + b0 * (uint64_t)p->out);
         if (st) return st;
     }
     return RBP_OK;

@@ -89,9 +89,9 @@ def multi(names, shots_each: int, seed: int = 11, params: rbp.RelayParams | None
     st = torch.empty((total, 32), dtype=torch.uint8, device="cuda")
     res = {"models": [{"name": nm, "M": d.M, "N": d.N, "nnz": d.nnz, "k": d.k} for nm, d in zip(names, dems)],
            "shots_each": shots_each, "one_launch": {}, "per_model_launches": {}}
-    # one launch, every launch shape
-    for waves in (4, 8, 16):
-        for state in (1, 2):
+    # one launch, every launch shape (0 = the library's choice)
+    for waves in (0, 4, 8, 16):
+        for state in (0, 1, 3):
             try:
                 codes[0].set_launch_config(waves, state, 0)
                 ms, _ = _timed(lambda: rbp.decode_multi(codes, [d.priors for d in dems], shot_code, shot_index,

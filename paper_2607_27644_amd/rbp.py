@@ -139,6 +139,8 @@ def lib():
         "rbp_decode": [vp, vp, vp, u64, P(RelayParamsC), vp, vp, vp, vp, vp],
         "rbp_decode_multi": [i32, vp, vp, vp, vp, u64, vp, P(RelayParamsC), vp, vp, vp, vp],
         "rbp_decode_noalloc": [vp, vp, vp, u64, P(RelayParamsC), vp, vp, vp, vp, vp],
+        "rbp_decode_proposal": [vp, vp, vp, u64, P(RelayParamsC), vp, vp, vp, vp, vp],
+        "rbp_mlp_forward_bf16": [vp, vp, u64, vp, vp],
         "rbp_set_launch_config": [vp, P(LaunchConfigC)],
         "rbp_get_launch_config": [vp, P(LaunchConfigC), P(i32), P(i32)],
         "rbp_trace": [vp, vp, vp, P(RelayParamsC), vp, i32, i32, i32, vp, vp, P(i32), vp],
@@ -312,6 +314,21 @@ class Code:
         prm = params.c()
         check(lib().rbp_decode(self.h, pr.ctypes.data, _ptr(syndromes), shots, ctypes.byref(prm), _ptr(delta),
                                _ptr(corr), _ptr(obsp), _ptr(st), _stream(stream)))
+        return corr, obsp, st
+
+    def decode_proposal(self, priors, syndromes: torch.Tensor, params: RelayParams, delta_bf16: torch.Tensor,
+                        stats: bool = True, stream=None, out=None):
+        """rbp_decode_proposal: the learned-proposal decode with BF16 adjustments
+        (torch.bfloat16 [shots][N], e.g. from MLP.forward_bf16)."""
+        _need(syndromes, "syndromes", torch.int32)
+        shots = syndromes.shape[0]
+        _need(syndromes, "syndromes", torch.int32, (shots, words(self.M)))
+        _need(delta_bf16, "delta_bf16", torch.bfloat16, (shots, self.N))
+        corr, obsp, st = self._outputs(shots, syndromes.device, stats, out)
+        pr = self._priors(priors)
+        prm = params.c()
+        check(lib().rbp_decode_proposal(self.h, pr.ctypes.data, _ptr(syndromes), shots, ctypes.byref(prm),
+                                        _ptr(delta_bf16), _ptr(corr), _ptr(obsp), _ptr(st), _stream(stream)))
         return corr, obsp, st
 
     def decode_noalloc(self, priors, syndromes: torch.Tensor, params: RelayParams,
@@ -583,6 +600,17 @@ class MLP:
             out = torch.empty((shots, self.out_dim), dtype=torch.float32, device=syndromes.device)
         _need(out, "out", torch.float32, (shots, self.out_dim))
         check(lib().rbp_mlp_forward(self.h, _ptr(syndromes), shots, _ptr(out), _stream(stream)))
+        return out
+
+    def forward_bf16(self, syndromes: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """The forward pass with BF16 output (rbp_mlp_forward_bf16): torch.bfloat16 [shots][out_dim]."""
+        _need(syndromes, "syndromes", torch.int32)
+        shots = syndromes.shape[0]
+        _need(syndromes, "syndromes", torch.int32, (shots, words(self.in_dim)))
+        if out is None:
+            out = torch.empty((shots, self.out_dim), dtype=torch.bfloat16, device=syndromes.device)
+        _need(out, "out", torch.bfloat16, (shots, self.out_dim))
+        check(lib().rbp_mlp_forward_bf16(self.h, _ptr(syndromes), shots, _ptr(out), _stream(stream)))
         return out
 
     def train_step(self, syndromes: torch.Tensor, targets: torch.Tensor, llr: torch.Tensor, lr: float,
