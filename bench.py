@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--no-sequential", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-first-solution", action="store_true")
     ap.add_argument("--train-pairs", type=int, default=1_000_000)
     ap.add_argument("--hidden", type=int, default=128, help="width of the proposal network's hidden layers")
     ap.add_argument("--delta-scale", type=float, default=0.5, help="shrinkage of the network's output")
@@ -253,8 +254,9 @@ def main():
     }
     paths = {}
     fs = rbp.RelayParams(stop_nconv=1)
-    paths["first_solution"] = timed("plain", fs)
-    paths["first_solution"]["note"] = "Relay-BP with stop_nconv = 1: the proposal path's stop rule, no proposal"
+    if not args.no_first_solution:
+        paths["first_solution"] = timed("plain", fs)
+        paths["first_solution"]["note"] = "Relay-BP with stop_nconv = 1: the proposal path's stop rule, no proposal"
 
     if not args.no_learned:
         from paper_2607_27644_amd import learned
@@ -284,7 +286,8 @@ def main():
                          "delta_scale": cfg.delta_scale, "generate_s": t1 - t0, "train_s": t2 - t1,
                          "final_loss": hist[-1][1]}
         L["vs_proposal_zero"] = L["value"] / paths["proposal_zero"]["value"]
-        L["vs_first_solution"] = L["value"] / paths["first_solution"]["value"]
+        if "first_solution" in paths:
+            L["vs_first_solution"] = L["value"] / paths["first_solution"]["value"]
         L["vs_plain"] = L["value"] / P["value"]
         paths["proposal_zero"]["note"] = "control: the same proposal leg with delta = 0 (no network)"
         L["note"] = ("network -> BF16 adjustments (rbp_mlp_forward_bf16) -> proposal leg with the adjustments "
