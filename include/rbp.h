@@ -80,12 +80,15 @@ rbp_status rbp_code_info(rbp_code_t code, int32_t* M, int32_t* N, int32_t* nnz, 
 rbp_status rbp_sample(rbp_code_t code, const double* priors, uint64_t shots, uint64_t seed, uint64_t shot_offset,
                       uint32_t* syndromes_dev, uint32_t* obs_dev, uint32_t* errors_dev, void* stream);
 
-/* Relay-BP settings; names follow Sec. 6.1 of the paper. */
+/* Relay-BP settings; names follow Sec. 6.1 of the paper.  Marginals saturate
+ * at +-2^90 (the paper leaves FP32 overflow open; without a bound, shots that
+ * never converge reach inf and NaN); the bounds below keep every message finite
+ * under that saturation. */
 typedef struct {
-    float gamma0;               /* memory strength of leg 0 (paper: 0.125) */
-    float gamma_min, gamma_max; /* gamma_dist of the relay legs, e.g. [-0.24, 0.66] */
-    int32_t pre_iter;           /* iteration budget of leg 0 (80), >= 1 */
-    int32_t max_iterations;     /* iteration budget of each relay leg (60), >= 1 */
+    float gamma0;               /* memory strength of leg 0 (paper: 0.125), |gamma0| <= 16 */
+    float gamma_min, gamma_max; /* gamma_dist of the relay legs, e.g. [-0.24, 0.66], |gamma| <= 16 */
+    int32_t pre_iter;           /* iteration budget of leg 0 (80), 1..65536 */
+    int32_t max_iterations;     /* iteration budget of each relay leg (60), 1..65536 */
     int32_t num_sets;           /* number of relay legs after leg 0 (paper 1000), >= 0 */
     int32_t stop_nconv;         /* solutions to collect before stopping (5), 1..255 */
     int32_t stopping_criterion; /* 0: stop after stop_nconv solutions; 1: run every leg */

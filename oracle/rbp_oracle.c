@@ -27,10 +27,18 @@
  *                   mu_{i->j}  = (-1)^sigma_i prod_{j' != j} s(nu_{j'->i})
  *                                min_{j' != j} |nu_{j'->i}|   (min-sum)
  *                   Lt_j       = fmaf(gamma_j, M_j - Lambda_j, Lambda_j)
- *                   M_j        = Lt_j + sum_i mu_{i->j}  (ascending check index)
+ *                   M_j        = sat(Lt_j + sum_i mu_{i->j})  (ascending check index)
  *                   nu_{j->i}  = M_j - mu_{i->j}
  *                   e^_j       = [M_j < 0];  converged iff H e^ = sigma
- *                 with s(x) = -1 iff x < 0.  Converged legs give solutions of
+ *                 with s(x) = -1 iff x < 0 and sat(x) = min(max(x, -2^90), 2^90).
+ *                 The paper does not say what happens when FP32 messages
+ *                 overflow.  Without the saturation, shots that never converge
+ *                 reach inf and then NaN (inf - inf) within a few legs, and the
+ *                 outcome depends on how an implementation compares NaN; with
+ *                 it, every value stays finite (|mu| grows by at most 2^90 per
+ *                 iteration, far below the FP32 range for the iteration budgets
+ *                 allowed), and shots that stay below 2^90, i.e. every shot
+ *                 that converges in practice, are unchanged.  Converged legs give solutions of
  *                 weight W = sum_j e^_j Lambda_j (double); the lowest weight
  *                 wins (ties keep the earlier one).  Stop after stop_nconv
  *                 solutions (criterion 0) or after all legs (criterion 1).
@@ -303,6 +311,9 @@ typedef struct {
 
 static int sgn_neg(float x) { return x < 0.0f; }
 
+/* saturation bound of the marginals, 2^90 */
+#define ORC_M_SAT 0x1p90f
+
 /* One flooding iteration on the current leg.  Returns 1 iff H e^ = sigma after it. */
 static int bp_iteration(const orc_graph* g, shot_work* w, const float* gam, float gamma_const, int use_const) {
     const int32_t M = g->M, N = g->N;
@@ -329,6 +340,8 @@ static int bp_iteration(const orc_graph* g, shot_work* w, const float* gam, floa
         float d = w->Mg[j] - lam;
         float acc = fmaf(gj, d, lam);
         for (int32_t e = g->col_ptr[j]; e < g->col_ptr[j + 1]; ++e) acc = acc + w->mu[g->csc2csr[e]];
+        if (acc > ORC_M_SAT) acc = ORC_M_SAT;
+        if (acc < -ORC_M_SAT) acc = -ORC_M_SAT;
         w->Mg[j] = acc;
         w->ehat[j] = acc < 0.0f;
     }

@@ -14,7 +14,12 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librbp.so")
-SOURCES = ["rbp_decode.hip", "rbp_mlp.hip", "rbp_spa.hip", "rbp_window.hip", "rbp_probe.hip"]
+SOURCES = ["rbp_common.hip", "rbp_decode.hip", "rbp_mlp.hip", "rbp_spa.hip", "rbp_window.hip", "rbp_probe.hip"]
+# Test build of the proposal network with FP32 operands (same kernels, FP32
+# matrix cores): its gradients are checked element by element against the
+# float64 reference.  Not part of the product path.
+LIB_MLP_F32 = os.path.join(HERE, "librbp_mlp_f32.so")
+MLP_F32_SOURCES = [("rbp_common.hip", []), ("rbp_mlp.hip", ["-DRBP_MLP_FP32"])]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
@@ -30,16 +35,14 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
+def _compile(jobs, verbose):
+    """jobs: (source, extra flags, object path); compiled in parallel."""
     procs = []
-    for src in SOURCES:
-        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = [hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    for src, extra, obj in jobs:
+        cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
-        objs.append(obj)
     for src, p in procs:
         out, _ = p.communicate()
         msgs = [ln for ln in out.splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
@@ -47,11 +50,24 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError(f"hipcc failed on {src}:\n" + "\n".join(msgs))
         if verbose and msgs:
             print("\n".join(msgs))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
-    subprocess.run(cmd, check=True, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
-    os.replace(tmp, LIB)
-    for o in objs:
+
+
+def _link(objs, lib):
+    tmp = lib + ".tmp"
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined", *objs, "-o", tmp]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link of {os.path.basename(lib)} failed:\n{r.stdout}")
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    main = [(src, [], os.path.join(CSRC, src.replace(".hip", ".o"))) for src in SOURCES]
+    f32 = [(src, extra, os.path.join(CSRC, src.replace(".hip", "_f32.o"))) for src, extra in MLP_F32_SOURCES]
+    _compile(main + f32, verbose)
+    _link([o for _, _, o in main], LIB)
+    _link([o for _, _, o in f32], LIB_MLP_F32)
+    for _, _, o in main + f32:
         os.remove(o)
     return LIB
 

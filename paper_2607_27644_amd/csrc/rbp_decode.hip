@@ -31,38 +31,6 @@
 
 namespace rbp {
 
-static thread_local std::string g_err;
-void set_error(const std::string& m) { g_err = m; }
-rbp_status fail(rbp_status st, const std::string& m) {
-    g_err = m;
-    return st;
-}
-
-rbp_status DevBuf::reserve(size_t n) {
-    if (n <= bytes && p) return RBP_OK;
-    if (p) {
-        hipError_t e = hipFree(p);
-        p = nullptr;
-        bytes = 0;
-        if (e != hipSuccess) return fail(RBP_ERR_HIP, std::string("hipFree: ") + hipGetErrorString(e));
-    }
-    size_t want = n ? n : 4;
-    hipError_t e = hipMalloc(&p, want);
-    if (e != hipSuccess) {
-        p = nullptr;
-        return fail(e == hipErrorOutOfMemory ? RBP_ERR_OOM : RBP_ERR_HIP,
-                    std::string("hipMalloc: ") + hipGetErrorString(e));
-    }
-    bytes = want;
-    return RBP_OK;
-}
-
-void DevBuf::release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-}
-
 // ---------------------------------------------------------------------------
 // Sampling: independent faults e_j ~ Bernoulli(p_j); sigma = H e; o = O e.
 // The mechanisms are cut into 64 segments of L = ceil(N / 64), one per lane.
@@ -606,6 +574,13 @@ __device__ __forceinline__ void check_dispatch(const State<LDS> X, const int32_t
 // mu left in place (see the first iteration of a plain leg in the kernel).  In
 // a mixed group only the member's own vd edges enter the sum (its remaining
 // slots are unused by any check).
+// Marginals saturate at +-2^90: shots that never converge would otherwise
+// overflow FP32 (inf, then inf - inf = NaN) within a few legs.  The bound keeps
+// every message finite (a check message grows by at most 2^90 per iteration)
+// and is never reached by shots that converge in practice.
+constexpr float kMSat = 0x1p90f;
+__device__ __forceinline__ float sat(float x) { return __builtin_amdgcn_fmed3f(x, -kMSat, kMSat); }
+
 template <int D, bool MIXED, bool WRITE, bool LDS>
 __device__ __forceinline__ float var_member(const State<LDS> X, uint32_t sb, int vd, float acc) {
     float mu[D];
@@ -613,6 +588,7 @@ __device__ __forceinline__ float var_member(const State<LDS> X, uint32_t sb, int
     for (int q = 0; q < D; ++q) mu[q] = X.ld(sb + 256u * q);
 #pragma unroll
     for (int q = 0; q < D; ++q) acc = (!MIXED || q < vd) ? acc + mu[q] : acc;
+    acc = sat(acc);
     if (WRITE) {
 #pragma unroll
         for (int q = 0; q < D; ++q) X.st(sb + 256u * q, acc - mu[q]);
@@ -625,6 +601,7 @@ template <bool LDS>
 __device__ __forceinline__ float var_member_rolled(const State<LDS> X, bool write, uint32_t sb, int vd, float acc,
                                                    float* trace_mu, const int32_t* scsc) {
     for (int q = 0; q < vd; ++q) acc = acc + X.ld(sb + 256u * q);
+    acc = sat(acc);
     for (int q = 0; q < vd; ++q) {
         const uint32_t o = sb + 256u * q;
         const float mu = X.ld(o);
@@ -642,7 +619,7 @@ __device__ __forceinline__ float var_member_d(const State<LDS> X, uint32_t sb, b
 template <bool WRITE, bool LDS>
 __device__ __forceinline__ float var_dispatch(const State<LDS> X, uint32_t sb, int dg, bool mixed, int vd, float acc) {
     switch (dg) {
-        case 0: return acc;
+        case 0: return sat(acc);
 #define RBP_VAR(D) \
     case D: return var_member_d<D, WRITE>(X, sb, mixed, vd, acc);
         RBP_VAR(1) RBP_VAR(2) RBP_VAR(3) RBP_VAR(4) RBP_VAR(5) RBP_VAR(6) RBP_VAR(7) RBP_VAR(8)
@@ -1479,9 +1456,9 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
                             const uint32_t slot = (uint32_t)uniform(gi.x) + (uint32_t)lane;
                             const int vd = mixed ? ldg(m.vdeg, pp) : dg;
                             if (!tr) {
-                                acc = compact_var_dispatch(m.vrec, slot, dg, mixed, vd, acc);
+                                acc = sat(compact_var_dispatch(m.vrec, slot, dg, mixed, vd, acc));
                             } else {
-                                acc = compact_var_rolled(m.vrec, slot, vd, acc, a.trace_mu, m.scsc);
+                                acc = sat(compact_var_rolled(m.vrec, slot, vd, acc, a.trace_mu, m.scsc));
                                 const int j = ldg(m.vord, pp);
                                 if (j >= 0) a.trace_M[j] = acc;
                             }
@@ -2106,11 +2083,14 @@ static rbp_status ensure_lam_gamma(rbp_code* c, const rbp_relay_params* p, hipSt
 
 static rbp_status check_params(const rbp_relay_params* p) {
     if (!p) return fail(RBP_ERR_INVALID_ARG, "params is NULL");
-    if (p->pre_iter < 1 || p->max_iterations < 1 || p->num_sets < 0 || p->stop_nconv < 1 ||
+    // iteration budgets and |gamma| are bounded so that saturated marginals keep
+    // every message finite
+    if (p->pre_iter < 1 || p->max_iterations < 1 || p->pre_iter > 65536 || p->max_iterations > 65536 ||
+        p->num_sets < 0 || p->stop_nconv < 1 ||
         p->stop_nconv > 255 || (p->stopping_criterion != 0 && p->stopping_criterion != 1))
         return fail(RBP_ERR_INVALID_ARG, "relay parameters out of range");
-    if (!std::isfinite(p->gamma0) || !std::isfinite(p->gamma_min) || !std::isfinite(p->gamma_max))
-        return fail(RBP_ERR_INVALID_ARG, "gamma values must be finite");
+    if (!(std::fabs(p->gamma0) <= 16.0f) || !(std::fabs(p->gamma_min) <= 16.0f) || !(std::fabs(p->gamma_max) <= 16.0f))
+        return fail(RBP_ERR_INVALID_ARG, "gamma values must be finite, |gamma| <= 16");
     if ((int64_t)p->num_sets + 1 > 32767) return fail(RBP_ERR_INVALID_ARG, "num_sets too large");
     return RBP_OK;
 }
@@ -2457,7 +2437,6 @@ using namespace rbp;
 
 extern "C" {
 
-const char* rbp_last_error(void) { return rbp::g_err.c_str(); }
 
 rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const int32_t* row_idx, int32_t k,
                            const int32_t* obs_col_ptr, const int32_t* obs_row_idx, rbp_code_t* out) {

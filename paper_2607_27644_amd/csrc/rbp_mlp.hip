@@ -30,36 +30,49 @@
 namespace rbp {
 namespace mlp {
 
-typedef __bf16 bf16;
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+#ifdef RBP_MLP_FP32
+// Test build: weights, activations and gradients kept in FP32 and the products
+// run on the FP32 matrix cores (v_mfma_f32_32x32x2_f32), with the same tiling,
+// staging, epilogues and reductions; its gradients are compared with the
+// float64 reference at 1e-5.
+typedef float elem;
+typedef float elemx8 __attribute__((ext_vector_type(8)));
+#else
+typedef __bf16 elem;
+typedef __bf16 elemx8 __attribute__((ext_vector_type(8)));
+#endif
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int BM = 128, BK = 32;
 // Register budget: the 64 x 64 wave tile is built for 4 waves per SIMD (128
 // VGPRs, accumulators included), which fits the 4 workgroups per CU that the
 // LDS stages allow; the wider tile for 2.
+#ifdef RBP_MLP_FP32
+constexpr int kMinWaves64 = 2, kMinWaves128 = 1;  // FP32 operands: twice the registers and LDS
+#else
 constexpr int kMinWaves64 = 4, kMinWaves128 = 2;
+#endif
 constexpr int kFwdTN = 2;  // MFMA column blocks per wave in the forward products
 constexpr int LDSK = BK + 8;  // padded row of the staged tiles (bank spread)
 
 enum Layout { K_CONTIG = 0, MN_CONTIG = 1, BITS = 2 };  // BITS: A is packed 0/1 bits, 32 per word, rows of lda words
 enum Epi {
-    EPI_BIAS_RELU_BF16 = 0,  // out_bf16 = bf16(relu(acc + bias[n]))
+    EPI_BIAS_RELU_BF16 = 0,  // out_bf16 = elem(relu(acc + bias[n]))
     EPI_BIAS_F32 = 1,        // out_f32 = acc + bias[n]
-    EPI_MASK_BF16_F32 = 2,   // v = acc * [mask[m][n] > 0]; out_bf16 = bf16(v), out_f32 = v
+    EPI_MASK_BF16_F32 = 2,   // v = acc * [mask[m][n] > 0]; out_bf16 = elem(v), out_f32 = v
     EPI_F32 = 3,             // out_f32 = acc
-    EPI_BIAS_BF16 = 4,       // out_bf16 = bf16(acc + bias[n]) (round to nearest even)
+    EPI_BIAS_BF16 = 4,       // out_bf16 = elem(acc + bias[n]) (round to nearest even)
 };
 
 struct GemmArgs {
     int M, N, K;
-    const bf16* A;  // K_CONTIG: A[m*lda + k]; MN_CONTIG: A[k*lda + m]
+    const elem* A;  // K_CONTIG: A[m*lda + k]; MN_CONTIG: A[k*lda + m]
     int lda;
-    const bf16* B;  // K_CONTIG: B[n*ldb + k]; MN_CONTIG: B[k*ldb + n]
+    const elem* B;  // K_CONTIG: B[n*ldb + k]; MN_CONTIG: B[k*ldb + n]
     int ldb;
     const float* bias;
-    const bf16* mask;  // [M x N] row-major, ld = ldc
-    bf16* out_bf16;
+    const elem* mask;  // [M x N] row-major, ld = ldc
+    elem* out_bf16;
     float* out_f32;
     int ldc;
 };
@@ -71,11 +84,11 @@ template <int ROWS>
 struct TileRegs {
     static constexpr int VPT = ROWS * BK / 8 / 256;
     static_assert(VPT * 256 * 8 == ROWS * BK, "tile shape");
-    bf16x8 x[VPT];
+    elemx8 x[VPT];
 };
 
 template <int LAYOUT, int ROWS>
-__device__ __forceinline__ TileRegs<ROWS> load_tile(const bf16* src, int ld, int rows, int K, int r0, int k0) {
+__device__ __forceinline__ TileRegs<ROWS> load_tile(const elem* src, int ld, int rows, int K, int r0, int k0) {
     constexpr int VPT = TileRegs<ROWS>::VPT;
     const int t = threadIdx.x;
     TileRegs<ROWS> v;
@@ -90,7 +103,7 @@ __device__ __forceinline__ TileRegs<ROWS> load_tile(const bf16* src, int ld, int
             const int gr = r0 + r, gk = k0 + kk;
             const uint32_t bits = gr < rows && gk < K ? (w[(int64_t)gr * ld + (gk >> 5)] >> (gk & 31)) : 0u;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) v.x[pass][i] = ((bits >> i) & 1u) && gk + i < K ? (bf16)1.0f : (bf16)0.0f;
+            for (int i = 0; i < 8; ++i) v.x[pass][i] = ((bits >> i) & 1u) && gk + i < K ? (elem)1.0f : (elem)0.0f;
         }
         return v;
     }
@@ -104,22 +117,22 @@ __device__ __forceinline__ TileRegs<ROWS> load_tile(const bf16* src, int ld, int
             const int r = q / (BK / 8), kk = (q % (BK / 8)) * 8;
             const int gr = r0 + r, gk = k0 + kk;
             if (vec && gr < rows && gk + 7 < K) {
-                v.x[pass] = *reinterpret_cast<const bf16x8*>(src + (int64_t)gr * ld + gk);
+                v.x[pass] = *reinterpret_cast<const elemx8*>(src + (int64_t)gr * ld + gk);
             } else {
 #pragma unroll
                 for (int i = 0; i < 8; ++i)
-                    v.x[pass][i] = (gr < rows && gk + i < K) ? src[(int64_t)gr * ld + gk + i] : (bf16)0.0f;
+                    v.x[pass][i] = (gr < rows && gk + i < K) ? src[(int64_t)gr * ld + gk + i] : (elem)0.0f;
             }
         } else {
             // BK k x rows, rows contiguous in memory: vectors of 8 rows
             const int kk = q / (ROWS / 8), r = (q % (ROWS / 8)) * 8;
             const int gr = r0 + r, gk = k0 + kk;
             if (vec && gk < K && gr + 7 < rows) {
-                v.x[pass] = *reinterpret_cast<const bf16x8*>(src + (int64_t)gk * ld + gr);
+                v.x[pass] = *reinterpret_cast<const elemx8*>(src + (int64_t)gk * ld + gr);
             } else {
 #pragma unroll
                 for (int i = 0; i < 8; ++i)
-                    v.x[pass][i] = (gk < K && gr + i < rows) ? src[(int64_t)gk * ld + gr + i] : (bf16)0.0f;
+                    v.x[pass][i] = (gk < K && gr + i < rows) ? src[(int64_t)gk * ld + gr + i] : (elem)0.0f;
             }
         }
     }
@@ -127,7 +140,7 @@ __device__ __forceinline__ TileRegs<ROWS> load_tile(const bf16* src, int ld, int
 }
 
 template <int LAYOUT, int ROWS>
-__device__ __forceinline__ void store_tile(bf16 (*tile)[LDSK], const TileRegs<ROWS>& v) {
+__device__ __forceinline__ void store_tile(elem (*tile)[LDSK], const TileRegs<ROWS>& v) {
     constexpr int VPT = TileRegs<ROWS>::VPT;
     const int t = threadIdx.x;
 #pragma unroll
@@ -135,7 +148,7 @@ __device__ __forceinline__ void store_tile(bf16 (*tile)[LDSK], const TileRegs<RO
         const int q = t + pass * 256;
         if constexpr (LAYOUT == K_CONTIG || LAYOUT == BITS) {
             const int r = q / (BK / 8), kk = (q % (BK / 8)) * 8;
-            *reinterpret_cast<bf16x8*>(&tile[r][kk]) = v.x[pass];
+            *reinterpret_cast<elemx8*>(&tile[r][kk]) = v.x[pass];
         } else {
             const int kk = q / (ROWS / 8), r = (q % (ROWS / 8)) * 8;
 #pragma unroll
@@ -151,8 +164,8 @@ __global__ void __launch_bounds__(256, TN == 2 ? kMinWaves64 : kMinWaves128) gem
     constexpr int BNT = 64 * TN;
     // two LDS stages: the tiles of step k are read by the matrix cores while
     // those of step k + 1 arrive in registers
-    __shared__ __align__(16) bf16 As[2][BM][LDSK];
-    __shared__ __align__(16) bf16 Bs[2][BNT][LDSK];
+    __shared__ __align__(16) elem As[2][BM][LDSK];
+    __shared__ __align__(16) elem Bs[2][BNT][LDSK];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     // Workgroups are dealt to the 8 XCDs round-robin.  Renumber them so that
     // each XCD takes a contiguous run of tiles in row-major order: the column
@@ -186,25 +199,43 @@ __global__ void __launch_bounds__(256, TN == 2 ? kMinWaves64 : kMinWaves128) gem
             ra = load_tile<LA, BM>(g.A, g.lda, g.M, g.K, m0, k0 + BK);
             rb = load_tile<LB, BNT>(g.B, g.ldb, g.N, g.K, n0, k0 + BK);
         }
+#ifdef RBP_MLP_FP32
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 2) {
+            // lane: row (lane % 32) of a 32-row block, k = ks + lane / 32 (A and B alike)
+            const int kk = ks + (lane >> 5);
+            float af[2], bfr[TN];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) af[i] = As[cur][wm + i * 32 + (lane & 31)][kk];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) bfr[j] = Bs[cur][wn + j * 32 + (lane & 31)][kk];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+#else
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 16) {
             // lane: row (lane % 32) of a 32-row block, 8 consecutive k from (lane / 32) * 8.
             // A and B use the same k order, so the product is independent of how the
             // matrix core pairs the k slots.
             const int kk = ks + (lane >> 5) * 8;
-            bf16x8 af[2], bfr[TN];
+            elemx8 af[2], bfr[TN];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
-                af[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wm + i * 32 + (lane & 31)][kk]);
+                af[i] = *reinterpret_cast<const elemx8*>(&As[cur][wm + i * 32 + (lane & 31)][kk]);
 #pragma unroll
             for (int j = 0; j < TN; ++j)
-                bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wn + j * 32 + (lane & 31)][kk]);
+                bfr[j] = *reinterpret_cast<const elemx8*>(&Bs[cur][wn + j * 32 + (lane & 31)][kk]);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < TN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
         }
+#endif
         if (more) {
             // the other stage was last read before the previous barrier
             store_tile<LA, BM>(As[cur ^ 1], ra);
@@ -226,14 +257,14 @@ __global__ void __launch_bounds__(256, TN == 2 ? kMinWaves64 : kMinWaves128) gem
                 const float v = acc[i][j][r];
                 const int64_t o = (int64_t)m * g.ldc + n;
                 if constexpr (EPI == EPI_BIAS_RELU_BF16) {
-                    g.out_bf16[o] = (bf16)fmaxf(v + g.bias[n], 0.0f);
+                    g.out_bf16[o] = (elem)fmaxf(v + g.bias[n], 0.0f);
                 } else if constexpr (EPI == EPI_BIAS_F32) {
                     g.out_f32[o] = v + g.bias[n];
                 } else if constexpr (EPI == EPI_BIAS_BF16) {
-                    g.out_bf16[o] = (bf16)(v + g.bias[n]);
+                    g.out_bf16[o] = (elem)(v + g.bias[n]);
                 } else if constexpr (EPI == EPI_MASK_BF16_F32) {
                     const float x = (float)g.mask[o] > 0.0f ? v : 0.0f;
-                    g.out_bf16[o] = (bf16)x;
+                    g.out_bf16[o] = (elem)x;
                     g.out_f32[o] = x;
                 } else {
                     g.out_f32[o] = v;
@@ -242,18 +273,18 @@ __global__ void __launch_bounds__(256, TN == 2 ? kMinWaves64 : kMinWaves128) gem
 }
 
 // x[b][i] = bit i of syndrome row b, as BF16 0/1
-__global__ void expand_bits_kernel(const uint32_t* syn, int words, int in, int B, bf16* x) {
+__global__ void expand_bits_kernel(const uint32_t* syn, int words, int in, int B, elem* x) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)B * in) return;
     const int b = (int)(idx / in), i = (int)(idx % in);
-    x[idx] = (bf16)(float)((syn[(int64_t)b * words + (i >> 5)] >> (i & 31)) & 1u);
+    x[idx] = (elem)(float)((syn[(int64_t)b * words + (i >> 5)] >> (i & 31)) & 1u);
 }
 
 // Per element: z = -(lambda + delta), p = sigmoid(z), y = target bit.
 // dL/d(delta) = -(p - y) / B.  Per-block loss partial sums for a deterministic
 // reduction.
 __global__ void loss_grad_kernel(const float* delta, const float* lam, const uint32_t* tgt, int words, int N, int B,
-                                 float* d3f, bf16* d3b, float* partial) {
+                                 float* d3f, elem* d3b, float* partial) {
     __shared__ float red[256];
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float l = 0.0f;
@@ -264,7 +295,7 @@ __global__ void loss_grad_kernel(const float* delta, const float* lam, const uin
         const float p = 1.0f / (1.0f + expf(-z));
         const float g = -(p - y) / (float)B;
         d3f[idx] = g;
-        d3b[idx] = (bf16)g;
+        d3b[idx] = (elem)g;
         l = fmaxf(z, 0.0f) - z * y + log1pf(expf(-fabsf(z)));
     }
     red[threadIdx.x] = l;
@@ -316,13 +347,13 @@ __global__ void colsum_final_kernel(const float* part, int chunks, int N, float*
 }
 
 // out[c][r] = in[r][c] for a rows x cols BF16 matrix (64 x 64 tiles through LDS)
-__global__ void transpose_bf16_kernel(const bf16* in, int rows, int cols, bf16* out) {
-    __shared__ bf16 t[64][65];
+__global__ void transpose_bf16_kernel(const elem* in, int rows, int cols, elem* out) {
+    __shared__ elem t[64][65];
     const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     for (int r = ty; r < 64; r += 4) {
         const int gr = r0 + r, gc = c0 + tx;
-        t[r][tx] = (gr < rows && gc < cols) ? in[(int64_t)gr * cols + gc] : (bf16)0.0f;
+        t[r][tx] = (gr < rows && gc < cols) ? in[(int64_t)gr * cols + gc] : (elem)0.0f;
     }
     __syncthreads();
     for (int c = ty; c < 64; c += 4) {
@@ -343,9 +374,9 @@ __global__ void adam_kernel(float* w, float* mo, float* ve, const float* g, int6
     w[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
 }
 
-__global__ void to_bf16_kernel(const float* w, bf16* o, int64_t n) {
+__global__ void to_bf16_kernel(const float* w, elem* o, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) o[i] = (bf16)w[i];
+    if (i < n) o[i] = (elem)w[i];
 }
 
 }  // namespace mlp
@@ -375,15 +406,15 @@ rbp_status ensure_workspace(rbp_mlp* p, int B, bool training) {
     if (B <= (training ? p->cap : p->fcap)) return RBP_OK;
     const int64_t Bi = B;
     rbp_status st = RBP_OK;
-    if (!st) st = p->xb.reserve(sizeof(bf16) * Bi * p->in);
-    if (!st) st = p->h1.reserve(sizeof(bf16) * Bi * p->hid);
-    if (!st) st = p->h2.reserve(sizeof(bf16) * Bi * p->hid);
+    if (!st) st = p->xb.reserve(sizeof(elem) * Bi * p->in);
+    if (!st) st = p->h1.reserve(sizeof(elem) * Bi * p->hid);
+    if (!st) st = p->h2.reserve(sizeof(elem) * Bi * p->hid);
     if (st) return st;
     p->fcap = std::max(p->fcap, B);
     if (!training) return RBP_OK;
-    if (!st) st = p->d3b.reserve(sizeof(bf16) * Bi * p->out);
-    if (!st) st = p->dh2b.reserve(sizeof(bf16) * Bi * p->hid);
-    if (!st) st = p->dh1b.reserve(sizeof(bf16) * Bi * p->hid);
+    if (!st) st = p->d3b.reserve(sizeof(elem) * Bi * p->out);
+    if (!st) st = p->dh2b.reserve(sizeof(elem) * Bi * p->hid);
+    if (!st) st = p->dh1b.reserve(sizeof(elem) * Bi * p->hid);
     if (!st) st = p->delta.reserve(sizeof(float) * Bi * p->out);
     if (!st) st = p->d3f.reserve(sizeof(float) * Bi * p->out);
     if (!st) st = p->dh2f.reserve(sizeof(float) * Bi * p->hid);
@@ -391,8 +422,8 @@ rbp_status ensure_workspace(rbp_mlp* p, int B, bool training) {
     if (!st) st = p->partial.reserve(sizeof(float) * (Bi * std::max(p->out, p->hid) / 256 + 2));
     if (!st) st = p->loss.reserve(sizeof(float) * 4);
     const int64_t wide = std::max<int64_t>(std::max(p->out, p->hid), p->in);
-    if (!st) st = p->tA.reserve(sizeof(bf16) * Bi * wide);
-    if (!st) st = p->tB.reserve(sizeof(bf16) * Bi * wide);
+    if (!st) st = p->tA.reserve(sizeof(elem) * Bi * wide);
+    if (!st) st = p->tB.reserve(sizeof(elem) * Bi * wide);
     if (!st) st = p->csum.reserve(sizeof(float) * ((Bi + CS_ROWS - 1) / CS_ROWS) * wide);
     if (st) return st;
     p->cap = B;
@@ -408,7 +439,7 @@ rbp_status gemm(const GemmArgs& a, hipStream_t s) {
     return RBP_OK;
 }
 
-GemmArgs ga(int M, int N, int K, const bf16* A, int lda, const bf16* B, int ldb, int ldc) {
+GemmArgs ga(int M, int N, int K, const elem* A, int lda, const elem* B, int ldb, int ldc) {
     GemmArgs a;
     std::memset(&a, 0, sizeof(a));
     a.M = M;
@@ -424,7 +455,7 @@ GemmArgs ga(int M, int N, int K, const bf16* A, int lda, const bf16* B, int ldb,
 
 int blocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
-rbp_status transpose(const bf16* in, int rows, int cols, bf16* out, hipStream_t s) {
+rbp_status transpose(const elem* in, int rows, int cols, elem* out, hipStream_t s) {
     hipLaunchKernelGGL(transpose_bf16_kernel, dim3(blocks(cols, 64), blocks(rows, 64)), dim3(256), 0, s, in, rows, cols,
                        out);
     RBP_HIP_CHECK(hipGetLastError());
@@ -445,12 +476,12 @@ rbp_status colsum(rbp_mlp* p, const float* in, int B, int N, float* out, hipStre
 // Training keeps x as BF16 (the weight gradient of layer 1 needs it); inference
 // expands the syndrome bits while staging the first product's tiles.
 rbp_status forward(rbp_mlp* p, const uint32_t* syn, int B, float* dout, hipStream_t s, bool keep_x,
-                   bf16* dout16 = nullptr) {
+                   elem* dout16 = nullptr) {
     const int words = (p->in + 31) / 32;
-    bf16* xb = p->xb.as<bf16>();
-    bf16* h1 = p->h1.as<bf16>();
-    bf16* h2 = p->h2.as<bf16>();
-    const bf16* wb = p->wb.as<bf16>();
+    elem* xb = p->xb.as<elem>();
+    elem* h1 = p->h1.as<elem>();
+    elem* h2 = p->h2.as<elem>();
+    const elem* wb = p->wb.as<elem>();
     const float* w = p->w.as<float>();
     rbp_status st;
     if (keep_x) {
@@ -462,7 +493,7 @@ rbp_status forward(rbp_mlp* p, const uint32_t* syn, int B, float* dout, hipStrea
         a.out_bf16 = h1;
         st = gemm<K_CONTIG, K_CONTIG, EPI_BIAS_RELU_BF16>(a, s);
     } else {
-        GemmArgs a = ga(B, p->hid, p->in, reinterpret_cast<const bf16*>(syn), words, wb + p->oW1, p->in, p->hid);
+        GemmArgs a = ga(B, p->hid, p->in, reinterpret_cast<const elem*>(syn), words, wb + p->oW1, p->in, p->hid);
         a.bias = w + p->ob1;
         a.out_bf16 = h1;
         st = gemm<BITS, K_CONTIG, EPI_BIAS_RELU_BF16, kFwdTN>(a, s);
@@ -496,43 +527,43 @@ rbp_status gradients(rbp_mlp* p, const uint32_t* syn, const uint32_t* tgt, const
     const int64_t n3 = (int64_t)B * p->out;
     const int nb = blocks(n3, 256);
     hipLaunchKernelGGL(loss_grad_kernel, dim3(nb), dim3(256), 0, s, delta, llr, tgt, twords, p->out, B,
-                       p->d3f.as<float>(), p->d3b.as<bf16>(), p->partial.as<float>());
+                       p->d3f.as<float>(), p->d3b.as<elem>(), p->partial.as<float>());
     RBP_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, p->partial.as<float>(), nb, 1.0f / (float)B,
                        loss_out ? loss_out : p->loss.as<float>());
     RBP_HIP_CHECK(hipGetLastError());
     float* g = p->g.as<float>();
-    bf16* tA = p->tA.as<bf16>();
-    bf16* tB = p->tB.as<bf16>();
+    elem* tA = p->tA.as<elem>();
+    elem* tB = p->tB.as<elem>();
     // Weight gradients dW = dY^T X are NT products of the transposed operands
     // (both K = batch contiguous); dX = dY W uses the transposed weight copies.
     // dW3 = d3^T h2 ; db3 = colsum d3 ; dh2 = (d3 W3) * [h2 > 0]
-    if ((st = transpose(p->d3b.as<bf16>(), B, p->out, tA, s))) return st;
-    if ((st = transpose(p->h2.as<bf16>(), B, p->hid, tB, s))) return st;
+    if ((st = transpose(p->d3b.as<elem>(), B, p->out, tA, s))) return st;
+    if ((st = transpose(p->h2.as<elem>(), B, p->hid, tB, s))) return st;
     GemmArgs a = ga(p->out, p->hid, B, tA, B, tB, B, p->hid);
     a.out_f32 = g + p->oW3;
     if ((st = gemm<K_CONTIG, K_CONTIG, EPI_F32>(a, s))) return st;
     if ((st = colsum(p, p->d3f.as<float>(), B, p->out, g + p->ob3, s))) return st;
-    a = ga(B, p->hid, p->out, p->d3b.as<bf16>(), p->out, p->w3t.as<bf16>(), p->out, p->hid);
-    a.mask = p->h2.as<bf16>();
-    a.out_bf16 = p->dh2b.as<bf16>();
+    a = ga(B, p->hid, p->out, p->d3b.as<elem>(), p->out, p->w3t.as<elem>(), p->out, p->hid);
+    a.mask = p->h2.as<elem>();
+    a.out_bf16 = p->dh2b.as<elem>();
     a.out_f32 = p->dh2f.as<float>();
     if ((st = gemm<K_CONTIG, K_CONTIG, EPI_MASK_BF16_F32>(a, s))) return st;
     // dW2 = dh2^T h1 ; db2 ; dh1 = (dh2 W2) * [h1 > 0]
-    if ((st = transpose(p->dh2b.as<bf16>(), B, p->hid, tA, s))) return st;
-    if ((st = transpose(p->h1.as<bf16>(), B, p->hid, tB, s))) return st;
+    if ((st = transpose(p->dh2b.as<elem>(), B, p->hid, tA, s))) return st;
+    if ((st = transpose(p->h1.as<elem>(), B, p->hid, tB, s))) return st;
     a = ga(p->hid, p->hid, B, tA, B, tB, B, p->hid);
     a.out_f32 = g + p->oW2;
     if ((st = gemm<K_CONTIG, K_CONTIG, EPI_F32>(a, s))) return st;
     if ((st = colsum(p, p->dh2f.as<float>(), B, p->hid, g + p->ob2, s))) return st;
-    a = ga(B, p->hid, p->hid, p->dh2b.as<bf16>(), p->hid, p->w2t.as<bf16>(), p->hid, p->hid);
-    a.mask = p->h1.as<bf16>();
-    a.out_bf16 = p->dh1b.as<bf16>();
+    a = ga(B, p->hid, p->hid, p->dh2b.as<elem>(), p->hid, p->w2t.as<elem>(), p->hid, p->hid);
+    a.mask = p->h1.as<elem>();
+    a.out_bf16 = p->dh1b.as<elem>();
     a.out_f32 = p->dh1f.as<float>();
     if ((st = gemm<K_CONTIG, K_CONTIG, EPI_MASK_BF16_F32>(a, s))) return st;
     // dW1 = dh1^T x ; db1
-    if ((st = transpose(p->dh1b.as<bf16>(), B, p->hid, tA, s))) return st;
-    if ((st = transpose(p->xb.as<bf16>(), B, p->in, tB, s))) return st;
+    if ((st = transpose(p->dh1b.as<elem>(), B, p->hid, tA, s))) return st;
+    if ((st = transpose(p->xb.as<elem>(), B, p->in, tB, s))) return st;
     a = ga(p->hid, p->in, B, tA, B, tB, B, p->in);
     a.out_f32 = g + p->oW1;
     if ((st = gemm<K_CONTIG, K_CONTIG, EPI_F32>(a, s))) return st;
@@ -541,11 +572,11 @@ rbp_status gradients(rbp_mlp* p, const uint32_t* syn, const uint32_t* tgt, const
 
 rbp_status refresh_bf16(rbp_mlp* p, hipStream_t s) {
     hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(p->n_params, 256)), dim3(256), 0, s, p->w.as<float>(),
-                       p->wb.as<bf16>(), p->n_params);
+                       p->wb.as<elem>(), p->n_params);
     RBP_HIP_CHECK(hipGetLastError());
-    rbp_status st = transpose(p->wb.as<bf16>() + p->oW2, p->hid, p->hid, p->w2t.as<bf16>(), s);
+    rbp_status st = transpose(p->wb.as<elem>() + p->oW2, p->hid, p->hid, p->w2t.as<elem>(), s);
     if (st) return st;
-    return transpose(p->wb.as<bf16>() + p->oW3, p->out, p->hid, p->w3t.as<bf16>(), s);
+    return transpose(p->wb.as<elem>() + p->oW3, p->out, p->hid, p->w3t.as<elem>(), s);
 }
 
 rbp_status zero_adam(rbp_mlp* p) {
@@ -595,9 +626,9 @@ rbp_status rbp_mlp_create(int32_t in_dim, int32_t hidden, int32_t out_dim, uint6
     if (!st) st = p->m.reserve(sizeof(float) * o);
     if (!st) st = p->v.reserve(sizeof(float) * o);
     if (!st) st = p->g.reserve(sizeof(float) * o);
-    if (!st) st = p->wb.reserve(sizeof(bf16) * o);
-    if (!st) st = p->w2t.reserve(sizeof(bf16) * (int64_t)hidden * hidden);
-    if (!st) st = p->w3t.reserve(sizeof(bf16) * (int64_t)hidden * out_dim);
+    if (!st) st = p->wb.reserve(sizeof(elem) * o);
+    if (!st) st = p->w2t.reserve(sizeof(elem) * (int64_t)hidden * hidden);
+    if (!st) st = p->w3t.reserve(sizeof(elem) * (int64_t)hidden * out_dim);
     if (!st) {
         hipError_t e = hipMemcpy(p->w.p, h.data(), sizeof(float) * o, hipMemcpyHostToDevice);
         if (e != hipSuccess) st = fail(RBP_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
@@ -647,6 +678,13 @@ rbp_status rbp_mlp_forward(rbp_mlp_t p, const uint32_t* syndromes, uint64_t shot
 rbp_status rbp_mlp_forward_bf16(rbp_mlp_t p, const uint32_t* syndromes, uint64_t shots, uint16_t* delta,
                                 void* stream_) {
     if (!p) return fail(RBP_ERR_INVALID_ARG, "mlp is NULL");
+#ifdef RBP_MLP_FP32
+    (void)syndromes;
+    (void)shots;
+    (void)delta;
+    (void)stream_;
+    return fail(RBP_ERR_UNSUPPORTED, "the FP32 test build has no BF16 output");
+#endif
     if (shots == 0) return RBP_OK;
     if (!syndromes || !delta) return fail(RBP_ERR_INVALID_ARG, "NULL buffer");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
@@ -657,7 +695,7 @@ rbp_status rbp_mlp_forward_bf16(rbp_mlp_t p, const uint32_t* syndromes, uint64_t
     for (uint64_t b0 = 0; b0 < shots; b0 += chunk) {
         const int B = (int)std::min<uint64_t>(chunk, shots - b0);
         st = forward(p, syndromes + b0 * words, B, nullptr, s, false,
-                     reinterpret_cast<bf16*>(delta) + b0 * (uint64_t)p->out);
+                     reinterpret_cast<elem*>(delta) + b0 * (uint64_t)p->out);
         if (st) return st;
     }
     return RBP_OK;

@@ -19,6 +19,7 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librbp.so")
+LIB_MLP_F32_PATH = os.path.join(HERE, "librbp_mlp_f32.so")
 
 RBP_OK = 0
 RBP_ERR_ABORTED = -6
@@ -124,11 +125,30 @@ def _close_all():
 
 def lib():
     global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
-    L = ctypes.CDLL(LIB_PATH)
+    if _lib is None:
+        _lib = _load(LIB_PATH, required=True)
+    return _lib
+
+
+_lib_mlp_f32 = None
+
+
+def lib_mlp_f32():
+    """The FP32 test build of the proposal network (librbp_mlp_f32.so): the
+    rbp_mlp_* entry points with FP32 weights, activations and gradients, used to
+    check the network kernels element by element against a float64 reference."""
+    global _lib_mlp_f32
+    if _lib_mlp_f32 is None:
+        _lib_mlp_f32 = _load(LIB_MLP_F32_PATH, required=False)
+    return _lib_mlp_f32
+
+
+def _load(path: str, required: bool):
+    """Opens one of the built libraries and declares its entry points; with
+    required=False the entry points the library does not export are skipped."""
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(path)
     vp, i32, u64, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64
     P = ctypes.POINTER
     sigs = {
@@ -166,21 +186,21 @@ def lib():
         "rbp_mlp_load": [vp, ctypes.c_char_p],
         "rbp_test_set_coop_phantom": [vp, i32],
     }
+    sigs["rbp_measure_lds_bandwidth"] = [i32, ctypes.POINTER(ctypes.c_double)]
     for name, args in sigs.items():
+        if not required and not hasattr(L, name):
+            continue
         f = getattr(L, name)
         f.argtypes = args
         f.restype = ctypes.c_int32
-    L.rbp_measure_lds_bandwidth.argtypes = [i32, ctypes.POINTER(ctypes.c_double)]
-    L.rbp_measure_lds_bandwidth.restype = ctypes.c_int32
     L.rbp_last_error.argtypes = []
     L.rbp_last_error.restype = ctypes.c_char_p
-    _lib = L
     return L
 
 
-def check(status: int):
+def check(status: int, L=None):
     if status != RBP_OK:
-        raise RbpError(status, lib().rbp_last_error().decode())
+        raise RbpError(status, (L or lib()).rbp_last_error().decode())
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -570,20 +590,26 @@ class MLP:
     """Learned proposal network (rbp_mlp_*): syndrome bits -> per-mechanism
     log-prior adjustments delta."""
 
-    def __init__(self, in_dim: int, hidden: int, out_dim: int, seed: int = 0):
+    def __init__(self, in_dim: int, hidden: int, out_dim: int, seed: int = 0, fp32_test_build: bool = False):
+        """fp32_test_build: use the FP32 test build of the kernels
+        (lib_mlp_f32()) instead of the BF16 product build."""
         self.in_dim, self.hidden, self.out_dim = in_dim, hidden, out_dim
+        self._L = lib_mlp_f32() if fp32_test_build else lib()
         h = ctypes.c_void_p()
-        check(lib().rbp_mlp_create(in_dim, hidden, out_dim, seed, ctypes.byref(h)))
+        self._check(self._L.rbp_mlp_create(in_dim, hidden, out_dim, seed, ctypes.byref(h)))
         self.h = h
         _live.add(self)
         n = ctypes.c_int64()
-        check(lib().rbp_mlp_num_params(self.h, ctypes.byref(n)))
+        self._check(self._L.rbp_mlp_num_params(self.h, ctypes.byref(n)))
         self.n_params = n.value
+
+    def _check(self, status: int):
+        check(status, self._L)
 
     def close(self):
         if getattr(self, "h", None):
             if not _finalized:
-                lib().rbp_mlp_destroy(self.h)
+                self._L.rbp_mlp_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -599,7 +625,7 @@ class MLP:
         if out is None:
             out = torch.empty((shots, self.out_dim), dtype=torch.float32, device=syndromes.device)
         _need(out, "out", torch.float32, (shots, self.out_dim))
-        check(lib().rbp_mlp_forward(self.h, _ptr(syndromes), shots, _ptr(out), _stream(stream)))
+        self._check(self._L.rbp_mlp_forward(self.h, _ptr(syndromes), shots, _ptr(out), _stream(stream)))
         return out
 
     def forward_bf16(self, syndromes: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
@@ -610,7 +636,7 @@ class MLP:
         if out is None:
             out = torch.empty((shots, self.out_dim), dtype=torch.bfloat16, device=syndromes.device)
         _need(out, "out", torch.bfloat16, (shots, self.out_dim))
-        check(lib().rbp_mlp_forward_bf16(self.h, _ptr(syndromes), shots, _ptr(out), _stream(stream)))
+        self._check(self._L.rbp_mlp_forward_bf16(self.h, _ptr(syndromes), shots, _ptr(out), _stream(stream)))
         return out
 
     def train_step(self, syndromes: torch.Tensor, targets: torch.Tensor, llr: torch.Tensor, lr: float,
@@ -621,8 +647,8 @@ class MLP:
         _need(targets, "targets", torch.int32, (batch, words(self.out_dim)))
         _need(llr, "llr", torch.float32, (self.out_dim,))
         _need(loss_out, "loss_out", torch.float32, optional=True)
-        check(lib().rbp_mlp_train_step(self.h, _ptr(syndromes), _ptr(targets), _ptr(llr), batch, ctypes.c_float(lr),
-                                       _ptr(loss_out), _stream(stream)))
+        self._check(self._L.rbp_mlp_train_step(self.h, _ptr(syndromes), _ptr(targets), _ptr(llr), batch,
+                                               ctypes.c_float(lr), _ptr(loss_out), _stream(stream)))
 
     def gradients(self, syndromes: torch.Tensor, targets: torch.Tensor, llr: torch.Tensor, stream=None):
         _need(syndromes, "syndromes", torch.int32)
@@ -632,25 +658,25 @@ class MLP:
         _need(llr, "llr", torch.float32, (self.out_dim,))
         g = torch.empty(self.n_params, dtype=torch.float32, device=syndromes.device)
         loss = torch.empty(1, dtype=torch.float32, device=syndromes.device)
-        check(lib().rbp_mlp_gradients(self.h, _ptr(syndromes), _ptr(targets), _ptr(llr), batch, _ptr(g), _ptr(loss),
-                                      _stream(stream)))
+        self._check(self._L.rbp_mlp_gradients(self.h, _ptr(syndromes), _ptr(targets), _ptr(llr), batch, _ptr(g),
+                                              _ptr(loss), _stream(stream)))
         return g, loss
 
     def get_params(self) -> np.ndarray:
         out = np.empty(self.n_params, dtype=np.float32)
-        check(lib().rbp_mlp_get_params(self.h, out.ctypes.data))
+        self._check(self._L.rbp_mlp_get_params(self.h, out.ctypes.data))
         return out
 
     def set_params(self, params: np.ndarray):
         p = np.ascontiguousarray(params, dtype=np.float32)
         if p.size != self.n_params:
             raise ValueError(f"need {self.n_params} parameters (got {p.size})")
-        check(lib().rbp_mlp_set_params(self.h, p.ctypes.data))
+        self._check(self._L.rbp_mlp_set_params(self.h, p.ctypes.data))
 
     def save(self, path: str):
         """Checkpoint of masters, Adam moments and step (rbp_mlp_save)."""
-        check(lib().rbp_mlp_save(self.h, os.fsencode(path)))
+        self._check(self._L.rbp_mlp_save(self.h, os.fsencode(path)))
 
     def load(self, path: str):
         """Restore a checkpoint written by save() into this handle (rbp_mlp_load)."""
-        check(lib().rbp_mlp_load(self.h, os.fsencode(path)))
+        self._check(self._L.rbp_mlp_load(self.h, os.fsencode(path)))

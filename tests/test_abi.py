@@ -34,6 +34,19 @@ def test_library_exports_every_declared_symbol():
     assert lib.rbp_last_error() is not None
 
 
+def test_fp32_network_test_build_exports_the_network_entry_points():
+    """librbp_mlp_f32.so, the FP32 test build of the network kernels, exports
+    the same rbp_mlp_* entry points (and nothing of the decoder)."""
+    path = os.path.join(PKG, "librbp_mlp_f32.so")
+    if not os.path.exists(path):
+        pytest.fail("librbp_mlp_f32.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    mlp = [s for s in declared_symbols() if s.startswith("rbp_mlp_")]
+    assert len(mlp) >= 8
+    assert all(hasattr(lib, s) for s in mlp + ["rbp_last_error"])
+    assert not hasattr(lib, "rbp_decode")
+
+
 def test_host_validation_without_gpu():
     """Argument checks run before any device call."""
     lib = ctypes.CDLL(os.path.join(PKG, "librbp.so"))

@@ -241,15 +241,16 @@ def test_phen840_full_size_against_oracle(rbp):
 
 def test_compact_multi_model_launch(rbp):
     """One compact launch over the four phenomenological candidates
-    (ZSZ-LP-160/320/550/775, 9 rounds) equals the single-model decodes, and one
-    shot in 20 of every model matches the oracle."""
+    (ZSZ-LP-160/320/550/775, 9 rounds) equals the single-model decodes, and
+    1000 shots of every model (one in four) decode as the oracle does on at
+    least 99.9% of them."""
     names = ["phen160", "phen320", "phen550", "phen775"]
     dems = [dem_of(n) for n in names]
     codes = [rbp.Code.from_dem(d) for d in dems]
     for c in codes:
         c.set_launch_config(0, COMPACT, 0)
     params = rbp.RelayParams()
-    per = 2000
+    per = 4000
     syns, singles = [], []
     for i, (d, c) in enumerate(zip(dems, codes)):
         syn, _, _ = c.sample(d.priors, per, seed=300 + i)
@@ -269,7 +270,7 @@ def test_compact_multi_model_launch(rbp):
         assert np.array_equal(u32(corrs[i]), u32(singles[i][0])), names[i]
         assert np.array_equal(u32(obsps[i]), u32(singles[i][1])), names[i]
         assert np.array_equal(stats["iters"][i::n], rbp.stats_to_numpy(singles[i][2])["iters"])
-        idx = np.arange(0, per, 20)
+        idx = np.arange(0, per, 4)
         ref = oracle.decode(oracle.Graph(dems[i].H, dems[i].O), dems[i].priors, u32(syns[i])[idx], oparams(params),
                             nthreads=16)
-        assert (u32(corrs[i])[idx] == ref["corrections"]).all(axis=1).mean() >= 0.99
+        assert (u32(corrs[i])[idx] == ref["corrections"]).all(axis=1).mean() >= 0.999, names[i]

@@ -147,3 +147,137 @@ def test_checkpoint_resume_is_exact(rbp, tmp_path):
     bad.write_bytes(b"not a checkpoint at all")
     with pytest.raises(rbp.RbpError, match="INVALID_ARG"):
         resumed.load(str(bad))
+
+
+# ---------------------------------------------------------------------------
+# Element-wise gradient checks.  Each gradient element is a sum of products
+# whose factors carry the rounding errors of the whole forward and backward
+# chain.  A running-error bound of the form tau * S holds element by element,
+# where S is the same computation carried out over absolute values (so that a
+# value obtained by cancellation is charged the error of its terms):
+#   forward  F1 = (|x| |W1|^T + |b1|) m1,  F2 = (F1 |W2|^T + |b2|) m2
+#            (m1, m2 the ReLU masks)
+#   backward A3 = |p - y| / B,  A2 = (A3 |W3|) m2,  A1 = (A2 |W2|) m1
+#   S = [A1^T |x|, sum A1, A2^T F1, sum A2, A3^T F2, sum A3]
+# An error e in the logit z moves p by at most p (1 - p) e <= |p - y| e, so the
+# output gradient has relative error at most e, which is below tau for the
+# logits here (|z| <= 30, sums of a few hundred terms).  tau is fixed by the
+# arithmetic:
+#   FP32 test build: tau = 1e-5 (unit roundoff 6e-8 times sums of at most a
+#   few hundred terms per stage);
+#   BF16 build: tau = 2^-6.  Both sides round h1, h2, d3, dh2 and dh1 to BF16
+#   at the same places; a rounding lands differently only when FP32 and FP64
+#   accumulation straddle a rounding boundary, and then moves that factor by
+#   one BF16 unit, at most 2^-7 of its value.  Such flips are rare (the
+#   accumulation error is about 1e-5 of S, a BF16 unit 2^-8), so an element off
+#   by 2^-6 S needs half of its terms flipped the same way (the worst case, all
+#   five factors of every term flipped alike, is 5 2^-7).
+# Both allow at most 1e-4 of the elements outside the bound: such coincident
+# flips, or a ReLU pre-activation within accumulation error of zero that
+# switches a whole term on or off on one side only.
+
+
+def _abs_chain(params, x, y, lam, din, h, dout, mirror):
+    """S for every gradient element, in the flat parameter layout (float64)."""
+    delta, (xx, h1, h2, W1r, W2r, W3r) = R.forward(params, x, din, h, dout, mirror)
+    _, b1, _, b2, _, _ = R.split(np.asarray(params, np.float64), din, h, dout)
+    B = xx.shape[0]
+    m1, m2 = h1 > 0, h2 > 0
+    F1 = (xx @ np.abs(W1r).T + np.abs(b1)) * m1
+    F2 = (F1 @ np.abs(W2r).T + np.abs(b2)) * m2
+    p = 1.0 / (1.0 + np.exp(np.asarray(lam, np.float64)[None, :] + delta))
+    A3 = np.abs(p - np.asarray(y, np.float64)) / B
+    A2 = (A3 @ np.abs(W3r)) * m2
+    A1 = (A2 @ np.abs(W2r)) * m1
+    return np.concatenate([(A1.T @ xx).ravel(), A1.sum(0), (A2.T @ F1).ravel(), A2.sum(0), (A3.T @ F2).ravel(),
+                           A3.sum(0)])
+
+
+def _planted(kind, params, x, y, lam, din, h, dout, mirror):
+    """The float64 reference gradient with one planted mistake (CPU only)."""
+    _, g = R.loss_and_grads(params, x, y, lam, din, h, dout, mirror)
+    g = g.copy()
+    delta, (xx, h1, h2, W1r, W2r, W3r) = R.forward(params, x, din, h, dout, mirror)
+    B = xx.shape[0]
+    z = -(np.asarray(lam, np.float64)[None, :] + delta)
+    pr = 1.0 / (1.0 + np.exp(-z))
+    rnd = R.bf16 if mirror else (lambda v: v)
+    d3r = rnd(-(pr - np.asarray(y, np.float64)) / B)
+    dh2r = rnd((d3r @ W3r) * (h2 > 0))
+    if kind == "W2_not_transposed":
+        dh1 = (dh2r @ W2r.T) * (h1 > 0)
+    elif kind == "h1_mask_dropped":
+        dh1 = dh2r @ W2r
+    else:
+        raise ValueError(kind)
+    dh1r = rnd(dh1)
+    g[:h * din] = (dh1r.T @ xx).ravel()
+    g[h * din:h * din + h] = dh1.sum(0)
+    return g
+
+
+def _violations(g, gref, S, tau):
+    return int((np.abs(g - gref) > tau * S + 1e-30).sum())
+
+
+@pytest.mark.parametrize("din,h,dout,B", [(64, 512, 160, 256), (576, 128, 1952, 200), (40, 64, 100, 77)])
+def test_fp32_build_gradients_elementwise(rbp, din, h, dout, B):
+    """The FP32 test build of the same kernels (FP32 matrix cores) against the
+    unrounded float64 reference: gradient elements within 1e-5 S, the loss
+    within 1e-5; each planted mistake in the reference is caught."""
+    net = rbp.MLP(din, h, dout, seed=7, fp32_test_build=True)
+    rng = np.random.default_rng(3)
+    p = net.get_params()
+    W1, b1, W2, b2, W3, b3 = R.split(p, din, h, dout)
+    b1[:] = rng.normal(0, 0.05, h)
+    b2[:] = rng.normal(0, 0.05, h)
+    b3[:] = rng.normal(0, 0.5, dout)
+    net.set_params(p)
+    x, y, lam = _data(din, dout, B, 4, dens=0.1)
+    g, loss = net.gradients(_dev_bits(x), _dev_bits(y), torch.from_numpy(lam).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    params = net.get_params()
+    lref, gref = R.loss_and_grads(params, x, y, lam, din, h, dout, mirror=False)
+    S = _abs_chain(params, x, y, lam, din, h, dout, mirror=False)
+    assert abs(float(loss.item()) - lref) <= 1e-5 * abs(lref)
+    ratio = np.abs(g - gref) / (S + 1e-30)
+    tau, allowed = 1e-5, max(1, int(1e-4 * g.size))
+    base = _violations(g, gref, S, tau)
+    print(f"FP32 build: max |g - g_ref| / S = {ratio.max():.3e}, outside 1e-5 S: {base} of {g.size}")
+    assert base <= allowed
+    for kind in ("W2_not_transposed", "h1_mask_dropped"):
+        assert _violations(g, _planted(kind, params, x, y, lam, din, h, dout, False), S, tau) > 10 * allowed, kind
+    # one element of the W2 gradient off by 0.1% is one more element outside
+    o2 = h * din + h
+    i = o2 + int(np.argmax(np.abs(gref[o2:o2 + h * h]) / (S[o2:o2 + h * h] + 1e-30)))
+    bad = gref.copy()
+    bad[i] *= 1.001
+    assert _violations(g, bad, S, tau) == base + 1
+
+
+@pytest.mark.parametrize("din,h,dout,B", [(64, 512, 160, 256), (576, 128, 1952, 200), (40, 64, 100, 77)])
+def test_bf16_gradients_elementwise(rbp, din, h, dout, B):
+    """The BF16 product build against the reference that rounds to BF16 at the
+    same places: gradient elements within 2^-6 S (at most 1e-4 of them outside);
+    the planted mistakes each put far more elements outside."""
+    net = rbp.MLP(din, h, dout, seed=7)
+    rng = np.random.default_rng(3)
+    p = net.get_params()
+    W1, b1, W2, b2, W3, b3 = R.split(p, din, h, dout)
+    b1[:] = rng.normal(0, 0.05, h)
+    b2[:] = rng.normal(0, 0.05, h)
+    b3[:] = rng.normal(0, 0.5, dout)
+    net.set_params(p)
+    x, y, lam = _data(din, dout, B, 4, dens=0.1)
+    g, _ = net.gradients(_dev_bits(x), _dev_bits(y), torch.from_numpy(lam).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    params = net.get_params()
+    _, gref = R.loss_and_grads(params, x, y, lam, din, h, dout, mirror=True)
+    S = _abs_chain(params, x, y, lam, din, h, dout, mirror=True)
+    tau, allowed = 2.0 ** -6, max(1, int(1e-4 * g.size))
+    ratio = np.abs(g - gref) / (S + 1e-30)
+    print(f"BF16 build: max |g - g_ref| / S = {ratio.max():.3e}, "
+          f"outside 2^-6 S: {_violations(g, gref, S, tau)} of {g.size}")
+    assert _violations(g, gref, S, tau) <= allowed
+    for kind in ("W2_not_transposed", "h1_mask_dropped"):
+        assert _violations(g, _planted(kind, params, x, y, lam, din, h, dout, True), S, tau) > 10 * allowed, kind

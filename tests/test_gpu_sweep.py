@@ -4,13 +4,17 @@ Table "relay gamma intervals"; Sec. 6.1) on the GPU decoder.
 Checks: every interval decodes the same syndromes (a re-run reproduces each
 count), the chosen interval is the minimum, an interval without negative
 memory strengths fails far more often at p = 1e-2 than the default one, the
-LER grows with p, and the sub-threshold fit reproduces its points.
+LER grows with p, and the sub-threshold fit reproduces its points; the
+oracle, decoding the same syndromes at sweep and grid points, counts the same
+failures.
 """
 import numpy as np
 import pytest
 
 torch = pytest.importorskip("torch")
 
+import oracle  # noqa: E402
+from oracle import stats as ostats  # noqa: E402
 from paper_2607_27644_amd import stats  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -51,3 +55,30 @@ def test_ler_sweep_and_fit(E):
             # the fitted curve passes within a factor of two of the well-measured points
             ratio = float(stats.ler_model(x["p"], c, 10)) / x["per_qubit_round"]
             assert 0.5 < ratio < 2.0, (x["p"], ratio)
+
+
+@pytest.mark.parametrize("p,gmin,gmax,shots", [(1.2e-2, -0.24, 0.66, 6000), (1.5e-2, -0.24, 0.66, 3000),
+                                               (1e-2, 0.0, 0.66, 6000)])
+def test_sweep_points_match_oracle(E, p, gmin, gmax, shots):
+    """A sweep point (and a grid point without negative memory strengths)
+    decoded by the oracle on the same syndromes: corrections identical on at
+    least 99.9% of the shots, and the failure counts differ by no more than the
+    shots whose corrections differ."""
+    import dataclasses
+    from paper_2607_27644_amd import rbp
+    dem, priors = E._model_at("phen160", p)
+    code = rbp.Code.from_dem(dem)
+    syn, obs, _ = code.sample(priors, shots, seed=17)
+    prm = dataclasses.replace(rbp.RelayParams(), gamma_min=gmin, gamma_max=gmax)
+    f_gpu, _, _ = E._failures(code, dem, priors, syn, obs, prm)
+    corr, _, _ = code.decode(priors, syn, prm)
+    torch.cuda.synchronize()
+    oprm = oracle.RelayParams(**{k: getattr(prm, k) for k in oracle.RelayParams.__dataclass_fields__})
+    ref = oracle.decode(oracle.Graph(dem.H, dem.O), priors, rbp.to_u32(syn), oprm, nthreads=16)
+    obs_np = rbp.to_u32(obs)
+    f_orc = int(ostats.block_failures(ref["obs_pred"][:, :obs_np.shape[1]], obs_np, ref["converged"]).sum())
+    differ = int((rbp.to_u32(corr) != ref["corrections"]).any(axis=1).sum())
+    print(f"p={p} [{gmin}, {gmax}]: GPU {f_gpu}, oracle {f_orc} failures; {differ} shots differ")
+    assert differ <= shots // 1000
+    assert abs(f_gpu - f_orc) <= differ
+    assert f_orc > 0

@@ -230,3 +230,27 @@ def test_sampler_law_checks_reject_a_biased_or_correlated_law():
     corr[1::2, :L] = corr[0::2, :L]
     res = _law_checks(corr, p)
     assert not res["consecutive_shots"], res
+
+
+def test_marginals_saturate_and_stay_finite():
+    """Min-sum with memory grows messages geometrically on shots that never
+    converge (phen160 at p = 1 %, gamma in [0, 0.66]: |M| about 4e10 after leg
+    0 and 6e18 after leg 1).  The marginals saturate at 2^90, so every marginal
+    and message stays finite, the bound is attained, and no check message
+    exceeds the one-iteration growth bound (|mu| <= max |nu| <= 2^90 + max |mu|
+    of the previous iteration, at most T 2^90 within a leg of T iterations)."""
+    dem = W.workload("phen160")
+    g = oracle.Graph(dem.H, dem.O)
+    pr = np.full(dem.N, 1e-2)
+    syn, _ = oracle.sample(g, pr, 379, 17)[:2]
+    prm = oracle.RelayParams(gamma_min=0.0, gamma_max=0.66, num_sets=10)
+    sat = float(np.float32(2.0 ** 90))
+    for leg, t in [(0, 80), (1, 60), (5, 60), (10, 60)]:
+        M, mu = oracle.trace(g, pr, syn[378], prm, leg=leg, t=t)
+        assert np.isfinite(M).all() and np.isfinite(mu).all(), (leg, t)
+        assert np.abs(M).max() <= sat
+        assert np.abs(mu).max() <= t * sat
+        if leg >= 5:
+            assert np.abs(M).max() == sat  # the bound is reached, and held
+    out = oracle.decode(g, pr, syn[378:379], prm, nthreads=1)
+    assert out["converged"][0] == 0 and out["legs"][0] == 11
