@@ -316,6 +316,12 @@ def test_edge_cases(rbp):
         code.decode(dem.priors, syn, rbp.RelayParams(pre_iter=0))
     with pytest.raises(rbp.RbpError, match="INVALID_ARG"):
         code.decode(dem.priors, syn, rbp.RelayParams(stop_nconv=300))
+    # the bounds under which saturated marginals keep every message finite
+    for bad_params in (rbp.RelayParams(pre_iter=65537), rbp.RelayParams(max_iterations=70000),
+                       rbp.RelayParams(gamma_max=16.5), rbp.RelayParams(gamma0=float("nan"))):
+        with pytest.raises(rbp.RbpError, match="INVALID_ARG"):
+            code.decode(dem.priors, syn, bad_params)
+    code.decode(dem.priors, syn, rbp.RelayParams(pre_iter=65536, num_sets=0))
 
 
 def test_row_degree_32_kernel(rbp):
