@@ -191,11 +191,19 @@ rbp_status rbp_code_llr(rbp_code_t code, const double* priors, float* llr_dev, v
  * the least and the outgoing message signs -- and one float per variable;
  * rows of at most 16 edges; the messages are those of the per-edge form bit
  * for bit).  Auto takes 1 when it fits in LDS, else 3 when it fits, else 2.
- * max_slots: cap on the resident shot slots (0 = as many as fit). */
+ * max_slots: cap on the resident shot slots (0 = as many as fit; with several
+ * shots per workgroup it caps the workgroups).  shots_per_wg: 0 or 1, one shot
+ * per workgroup; 2 or 4, the workgroup decodes that many shots in lockstep,
+ * one flooding iteration of each per round, sharing every group's table loads
+ * (compact state only; applies to rbp_decode and rbp_decode_noalloc without a
+ * prior delta, one model; identical results).  Out-of-range values return
+ * RBP_ERR_INVALID_ARG; a decode whose K shots do not fit in LDS together
+ * returns RBP_ERR_UNSUPPORTED. */
 typedef struct {
     int32_t waves_per_shot;
     int32_t state;
     int32_t max_slots;
+    int32_t shots_per_wg;
 } rbp_launch_config;
 rbp_status rbp_set_launch_config(rbp_code_t code, const rbp_launch_config* cfg);
 /* Launch shape rbp_decode would use for this handle (after defaults). */

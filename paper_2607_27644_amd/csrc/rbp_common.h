@@ -65,6 +65,7 @@ struct LaunchCfg {
     int waves_per_shot = 0;
     int state = 0;
     int max_slots = 0;
+    int shots_per_wg = 0;  // 0 or 1: one shot per workgroup; 2 or 4: the multi-shot kernel
 };
 
 // largest row degree of H the decoder accepts (rows above 32 edges take the

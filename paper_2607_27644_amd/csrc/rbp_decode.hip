@@ -335,6 +335,9 @@ struct DecodeLaunch {
     // byte offsets in dynamic LDS (X itself starts at 0 when it lives there)
     int32_t off_M, off_sig, off_sigp, off_par, off_bestp, off_best, off_obs, off_misc;
     int32_t off_d16;  // compact state with BF16 adjustments: their LDS copy by position
+    int32_t off_grp;  // compact state: the model's variable and row group descriptors (int4 each)
+    int32_t nsub;        // shots per workgroup of the multi-shot kernel (1: the one-shot kernels)
+    int32_t sub_stride;  // LDS bytes between the multi-shot kernel's shot sub-slots (a multiple of 256)
     float gamma0;
     int32_t T0, Tr, R, S, crit;
     int32_t trace_on, trace_phase, trace_leg, trace_t;
@@ -794,6 +797,11 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
     uint32_t* best = reinterpret_cast<uint32_t*>(smem + a.off_best);
     uint32_t* obw = reinterpret_cast<uint32_t*>(smem + a.off_obs);
     SlotMisc* ms = reinterpret_cast<SlotMisc*>(smem + a.off_misc);
+    // the current model's group descriptors in LDS when they fit (copied when
+    // the model changes), else read from the model tables
+    const bool grp_lds = a.off_grp >= 0;
+    int4* lvg = reinterpret_cast<int4*>(smem + (grp_lds ? a.off_grp : 0));
+    int cur_model = -1;
 
     // Shots come from a device-wide ticket counter in runs of kShotRun (one
     // atomic per run) while many shots remain, one at a time near the end.
@@ -827,6 +835,15 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
         const float* dlt = a.delta ? a.delta + row * (uint64_t)N : nullptr;
         const uint16_t* dl16 = a.delta16 ? a.delta16 + row * (uint64_t)N : nullptr;
         if (tid == 0) X.st(4u * (uint32_t)m.S, INFINITY);  // read-only padding cell
+        int4* const lrg = lvg + m.GV;
+        if (grp_lds && mi != cur_model) {
+            // ordered before the sweeps' reads by the set-up barrier below
+            for (int i = tid; i < m.GV; i += nth) lvg[i] = m.vgrp[i];
+            for (int i = tid; i < m.GR; i += nth) lrg[i] = m.rgrp[i];
+            cur_model = mi;
+        }
+        auto vgrp_at = [&](int g) { return grp_lds ? lvg[g] : m.vgrp[g]; };
+        auto rgrp_at = [&](int g) { return grp_lds ? lrg[g] : m.rgrp[g]; };
         int pc = 0;
         for (int w = tid; w < WM; w += nth) {
             const uint32_t v = m.syn[row * WM + w];
@@ -926,7 +943,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                                     const bool wide = u < wide_units;
                                     const int g = wide ? u / kPersLpr : m.GRw + (u - wide_units);
                                     const int qq = wide ? u % kPersLpr : 0;
-                                    const int4 gi = m.rgrp[g];
+                                    const int4 gi = rgrp_at(g);
                                     const int dg = uniform(gi.y);
                                     const uint32_t off = (uint32_t)uniform(gi.x);
                                     if (dg > 32) {
@@ -949,7 +966,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                                 }
                             } else {
                                 for (int g = wid; g < m.GR; g += nw) {
-                                    const int4 gi = m.rgrp[g];
+                                    const int4 gi = rgrp_at(g);
                                     const uint32_t off = (uint32_t)uniform(gi.x);
                                     const uint32_t sbit = ((sigp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u) << 31;
                                     check_dispatch<RD>(X, m.rposp + off, m.rposw + off, m.m1pp + off, lane,
@@ -968,7 +985,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                         int dcount = 0;
                         double dW = 0.0;
                         for (int g = wid; g < m.GV; g += nw) {
-                            const int4 gi = m.vgrp[g];
+                            const int4 gi = vgrp_at(g);
                             const int dg = uniform(gi.y);
                             const bool mixed = uniform(gi.z) != 0;
                             const uint32_t pp = (uint32_t)(g * 64 + lane);
@@ -1013,7 +1030,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                         if (first_plain) {
                             // not converged on mu(1): nu(1) = M - mu(1) for the second check sweep
                             for (int g = wid; g < m.GV; g += nw) {
-                                const int4 gi = m.vgrp[g];
+                                const int4 gi = vgrp_at(g);
                                 const uint32_t pp = (uint32_t)(g * 64 + lane);
                                 extrinsic_dispatch(X, 4u * ((uint32_t)uniform(gi.x) + (uint32_t)lane), uniform(gi.y),
                                                    Mg[pp]);
@@ -1221,11 +1238,18 @@ __device__ __forceinline__ void compact_row_dispatch(int dg, const int32_t* cp, 
 // One variable with D edge slots (vrec entries slot + 64 q): the marginal
 // Lambda~ + sum_q mu_q in ascending check order.  In a mixed group only the
 // member's own vd edges enter the sum (unused slots hold x = 0, a valid read).
+// vrec entry q of a variable slot (its q-th edge); 32-bit offsets (folding the
+// constant 256 q into the loads' offset fields through 64-bit address
+// arithmetic measured 2 % slower on the [[840,168]] model)
+__device__ __forceinline__ uint32_t vrec_at(const uint32_t* vrec, uint32_t slot, int q) {
+    return ldg(vrec, slot + 64u * (uint32_t)q);
+}
+
 template <int D, bool MIXED>
 __device__ __forceinline__ float compact_var(const uint32_t* vrec, uint32_t slot, int vd, float acc) {
     uint32_t x[D];
 #pragma unroll
-    for (int q = 0; q < D; ++q) x[q] = ldg(vrec, slot + 64u * q);
+    for (int q = 0; q < D; ++q) x[q] = vrec_at(vrec, slot, q);
 #pragma unroll
     for (int q = 0; q < D; ++q) {
         const float mu = rec_mu(lds_rec(x[q] & ~15u), x[q]);
@@ -1239,11 +1263,10 @@ __device__ __forceinline__ float compact_var(const uint32_t* vrec, uint32_t slot
 __device__ __forceinline__ float compact_var_rolled(const uint32_t* vrec, uint32_t slot, int vd, float acc,
                                                    float* trace_mu, const int32_t* scsc) {
     for (int q = 0; q < vd; ++q) {
-        const uint32_t s = slot + 64u * (uint32_t)q;
-        const uint32_t x = ldg(vrec, s);
+        const uint32_t x = vrec_at(vrec, slot, q);
         const float mu = rec_mu(lds_rec(x & ~15u), x);
         acc = acc + mu;
-        if (trace_mu) trace_mu[ldg(scsc, s)] = mu;
+        if (trace_mu) trace_mu[ldg(scsc, slot + 64u * (uint32_t)q)] = mu;
     }
     return acc;
 }
@@ -1265,7 +1288,7 @@ __device__ __forceinline__ float compact_var_dispatch(const uint32_t* vrec, uint
 __device__ __forceinline__ void compact_flip(const uint32_t* vrec, uint32_t slot, int vd, uint32_t* par,
                                              int& dcount) {
     for (int q = 0; q < vd; ++q) {
-        const uint32_t rp = ldg(vrec, slot + 64u * (uint32_t)q) >> 4;
+        const uint32_t rp = vrec_at(vrec, slot, q) >> 4;
         const uint32_t bit = 1u << (rp & 31u);
         const uint32_t old = atomicXor(par + (rp >> 5), bit);
         dcount += (old & bit) ? -1 : 1;
@@ -1288,6 +1311,11 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
     uint32_t* best = reinterpret_cast<uint32_t*>(smem + a.off_best);
     uint32_t* obw = reinterpret_cast<uint32_t*>(smem + a.off_obs);
     SlotMisc* ms = reinterpret_cast<SlotMisc*>(smem + a.off_misc);
+    // the current model's group descriptors, copied to LDS when the model
+    // changes: every group of both sweeps starts with one, and an LDS read of
+    // a uniform address is far shorter than a load through the L2
+    int4* lvg = reinterpret_cast<int4*>(smem + a.off_grp);
+    int cur_model = -1;
 
     unsigned long long run_next = 0, run_end = 0, last_ticket = 0;
     for (;;) {
@@ -1322,6 +1350,14 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
         uint16_t* dpos = dl16 ? reinterpret_cast<uint16_t*>(smem + a.off_d16) : nullptr;
         float* Mg = reinterpret_cast<float*>(smem + m.coff_M);
         if (tid == 0) Mg[-4] = INFINITY;  // the padding cell at 16 * 64 GR
+        int4* const lrg = lvg + m.GV;
+        if (mi != cur_model) {
+            // the previous shot's sweeps ended before the end-of-shot barrier;
+            // the barrier below orders these stores before the next reads
+            for (int i = tid; i < m.GV; i += nth) lvg[i] = m.vgrp[i];
+            for (int i = tid; i < m.GR; i += nth) lrg[i] = m.rgrp[i];
+            cur_model = mi;
+        }
         int pc = 0;
         for (int w = tid; w < WM; w += nth) {
             const uint32_t v = m.syn[row * WM + w];
@@ -1422,7 +1458,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
                                 const uint4 r = ldg(m.r1rec, rp);
                                 lds_rec_st(16u * rp, make_uint4(r.x, r.y, 0u - sigma, r.w));
                             } else {
-                                const int4 gi = m.rgrp[g];
+                                const int4 gi = lrg[g];
                                 const uint32_t off = (uint32_t)uniform(gi.x) + (uint32_t)lane * (uint32_t)uniform(gi.w);
                                 if (t == 1)
                                     compact_row_dispatch<true>(uniform(gi.y), m.cvar + off, 16u * rp, sigma);
@@ -1436,7 +1472,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
                         int dcount = 0;
                         double dW = 0.0;
                         for (int g = wid; g < m.GV; g += nw) {
-                            const int4 gi = m.vgrp[g];
+                            const int4 gi = lvg[g];
                             const int dg = uniform(gi.y);
                             const bool mixed = uniform(gi.z) != 0;
                             const uint32_t pp = (uint32_t)(g * 64 + lane);
@@ -1559,6 +1595,440 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
                 st.t_end = wall_clock64();
                 a.stats[a.stats_by_row ? row : s] = st;
             }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Several shots per workgroup (compact state, one model, plain Relay-BP).
+//
+// The workgroup keeps K shots' compact states in LDS, sub-slot k at byte
+// offset k * sub_stride (the tables hold LDS addresses of sub-slot 0, so each
+// access adds the sub-slot's base; the bases are multiples of 256, which keeps
+// the low bits that encode an edge's code), and runs them in lockstep: one
+// round is one flooding iteration of every sub-slot.  The group descriptor,
+// the cvar / vrec table loads and the degree dispatch of each row or
+// variable group are shared by the K shots, which also gives each wave K
+// independent gathers per group.  A sub-slot whose shot finishes takes the
+// next ticket at the start of the next round; sub-slots without a shot at the
+// end of the batch are skipped.  Every shot's arithmetic is that of
+// relay_bp_compact_kernel.
+// ---------------------------------------------------------------------------
+template <int D, int K>
+__device__ __forceinline__ void compact_row_multi(const int32_t* cp, uint32_t rpx, const uint32_t (&sigma)[K],
+                                                  const uint32_t (&base)[K], uint32_t mask) {
+    constexpr int Q = (D + 3) / 4;
+    uint32_t pos[4 * Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const int4 v = reinterpret_cast<const int4*>(cp)[k];
+        pos[4 * k] = (uint32_t)v.x;
+        pos[4 * k + 1] = (uint32_t)v.y;
+        pos[4 * k + 2] = (uint32_t)v.z;
+        pos[4 * k + 3] = (uint32_t)v.w;
+    }
+    uint4 old[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s)
+        if ((mask >> s) & 1u) old[s] = lds_rec(base[s] + rpx);
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        if (!((mask >> s) & 1u)) continue;
+        const uint32_t rx = base[s] + rpx;
+        const uint32_t pa = old[s].w - rx;
+        uint32_t m1 = 0x7f800000u, m2 = 0x7f800000u, nb = 0u, am = 0u;
+#pragma unroll
+        for (int p = 0; p < D; ++p) {
+            const int c = D - 1 - p;  // the edge's code
+            const float M = lds_f(base[s] + pos[p]);
+            const uint32_t mag = pa == (uint32_t)c ? old[s].y : old[s].x;
+            const float mu = __uint_as_float(mag | ((old[s].z << (31 - c)) & 0x80000000u));
+            const uint32_t nu = __float_as_uint(M - mu);
+            const uint32_t av = nu & 0x7fffffffu;
+            nb = __builtin_amdgcn_alignbit(nb, nu, 31);
+            m2 = umed3(m1, m2, av);
+            const bool lt = av < m1;
+            m1 = lt ? av : m1;
+            am = lt ? (uint32_t)c : am;
+        }
+        const uint32_t flip = 0u - ((((uint32_t)__popc(nb)) ^ sigma[s]) & 1u);
+        const uint32_t sg = (nb ^ flip) & 0xFFFFu;
+        lds_rec_st(rx, make_uint4(m1, m2, sg | (sg << 16), rx + am));
+    }
+}
+
+// mask: the sub-slots (bit s) that take the update; uniform over the workgroup
+template <int K>
+__device__ __forceinline__ void compact_row_multi_dispatch(int dg, const int32_t* cp, uint32_t rpx,
+                                                           const uint32_t (&sigma)[K], const uint32_t (&base)[K],
+                                                           uint32_t mask) {
+    switch (dg) {
+#define RBP_CROWM(D) \
+    case D: compact_row_multi<D, K>(cp, rpx, sigma, base, mask); break;
+        RBP_CROWM(2) RBP_CROWM(3) RBP_CROWM(4) RBP_CROWM(5) RBP_CROWM(6) RBP_CROWM(7)
+        RBP_CROWM(8) RBP_CROWM(9) RBP_CROWM(10) RBP_CROWM(11) RBP_CROWM(12) RBP_CROWM(16)
+#undef RBP_CROWM
+        default: break;
+    }
+}
+
+// the K shots' marginals of one variable with D edge slots (in a mixed group
+// only the member's own vd edges enter the sums)
+template <int D, bool MIXED, int K>
+__device__ __forceinline__ void compact_var_multi(const uint32_t* vrec, uint32_t slot, int vd, float (&acc)[K],
+                                                  const uint32_t (&base)[K], uint32_t mask) {
+    uint32_t x[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) x[q] = vrec_at(vrec, slot, q);
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            if (!((mask >> s) & 1u)) continue;
+            const uint32_t xs = base[s] + x[q];
+            const float mu = rec_mu(lds_rec(xs & ~15u), xs);
+            acc[s] = (!MIXED || q < vd) ? acc[s] + mu : acc[s];
+        }
+}
+
+template <int K>
+__device__ __forceinline__ void compact_var_multi_dispatch(const uint32_t* vrec, uint32_t slot, int dg, bool mixed,
+                                                           int vd, float (&acc)[K], const uint32_t (&base)[K],
+                                                           uint32_t mask) {
+    switch (dg) {
+        case 0: return;
+#define RBP_CVARM(D)                                                         \
+    case D:                                                                  \
+        if (mixed)                                                           \
+            compact_var_multi<D, true, K>(vrec, slot, vd, acc, base, mask);  \
+        else                                                                 \
+            compact_var_multi<D, false, K>(vrec, slot, vd, acc, base, mask); \
+        return;
+        RBP_CVARM(1) RBP_CVARM(2) RBP_CVARM(3) RBP_CVARM(4) RBP_CVARM(5) RBP_CVARM(6) RBP_CVARM(7) RBP_CVARM(8)
+#undef RBP_CVARM
+        default:
+            for (int q = 0; q < vd; ++q) {
+                const uint32_t x = vrec_at(vrec, slot, q);
+#pragma unroll
+                for (int s = 0; s < K; ++s) {
+                    if (!((mask >> s) & 1u)) continue;
+                    const uint32_t xs = base[s] + x;
+                    acc[s] = acc[s] + rec_mu(lds_rec(xs & ~15u), xs);
+                }
+            }
+    }
+}
+
+template <int K, int MINW>
+__global__ void __launch_bounds__(1024, MINW) relay_bp_multishot_kernel(const DecodeLaunch a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63;
+    const int wid = uniform(tid >> 6), nw = nth >> 6;
+    const DecodeModel& m = a.m[0];
+    const uint32_t SS = (uint32_t)a.sub_stride;
+    const int N = m.N, WM = m.WM, WN = m.WN;
+    uint32_t base[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) base[s] = (uint32_t)s * SS;
+    auto P = [&](int s, int32_t off) { return smem + base[s] + off; };
+    int4* lvg = reinterpret_cast<int4*>(smem + a.off_grp);
+    int4* lrg = lvg + m.GV;
+    for (int i = tid; i < m.GV; i += nth) lvg[i] = m.vgrp[i];
+    for (int i = tid; i < m.GR; i += nth) lrg[i] = m.rgrp[i];
+
+    // per sub-slot state, kept identically by every thread (every decision
+    // below depends only on values all threads read after a barrier)
+    int status[K];  // 0: needs a shot, 1: decoding, 2: no shot left
+    int sbase[K], leg[K], t[K], nconv[K], legs[K], iters[K];
+    bool have[K];
+    double bestW[K];
+    unsigned long long shot[K];
+    uint64_t row[K], t_start[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        status[s] = 0;
+        sbase[s] = leg[s] = t[s] = nconv[s] = legs[s] = iters[s] = 0;
+        have[s] = false;
+        bestW[s] = 0.0;
+        shot[s] = 0;
+        row[s] = t_start[s] = 0;
+    }
+    unsigned long long run_next = 0, run_end = 0, last_ticket = 0;
+    __syncthreads();
+
+    for (;;) {
+        // ---- a new shot for every sub-slot that finished (zero syndromes are
+        // answered at once, and the sub-slot takes the next ticket)
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            while (status[s] == 0) {
+                SlotMisc* ms = reinterpret_cast<SlotMisc*>(P(s, a.off_misc));
+                if (tid == 0) {
+                    if (run_next == run_end) {
+                        const unsigned long long k = last_ticket + 8ull * kShotRun * K * gridDim.x < a.shots
+                                                         ? (unsigned long long)kShotRun
+                                                         : 1ull;
+                        run_next = atomicAdd(a.queue, k);
+                        run_end = run_next + k;
+                        last_ticket = run_next;
+                    }
+                    ms->shot = run_next++;
+                    ms->count = 0;
+                    ms->W = 0.0;
+                    ms->red[0] = 0;
+                }
+                __syncthreads();
+                const unsigned long long sh =
+                    ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(ms->shot >> 32)) << 32) |
+                    __builtin_amdgcn_readfirstlane((uint32_t)ms->shot);
+                if (sh >= a.shots) {
+                    status[s] = 2;
+                    break;
+                }
+                shot[s] = sh;
+                t_start[s] = wall_clock64();
+                row[s] = a.shot_index ? (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(a.shot_index[sh])
+                                      : (uint64_t)sh;
+                uint32_t* sig = reinterpret_cast<uint32_t*>(P(s, a.off_sig));
+                uint32_t* obw = reinterpret_cast<uint32_t*>(P(s, a.off_obs));
+                uint32_t* best = reinterpret_cast<uint32_t*>(P(s, a.off_best));
+                int pc = 0;
+                for (int w = tid; w < WM; w += nth) {
+                    const uint32_t v = m.syn[row[s] * WM + w];
+                    sig[w] = v;
+                    pc += __popc(v);
+                }
+                for (int w = tid; w < m.WK; w += nth) obw[w] = 0u;
+                for (int w = tid; w < WN; w += nth) best[w] = 0u;
+                if (pc) atomicAdd(&ms->red[0], pc);
+                __syncthreads();
+                sbase[s] = uniform(ms->red[0]);
+                if (sbase[s] == 0) {
+                    // zero syndrome: the zero correction, converged
+                    for (int w = tid; w < WN; w += nth) m.corr[row[s] * WN + w] = 0u;
+                    if (m.obsp)
+                        for (int w = tid; w < m.WK; w += nth) m.obsp[row[s] * m.WK + w] = 0u;
+                    if (a.stats && tid == 0) {
+                        rbp_shot_stats st;
+                        st.converged = 1;
+                        st.nconv = 0;
+                        st.path = 3;
+                        st.reserved = 0;
+                        st.legs = 0;
+                        st.reserved2 = 0;
+                        st.iters = 0;
+                        st.reserved3 = 0;
+                        st.t_start = t_start[s];
+                        st.t_end = wall_clock64();
+                        a.stats[a.stats_by_row ? row[s] : sh] = st;
+                    }
+                    __syncthreads();  // every thread has read ms before thread 0 rewrites it
+                    continue;
+                }
+                uint32_t* sigp = reinterpret_cast<uint32_t*>(P(s, a.off_sigp));
+                uint32_t* par = reinterpret_cast<uint32_t*>(P(s, a.off_par));
+                float* Mg = reinterpret_cast<float*>(P(s, m.coff_M));
+                for (int g = wid; g < m.GR; g += nw) {
+                    const int i = m.rord[g * 64 + lane];
+                    const bool b = i >= 0 && ((sig[i >> 5] >> (i & 31)) & 1u);
+                    const unsigned long long bb = __ballot(b);
+                    if (lane == 0) {
+                        sigp[2 * g] = (uint32_t)bb;
+                        sigp[2 * g + 1] = (uint32_t)(bb >> 32);
+                    }
+                }
+                if (tid == 0) Mg[-4] = INFINITY;  // the padding cell at 16 * 64 GR
+                for (int pp = tid; pp < m.Np; pp += nth) Mg[pp] = ldg(m.lamp, pp);
+                __syncthreads();
+                for (int w = tid; w < 2 * m.GR; w += nth) par[w] = sigp[w];
+                leg[s] = 0;
+                t[s] = 1;
+                nconv[s] = 0;
+                legs[s] = 1;
+                iters[s] = 0;
+                have[s] = false;
+                bestW[s] = 0.0;
+                status[s] = 1;
+                __syncthreads();
+            }
+        }
+        bool live = false;
+#pragma unroll
+        for (int s = 0; s < K; ++s) live = live || status[s] == 1;
+        if (!live) break;
+
+        // ---- check sweep: the min-sum update for the sub-slots past the first
+        // iteration of their leg, the model's first records for those at it
+        uint32_t normal = 0u, first = 0u, liveset = 0u;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            if (status[s] != 1) continue;
+            liveset |= 1u << s;
+            if (t[s] == 1)
+                first |= 1u << s;
+            else
+                normal |= 1u << s;
+        }
+        for (int g = wid; g < m.GR; g += nw) {
+            const int4 gi = lrg[g];
+            const uint32_t rp = (uint32_t)(g * 64 + lane);
+            uint32_t sigma[K];
+#pragma unroll
+            for (int s = 0; s < K; ++s)
+                sigma[s] = (reinterpret_cast<const uint32_t*>(P(s, a.off_sigp))[2 * g + (lane >> 5)] >> (lane & 31)) &
+                           1u;
+            const uint32_t off = (uint32_t)uniform(gi.x) + (uint32_t)lane * (uint32_t)uniform(gi.w);
+            if (normal) compact_row_multi_dispatch<K>(uniform(gi.y), m.cvar + off, 16u * rp, sigma, base, normal);
+            if (first) {
+                const uint4 r = ldg(m.r1rec, rp);
+#pragma unroll
+                for (int s = 0; s < K; ++s)
+                    if ((first >> s) & 1u)
+                        lds_rec_st(base[s] + 16u * rp, make_uint4(r.x, r.y, 0u - sigma[s], r.w + base[s]));
+            }
+        }
+        __syncthreads();
+
+        // ---- variable sweep
+        int dcount[K];
+        double dW[K];
+        const float2* lgl[K];
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            dcount[s] = 0;
+            dW[s] = 0.0;
+            lgl[s] = m.lg + (int64_t)leg[s] * m.Np;
+        }
+        for (int g = wid; g < m.GV; g += nw) {
+            const int4 gi = lvg[g];
+            const int dg = uniform(gi.y);
+            const bool mixed = uniform(gi.z) != 0;
+            const uint32_t pp = (uint32_t)(g * 64 + lane);
+            const uint32_t slot = (uint32_t)uniform(gi.x) + (uint32_t)lane;
+            const int vd = mixed ? ldg(m.vdeg, pp) : dg;
+            float acc[K], mo[K], l[K];
+#pragma unroll
+            for (int s = 0; s < K; ++s) {
+                if (!((liveset >> s) & 1u)) continue;
+                const float2 lgv = ldg(lgl[s], pp);
+                l[s] = lgv.x;
+                mo[s] = reinterpret_cast<const float*>(P(s, m.coff_M))[pp];
+                acc[s] = __builtin_fmaf(lgv.y, mo[s] - lgv.x, lgv.x);
+            }
+            compact_var_multi_dispatch<K>(m.vrec, slot, dg, mixed, vd, acc, base, liveset);
+#pragma unroll
+            for (int s = 0; s < K; ++s) {
+                if (!((liveset >> s) & 1u)) continue;
+                const float v = sat(acc[s]);
+                reinterpret_cast<float*>(P(s, m.coff_M))[pp] = v;
+                if ((v < 0.0f) != (mo[s] < 0.0f)) {
+                    compact_flip(m.vrec, slot, vd, reinterpret_cast<uint32_t*>(P(s, a.off_par)), dcount[s]);
+                    dW[s] += v < 0.0f ? (double)l[s] : -(double)l[s];
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            SlotMisc* ms = reinterpret_cast<SlotMisc*>(P(s, a.off_misc));
+            if (dcount[s]) atomicAdd(&ms->count, dcount[s]);
+            if (dW[s] != 0.0) atomicAdd(&ms->W, dW[s]);
+        }
+        __syncthreads();
+
+        // ---- per sub-slot: convergence, solutions, legs, end of the shot
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            if (status[s] != 1) continue;
+            SlotMisc* ms = reinterpret_cast<SlotMisc*>(P(s, a.off_misc));
+            const float* Mg = reinterpret_cast<const float*>(P(s, m.coff_M));
+            uint32_t* bestp = reinterpret_cast<uint32_t*>(P(s, a.off_bestp));
+            ++iters[s];
+            bool finish = false;
+            const int T = leg[s] == 0 ? a.T0 : a.Tr;
+            if (sbase[s] + uniform(ms->count) == 0) {
+                const double W = ms->W;
+                if (!have[s] || W < bestW[s]) {
+                    bestW[s] = W;
+                    have[s] = true;
+                    for (int g = wid; g < m.GV; g += nw) {
+                        const unsigned long long b = __ballot(Mg[g * 64 + lane] < 0.0f);
+                        if (lane == 0) {
+                            bestp[2 * g] = (uint32_t)b;
+                            bestp[2 * g + 1] = (uint32_t)(b >> 32);
+                        }
+                    }
+                }
+                ++nconv[s];
+                if ((a.crit == 0 && nconv[s] >= a.S) || leg[s] == a.R) {
+                    finish = true;
+                } else {
+                    ++leg[s];
+                    t[s] = 1;
+                    ++legs[s];
+                }
+            } else if (t[s] == T) {
+                if (leg[s] == a.R) {
+                    finish = true;
+                } else {
+                    ++leg[s];
+                    t[s] = 1;
+                    ++legs[s];
+                }
+            } else {
+                ++t[s];
+            }
+            if (!finish) continue;
+            if (!have[s]) {
+                for (int g = wid; g < m.GV; g += nw) {
+                    const unsigned long long b = __ballot(Mg[g * 64 + lane] < 0.0f);
+                    if (lane == 0) {
+                        bestp[2 * g] = (uint32_t)b;
+                        bestp[2 * g + 1] = (uint32_t)(b >> 32);
+                    }
+                }
+            }
+            __syncthreads();
+            uint32_t* best = reinterpret_cast<uint32_t*>(P(s, a.off_best));
+            uint32_t* obw = reinterpret_cast<uint32_t*>(P(s, a.off_obs));
+            for (int g = wid; g < m.GV; g += nw) {
+                if ((bestp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u) {
+                    const int j = ldg(m.vord, (uint32_t)(g * 64 + lane));
+                    atomicOr(best + (j >> 5), 1u << (j & 31));
+                }
+            }
+            __syncthreads();
+            for (int w = tid; w < WN; w += nth) {
+                const uint32_t bits = best[w];
+                m.corr[row[s] * WN + w] = bits;
+                uint32_t b = bits;
+                while (b) {
+                    const int j = w * 32 + __builtin_ctz(b);
+                    b &= b - 1u;
+                    for (int e = m.ocol_ptr[j]; e < m.ocol_ptr[j + 1]; ++e) {
+                        const int r = m.orow_idx[e];
+                        atomicXor(obw + (r >> 5), 1u << (r & 31));
+                    }
+                }
+            }
+            __syncthreads();
+            if (m.obsp)
+                for (int w = tid; w < m.WK; w += nth) m.obsp[row[s] * m.WK + w] = obw[w];
+            if (a.stats && tid == 0) {
+                rbp_shot_stats st;
+                st.converged = have[s] ? 1 : 0;
+                st.nconv = (uint8_t)(nconv[s] > 255 ? 255 : nconv[s]);
+                st.path = 0;
+                st.reserved = 0;
+                st.legs = (uint16_t)(legs[s] > 65535 ? 65535 : legs[s]);
+                st.reserved2 = 0;
+                st.iters = (uint32_t)iters[s];
+                st.reserved3 = 0;
+                st.t_start = t_start[s];
+                st.t_end = wall_clock64();
+                a.stats[a.stats_by_row ? row[s] : shot[s]] = st;
+            }
+            status[s] = 0;
         }
         __syncthreads();
     }
@@ -2166,6 +2636,9 @@ struct LaunchShape {
     int Smax = 0;
     int off_M = 0, off_sig = 0, off_sigp = 0, off_par = 0, off_bestp = 0, off_best = 0, off_obs = 0, off_misc = 0;
     int off_d16 = 0;
+    int off_grp = 0;
+    int nsub = 1;         // shots per workgroup (multi-shot kernel when > 1)
+    int sub_stride = 0;   // LDS bytes per shot sub-slot of the multi-shot kernel
 };
 
 static int align16(int64_t x) { return (int)((x + 15) & ~(int64_t)15); }
@@ -2173,7 +2646,15 @@ static int align16(int64_t x) { return (int)((x + 15) & ~(int64_t)15); }
 // Launch shape for a set of models decoded together (max sizes over models).
 // d16: the launch carries BF16 proposal adjustments (the compact state keeps a
 // copy of a shot's adjustments in LDS, 2 bytes per variable position)
-static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, LaunchShape* out, bool d16 = false) {
+static DecodeKernel multishot_kernel(int k, int minw) {
+    if (k == 4) return minw >= 8 ? relay_bp_multishot_kernel<4, 8> : relay_bp_multishot_kernel<4, 4>;
+    return minw >= 8 ? relay_bp_multishot_kernel<2, 8> : relay_bp_multishot_kernel<2, 4>;
+}
+
+// multishot_ok: the launch decodes one model with plain Relay-BP (no proposal,
+// no trace), so the handle's shots_per_wg setting applies
+static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, LaunchShape* out, bool d16 = false,
+                              bool multishot_ok = false) {
     int Smax = 0, Npmax = 0, GRmax = 0, WMmax = 0, WNmax = 0, WKmax = 1, rdmax = 0;
     for (int i = 0; i < n; ++i) {
         Smax = std::max(Smax, cs[i]->S);
@@ -2201,7 +2682,10 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
     }
     compact_bytes = align16(compact_bytes);
     const int64_t d16_bytes = d16 ? align16(2 * (int64_t)Npmax) : 0;
-    const bool compact_fits = compact_ok && compact_bytes + d16_bytes + small <= kMaxLds;
+    // the compact kernel keeps a model's group descriptors in LDS (GV + GR int4)
+    int64_t grp_bytes = 0;
+    for (int i = 0; i < n; ++i) grp_bytes = std::max<int64_t>(grp_bytes, 16 * ((int64_t)cs[i]->GV + cs[i]->GR));
+    const bool compact_fits = compact_ok && compact_bytes + d16_bytes + grp_bytes + small <= kMaxLds;
     bool lds = state_bytes + small <= kMaxLds;
     bool compact = false;
     if (cfg.state == 1 && !lds) return fail(RBP_ERR_UNSUPPORTED, "per-shot state does not fit in LDS");
@@ -2218,7 +2702,7 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
         if (lds) {
             // about 8 waves per SIMD (32 per CU) over the slots that fit in LDS, and
             // at least min(4, groups) waves so that a slow shot is not left to one wave
-            const int64_t per_slot = (compact ? compact_bytes + d16_bytes : state_bytes) + small;
+            const int64_t per_slot = (compact ? compact_bytes + d16_bytes + grp_bytes : state_bytes) + small;
             const int per_cu_lds = (int)std::max<int64_t>(kMaxLds / per_slot, 1);
             int groups = 0;
             for (int i = 0; i < n; ++i) groups = std::max(groups, std::max(cs[i]->GR, cs[i]->GV));
@@ -2261,14 +2745,37 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
     off += align16(sizeof(SlotMisc));
     L.off_d16 = (int)off;
     if (compact) off += d16_bytes;
+    // Group descriptors in LDS: measured 4-6 % faster with the compact state
+    // ([[840,168]], ZSZ-LP-550) and 4 % with device-memory state (hgp56), 2-3 %
+    // slower with the per-edge state in LDS (ZSZ-LP-160/320), which keeps them
+    // in the model tables.
+    L.off_grp = (int)off;
+    if (compact || (!lds && off + grp_bytes <= kMaxLds))
+        off += grp_bytes;
+    else
+        L.off_grp = -1;
     if (off > kMaxLds) return fail(RBP_ERR_UNSUPPORTED, "per-shot bit arrays do not fit in LDS");
     L.lds_bytes = (int)off;
+    const int nsub = multishot_ok && n == 1 && !d16 ? cfg.shots_per_wg : 1;
+    if (nsub > 1) {
+        if (!compact) return fail(RBP_ERR_UNSUPPORTED, "several shots per workgroup need the compact state");
+        // K sub-slots of the one-shot layout (without the descriptors), then the descriptors
+        L.nsub = nsub;
+        L.sub_stride = (L.off_grp + 255) & ~255;
+        const int64_t total = (int64_t)nsub * L.sub_stride + grp_bytes;
+        if (total > kMaxLds)
+            return fail(RBP_ERR_UNSUPPORTED, "the shots of one workgroup do not fit in LDS together");
+        L.off_grp = nsub * L.sub_stride;
+        L.lds_bytes = (int)total;
+        if (cfg.waves_per_shot <= 0) L.waves = 8;
+    }
     L.gstride = lds ? 0 : ((int64_t)Smax + 4 + Npmax + 63) / 64 * 64;
     // the register budget (128 or 64 VGPRs) that fits more slots per CU; on a
     // tie the larger budget (no spills)
     int per_cu = 0;
     for (int minw : {4, 8}) {
-        DecodeKernel k = compact ? compact_kernel(minw) : decode_kernel(rdmax, lds, minw);
+        DecodeKernel k = L.nsub > 1 ? multishot_kernel(L.nsub, minw)
+                                    : compact ? compact_kernel(minw) : decode_kernel(rdmax, lds, minw);
         int pc = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, reinterpret_cast<const void*>(k), 64 * waves,
                                                                     L.lds_bytes);
@@ -2306,7 +2813,8 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
         const int64_t cap = kStateCacheBytes / (4 * L.gstride);
         slots = std::min<int64_t>(slots, std::max<int64_t>(cap, std::max(cs[0]->num_cus, 1)));
     }
-    slots = std::min<int64_t>(slots, (int64_t)std::min<uint64_t>(std::max<uint64_t>(shots, 1), 1ull << 40));
+    slots = std::min<int64_t>(
+        slots, (int64_t)std::min<uint64_t>(std::max<uint64_t>((shots + L.nsub - 1) / L.nsub, 1), 1ull << 40));
     L.slots = (int)std::max<int64_t>(slots, 1);
     *out = L;
     return RBP_OK;
@@ -2318,7 +2826,8 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
 static rbp_status launch_decode(rbp_code* const* cs, int n, DecodeLaunch& a, uint64_t shots, hipStream_t stream,
                                 unsigned long long* queue = nullptr) {
     LaunchShape L;
-    rbp_status st = plan_launch(cs, n, shots, &L, a.delta16 != nullptr);
+    const bool multishot_ok = n == 1 && !a.delta && !a.delta16 && !a.trace_on && !a.shot_code;
+    rbp_status st = plan_launch(cs, n, shots, &L, a.delta16 != nullptr, multishot_ok);
     if (st) return st;
     rbp_code* c0 = cs[0];
     if (queue) {
@@ -2347,6 +2856,9 @@ static rbp_status launch_decode(rbp_code* const* cs, int n, DecodeLaunch& a, uin
     a.off_obs = L.off_obs;
     a.off_misc = L.off_misc;
     a.off_d16 = L.off_d16;
+    a.off_grp = L.off_grp;
+    a.nsub = L.nsub;
+    a.sub_stride = L.sub_stride;
     a.shots = shots;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, stream, a.queue, 1);
     RBP_HIP_CHECK(hipGetLastError());
@@ -3022,11 +3534,13 @@ rbp_status rbp_code_llr(rbp_code_t c, const double* priors, float* llr, void* st
 rbp_status rbp_set_launch_config(rbp_code_t c, const rbp_launch_config* cfg) {
     if (!c || !cfg) return fail(RBP_ERR_INVALID_ARG, "NULL argument");
     if (cfg->waves_per_shot < 0 || cfg->waves_per_shot > 16 || cfg->state < 0 || cfg->state > 3 ||
-        cfg->max_slots < 0)
+        cfg->max_slots < 0 || (cfg->shots_per_wg != 0 && cfg->shots_per_wg != 1 && cfg->shots_per_wg != 2 &&
+                               cfg->shots_per_wg != 4))
         return fail(RBP_ERR_INVALID_ARG, "launch config out of range");
     c->cfg.waves_per_shot = cfg->waves_per_shot;
     c->cfg.state = cfg->state;
     c->cfg.max_slots = cfg->max_slots;
+    c->cfg.shots_per_wg = cfg->shots_per_wg;
     return RBP_OK;
 }
 
@@ -3034,12 +3548,13 @@ rbp_status rbp_get_launch_config(rbp_code_t c, rbp_launch_config* cfg, int32_t* 
     if (!c) return fail(RBP_ERR_INVALID_ARG, "code is NULL");
     LaunchShape L;
     rbp_code* cs[1] = {c};
-    rbp_status st = plan_launch(cs, 1, 1ull << 40, &L);
+    rbp_status st = plan_launch(cs, 1, 1ull << 40, &L, false, true);
     if (st) return st;
     if (cfg) {
         cfg->waves_per_shot = L.waves;
         cfg->state = L.compact ? 3 : L.lds_state ? 1 : 2;
         cfg->max_slots = c->cfg.max_slots;
+        cfg->shots_per_wg = L.nsub;
     }
     if (slots) *slots = L.slots;
     if (lds_bytes) *lds_bytes = L.lds_bytes;

@@ -109,7 +109,8 @@ def multi(names, shots_each: int, seed: int = 11, params: rbp.RelayParams | None
         ms, _ = _timed(lambda: c.decode(d.priors, syn, params))
         tot_ms += ms
         res["per_model_launches"][nm] = {"ms": ms, "shots_per_s": shots_each / (ms * 1e-3),
-                                         "waves": tr["waves_per_shot"], "state": tr["state"]}
+                                         "waves": tr["waves_per_shot"], "state": tr["state"],
+                                         "shots_per_wg": tr["shots_per_wg"]}
     res["per_model_total"] = {"ms": tot_ms, "shots_per_s": total / (tot_ms * 1e-3)}
     return res
 

@@ -58,7 +58,8 @@ class SpaParams:
 
 
 class LaunchConfigC(ctypes.Structure):
-    _fields_ = [("waves_per_shot", ctypes.c_int32), ("state", ctypes.c_int32), ("max_slots", ctypes.c_int32)]
+    _fields_ = [("waves_per_shot", ctypes.c_int32), ("state", ctypes.c_int32), ("max_slots", ctypes.c_int32),
+                ("shots_per_wg", ctypes.c_int32)]
 
 
 SHOT_STATS_DTYPE = np.dtype([("converged", np.uint8), ("nconv", np.uint8), ("path", np.uint8), ("r0", np.uint8),
@@ -457,8 +458,10 @@ class Code:
                                    _ptr(counts), _stream(stream)))
         return bits, marg, st
 
-    def set_launch_config(self, waves_per_shot: int = 0, state: int = 0, max_slots: int = 0):
-        cfg = LaunchConfigC(waves_per_shot, state, max_slots)
+    def set_launch_config(self, waves_per_shot: int = 0, state: int = 0, max_slots: int = 0, shots_per_wg: int = 0):
+        """rbp_set_launch_config; shots_per_wg 2 or 4 selects the multi-shot
+        kernel (compact state, plain decodes of one model)."""
+        cfg = LaunchConfigC(waves_per_shot, state, max_slots, shots_per_wg)
         check(lib().rbp_set_launch_config(self.h, ctypes.byref(cfg)))
 
     def launch_config(self):
@@ -466,7 +469,7 @@ class Code:
         slots, lds = ctypes.c_int32(), ctypes.c_int32()
         check(lib().rbp_get_launch_config(self.h, ctypes.byref(cfg), ctypes.byref(slots), ctypes.byref(lds)))
         return dict(waves_per_shot=cfg.waves_per_shot, state=cfg.state, max_slots=cfg.max_slots,
-                    slots=slots.value, lds_bytes=lds.value)
+                    shots_per_wg=cfg.shots_per_wg, slots=slots.value, lds_bytes=lds.value)
 
 
 def decode_multi(codes: Sequence[Code], priors: Sequence, shot_code: torch.Tensor, shot_index: torch.Tensor,
