@@ -1295,6 +1295,62 @@ __device__ __forceinline__ void compact_flip(const uint32_t* vrec, uint32_t slot
     }
 }
 
+// Runs of equal-degree groups.  Groups are sorted by degree, so the groups a
+// wave takes in one sweep (g, g + nw, ...) come in long runs of one degree:
+// the degree dispatch is taken once per run, and inside a run each group only
+// checks that the next one still has the same degree.
+template <int D>
+__device__ __forceinline__ int compact_row_run(int g, int nw, int GR, const int4* lrg, const int32_t* cvar,
+                                               const uint32_t* sigp, int lane) {
+    do {
+        const int4 gi = lrg[g];
+        const uint32_t rp = (uint32_t)(g * 64 + lane);
+        const uint32_t sigma = (sigp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u;
+        const uint32_t off = (uint32_t)uniform(gi.x) + (uint32_t)lane * (uint32_t)uniform(gi.w);
+        compact_row<D, false>(cvar + off, 16u * rp, sigma);
+        g += nw;
+    } while (g < GR && uniform(lrg[g].y) == D);
+    return g;
+}
+
+// the check sweep past a leg's first iteration (nu = M - mu of the old record)
+__device__ __forceinline__ void compact_check_runs(int g, int nw, int GR, const int4* lrg, const int32_t* cvar,
+                                                   const uint32_t* sigp, int lane) {
+    while (g < GR) {
+        switch (uniform(lrg[g].y)) {
+#define RBP_CRUN(D) \
+    case D: g = compact_row_run<D>(g, nw, GR, lrg, cvar, sigp, lane); break;
+            RBP_CRUN(2) RBP_CRUN(3) RBP_CRUN(4) RBP_CRUN(5) RBP_CRUN(6) RBP_CRUN(7)
+            RBP_CRUN(8) RBP_CRUN(9) RBP_CRUN(10) RBP_CRUN(11) RBP_CRUN(12) RBP_CRUN(16)
+#undef RBP_CRUN
+            default: g += nw;  // no other stored degree occurs
+        }
+    }
+}
+
+// a run of unmixed variable groups of degree D in a plain leg
+template <int D>
+__device__ __forceinline__ int compact_var_run(int g, int nw, int GV, const int4* lvg, const uint32_t* vrec,
+                                               const float2* lgl, float* Mg, uint32_t* par, int& dcount, double& dW,
+                                               int lane) {
+    do {
+        const int4 gi = lvg[g];
+        const uint32_t pp = (uint32_t)(g * 64 + lane);
+        const float2 lgv = ldg(lgl, pp);
+        const float l = lgv.x;
+        const float mo = Mg[pp];
+        const uint32_t slot = (uint32_t)uniform(gi.x) + (uint32_t)lane;
+        const float acc = sat(compact_var<D, false>(vrec, slot, D, __builtin_fmaf(lgv.y, mo - l, l)));
+        Mg[pp] = acc;
+        if ((acc < 0.0f) != (mo < 0.0f)) {
+            compact_flip(vrec, slot, D, par, dcount);
+            dW += acc < 0.0f ? (double)l : -(double)l;
+        }
+        g += nw;
+    } while (g < GV && uniform(lvg[g].y) == D && uniform(lvg[g].z) == 0);
+    return g;
+}
+
 // Persistent Relay-BP on the compact state (always in LDS); the shot queue,
 // phases, legs, stop rule, statistics and outputs are those of
 // relay_bp_kernel.  The parity bits of the hard decision are kept by row
@@ -1457,13 +1513,14 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
                                 // nu(0) = Lambda > 0: the model's first records, signs = sigma
                                 const uint4 r = ldg(m.r1rec, rp);
                                 lds_rec_st(16u * rp, make_uint4(r.x, r.y, 0u - sigma, r.w));
-                            } else {
+                            } else if (t == 1) {
+                                // first iteration of a proposal leg: nu(0) = M(0)
                                 const int4 gi = lrg[g];
                                 const uint32_t off = (uint32_t)uniform(gi.x) + (uint32_t)lane * (uint32_t)uniform(gi.w);
-                                if (t == 1)
-                                    compact_row_dispatch<true>(uniform(gi.y), m.cvar + off, 16u * rp, sigma);
-                                else
-                                    compact_row_dispatch<false>(uniform(gi.y), m.cvar + off, 16u * rp, sigma);
+                                compact_row_dispatch<true>(uniform(gi.y), m.cvar + off, 16u * rp, sigma);
+                            } else {
+                                compact_check_runs(g, nw, m.GR, lrg, m.cvar, sigp, lane);
+                                break;  // the runs covered every remaining group of this wave
                             }
                         }
                         __syncthreads();
@@ -1475,6 +1532,19 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
                             const int4 gi = lvg[g];
                             const int dg = uniform(gi.y);
                             const bool mixed = uniform(gi.z) != 0;
+                            if (!lp && !tr && !mixed && dg >= 1 && dg <= 8) {
+                                // plain leg: runs of unmixed groups of one degree
+                                int h = g;
+                                switch (dg) {
+#define RBP_VRUN(D) \
+    case D: h = compact_var_run<D>(g, nw, m.GV, lvg, m.vrec, lgl, Mg, par, dcount, dW, lane); break;
+                                    RBP_VRUN(1) RBP_VRUN(2) RBP_VRUN(3) RBP_VRUN(4)
+                                    RBP_VRUN(5) RBP_VRUN(6) RBP_VRUN(7) RBP_VRUN(8)
+#undef RBP_VRUN
+                                }
+                                g = h - nw;  // the loop's increment takes the next group
+                                continue;
+                            }
                             const uint32_t pp = (uint32_t)(g * 64 + lane);
                             const float2 lgv = ldg(lgl, pp);
                             const float l = lgv.x, gm = lgv.y;
