@@ -1299,7 +1299,7 @@ __device__ __forceinline__ void compact_flip(const uint32_t* vrec, uint32_t slot
 // wave takes in one sweep (g, g + nw, ...) come in long runs of one degree:
 // the degree dispatch is taken once per run, and inside a run each group only
 // checks that the next one still has the same degree.
-template <int D>
+template <int D, bool FIRST>
 __device__ __forceinline__ int compact_row_run(int g, int nw, int GR, const int4* lrg, const int32_t* cvar,
                                                const uint32_t* sigp, int lane) {
     do {
@@ -1307,19 +1307,21 @@ __device__ __forceinline__ int compact_row_run(int g, int nw, int GR, const int4
         const uint32_t rp = (uint32_t)(g * 64 + lane);
         const uint32_t sigma = (sigp[2 * g + (lane >> 5)] >> (lane & 31)) & 1u;
         const uint32_t off = (uint32_t)uniform(gi.x) + (uint32_t)lane * (uint32_t)uniform(gi.w);
-        compact_row<D, false>(cvar + off, 16u * rp, sigma);
+        compact_row<D, FIRST>(cvar + off, 16u * rp, sigma);
         g += nw;
     } while (g < GR && uniform(lrg[g].y) == D);
     return g;
 }
 
-// the check sweep past a leg's first iteration (nu = M - mu of the old record)
+// a check sweep in runs: FIRST, the first iteration of a proposal leg (nu =
+// M); else past a leg's first iteration (nu = M - mu of the old record)
+template <bool FIRST>
 __device__ __forceinline__ void compact_check_runs(int g, int nw, int GR, const int4* lrg, const int32_t* cvar,
                                                    const uint32_t* sigp, int lane) {
     while (g < GR) {
         switch (uniform(lrg[g].y)) {
 #define RBP_CRUN(D) \
-    case D: g = compact_row_run<D>(g, nw, GR, lrg, cvar, sigp, lane); break;
+    case D: g = compact_row_run<D, FIRST>(g, nw, GR, lrg, cvar, sigp, lane); break;
             RBP_CRUN(2) RBP_CRUN(3) RBP_CRUN(4) RBP_CRUN(5) RBP_CRUN(6) RBP_CRUN(7)
             RBP_CRUN(8) RBP_CRUN(9) RBP_CRUN(10) RBP_CRUN(11) RBP_CRUN(12) RBP_CRUN(16)
 #undef RBP_CRUN
@@ -1328,19 +1330,21 @@ __device__ __forceinline__ void compact_check_runs(int g, int nw, int GR, const 
     }
 }
 
-// a run of unmixed variable groups of degree D in a plain leg
-template <int D>
+// a run of unmixed variable groups of degree D; PROP: a proposal leg, whose
+// prior is Lambda + delta with the shot's BF16 adjustments by position (dpos)
+template <int D, bool PROP>
 __device__ __forceinline__ int compact_var_run(int g, int nw, int GV, const int4* lvg, const uint32_t* vrec,
-                                               const float2* lgl, float* Mg, uint32_t* par, int& dcount, double& dW,
-                                               int lane) {
+                                               const float2* lgl, const uint16_t* dpos, float* Mg, uint32_t* par,
+                                               int& dcount, double& dW, int lane) {
     do {
         const int4 gi = lvg[g];
         const uint32_t pp = (uint32_t)(g * 64 + lane);
         const float2 lgv = ldg(lgl, pp);
         const float l = lgv.x;
+        const float lt = PROP ? l + bf16_to_f32(dpos[pp]) : l;
         const float mo = Mg[pp];
         const uint32_t slot = (uint32_t)uniform(gi.x) + (uint32_t)lane;
-        const float acc = sat(compact_var<D, false>(vrec, slot, D, __builtin_fmaf(lgv.y, mo - l, l)));
+        const float acc = sat(compact_var<D, false>(vrec, slot, D, __builtin_fmaf(lgv.y, mo - lt, lt)));
         Mg[pp] = acc;
         if ((acc < 0.0f) != (mo < 0.0f)) {
             compact_flip(vrec, slot, D, par, dcount);
@@ -1355,7 +1359,7 @@ __device__ __forceinline__ int compact_var_run(int g, int nw, int GV, const int4
 // phases, legs, stop rule, statistics and outputs are those of
 // relay_bp_kernel.  The parity bits of the hard decision are kept by row
 // position (initialised from the syndrome's row-position ballots).
-template <int MINW>
+template <int MINW, bool PROP>
 __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const DecodeLaunch a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63;
@@ -1445,7 +1449,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
                     sigp[2 * g + 1] = (uint32_t)(bb >> 32);
                 }
             }
-            const int first_phase = (dlt || dl16) ? 1 : 0;
+            const int first_phase = PROP && (dlt || dl16) ? 1 : 0;  // PROP = false: no proposal code at all
             for (int phase = first_phase; phase >= 0; --phase) {
                 const bool prop = phase == 1;
                 __syncthreads();  // sigp complete; the previous phase's counters read
@@ -1513,13 +1517,13 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
                                 // nu(0) = Lambda > 0: the model's first records, signs = sigma
                                 const uint4 r = ldg(m.r1rec, rp);
                                 lds_rec_st(16u * rp, make_uint4(r.x, r.y, 0u - sigma, r.w));
-                            } else if (t == 1) {
-                                // first iteration of a proposal leg: nu(0) = M(0)
-                                const int4 gi = lrg[g];
-                                const uint32_t off = (uint32_t)uniform(gi.x) + (uint32_t)lane * (uint32_t)uniform(gi.w);
-                                compact_row_dispatch<true>(uniform(gi.y), m.cvar + off, 16u * rp, sigma);
                             } else {
-                                compact_check_runs(g, nw, m.GR, lrg, m.cvar, sigp, lane);
+                                // in runs of equal degree (t = 1 here only in a proposal leg,
+                                // whose nu(0) is its M(0))
+                                if (t == 1)
+                                    compact_check_runs<true>(g, nw, m.GR, lrg, m.cvar, sigp, lane);
+                                else
+                                    compact_check_runs<false>(g, nw, m.GR, lrg, m.cvar, sigp, lane);
                                 break;  // the runs covered every remaining group of this wave
                             }
                         }
@@ -1532,15 +1536,26 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
                             const int4 gi = lvg[g];
                             const int dg = uniform(gi.y);
                             const bool mixed = uniform(gi.z) != 0;
-                            if (!lp && !tr && !mixed && dg >= 1 && dg <= 8) {
-                                // plain leg: runs of unmixed groups of one degree
+                            if ((!lp || dpos) && !tr && !mixed && dg >= 1 && dg <= 8) {
+                                // runs of unmixed groups of one degree (plain legs, and
+                                // proposal legs with BF16 adjustments)
                                 int h = g;
-                                switch (dg) {
+                                if (lp) {
+                                    switch (dg) {
 #define RBP_VRUN(D) \
-    case D: h = compact_var_run<D>(g, nw, m.GV, lvg, m.vrec, lgl, Mg, par, dcount, dW, lane); break;
-                                    RBP_VRUN(1) RBP_VRUN(2) RBP_VRUN(3) RBP_VRUN(4)
-                                    RBP_VRUN(5) RBP_VRUN(6) RBP_VRUN(7) RBP_VRUN(8)
+    case D: h = compact_var_run<D, true>(g, nw, m.GV, lvg, m.vrec, lgl, dpos, Mg, par, dcount, dW, lane); break;
+                                        RBP_VRUN(1) RBP_VRUN(2) RBP_VRUN(3) RBP_VRUN(4)
+                                        RBP_VRUN(5) RBP_VRUN(6) RBP_VRUN(7) RBP_VRUN(8)
 #undef RBP_VRUN
+                                    }
+                                } else {
+                                    switch (dg) {
+#define RBP_VRUN(D) \
+    case D: h = compact_var_run<D, false>(g, nw, m.GV, lvg, m.vrec, lgl, dpos, Mg, par, dcount, dW, lane); break;
+                                        RBP_VRUN(1) RBP_VRUN(2) RBP_VRUN(3) RBP_VRUN(4)
+                                        RBP_VRUN(5) RBP_VRUN(6) RBP_VRUN(7) RBP_VRUN(8)
+#undef RBP_VRUN
+                                    }
                                 }
                                 g = h - nw;  // the loop's increment takes the next group
                                 continue;
@@ -2677,8 +2692,11 @@ static DecodeModel model_of(const rbp_code* c, const uint32_t* syn, uint32_t* co
 
 typedef void (*DecodeKernel)(const DecodeLaunch);
 
-static DecodeKernel compact_kernel(int minw) {
-    return minw >= 8 ? relay_bp_compact_kernel<8> : relay_bp_compact_kernel<4>;
+// prop: the launch carries proposal adjustments (built separately, so that the
+// plain decode's code is not shaped by the proposal leg's)
+static DecodeKernel compact_kernel(int minw, bool prop) {
+    if (prop) return minw >= 8 ? relay_bp_compact_kernel<8, true> : relay_bp_compact_kernel<4, true>;
+    return minw >= 8 ? relay_bp_compact_kernel<8, false> : relay_bp_compact_kernel<4, false>;
 }
 
 static DecodeKernel decode_kernel(int max_stored_row_deg, bool lds, int minw) {
@@ -2724,7 +2742,7 @@ static DecodeKernel multishot_kernel(int k, int minw) {
 // multishot_ok: the launch decodes one model with plain Relay-BP (no proposal,
 // no trace), so the handle's shots_per_wg setting applies
 static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, LaunchShape* out, bool d16 = false,
-                              bool multishot_ok = false) {
+                              bool multishot_ok = false, bool prop = false) {
     int Smax = 0, Npmax = 0, GRmax = 0, WMmax = 0, WNmax = 0, WKmax = 1, rdmax = 0;
     for (int i = 0; i < n; ++i) {
         Smax = std::max(Smax, cs[i]->S);
@@ -2845,7 +2863,7 @@ static rbp_status plan_launch(rbp_code* const* cs, int n, uint64_t shots, Launch
     int per_cu = 0;
     for (int minw : {4, 8}) {
         DecodeKernel k = L.nsub > 1 ? multishot_kernel(L.nsub, minw)
-                                    : compact ? compact_kernel(minw) : decode_kernel(rdmax, lds, minw);
+                                    : compact ? compact_kernel(minw, prop || d16) : decode_kernel(rdmax, lds, minw);
         int pc = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, reinterpret_cast<const void*>(k), 64 * waves,
                                                                     L.lds_bytes);
@@ -2897,7 +2915,7 @@ static rbp_status launch_decode(rbp_code* const* cs, int n, DecodeLaunch& a, uin
                                 unsigned long long* queue = nullptr) {
     LaunchShape L;
     const bool multishot_ok = n == 1 && !a.delta && !a.delta16 && !a.trace_on && !a.shot_code;
-    rbp_status st = plan_launch(cs, n, shots, &L, a.delta16 != nullptr, multishot_ok);
+    rbp_status st = plan_launch(cs, n, shots, &L, a.delta16 != nullptr, multishot_ok, a.delta != nullptr);
     if (st) return st;
     rbp_code* c0 = cs[0];
     if (queue) {
