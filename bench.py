@@ -18,7 +18,8 @@ Paths, each timed the same way on the same shots:
   proposal_zero   the same proposal leg with delta = 0 (no network)
 Paired points at p = 5e-3 and 2.5e-2 decode the same syndromes with every
 path (the [[840,168]] model shows no failure in 10^5 shots below about 2 %).  Beside the headline: sequential
-single-shot latency, the batched uneven decode of four codes, the paper's
+single-shot latency (one decode call per shot, and the resident decoder fed
+through pinned host memory), the batched uneven decode of four codes, the paper's
 latency-table workload (circuit-level ZSZ-LP-320 memory), the classical AWGN
 benchmark and the earlier ZSZ-LP-160 workload.  Prints one JSON line.
 """
@@ -38,6 +39,11 @@ METRIC = "decoded shots/s + p50/p99 latency at fixed LER: Relay-BP vs learned pr
 LDS_NOMINAL_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz (a CDNA3-style figure)
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
+
+
+def progress(msg: str):
+    """One line per finished stage on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
@@ -258,6 +264,7 @@ def main():
         paths["first_solution"] = timed("plain", fs)
         paths["first_solution"]["note"] = "Relay-BP with stop_nconv = 1: the proposal path's stop rule, no proposal"
 
+    progress("headline steps done")
     if not args.no_learned:
         from paper_2607_27644_amd import learned
         cfg = learned.TrainConfig(pairs=args.train_pairs, hidden=args.hidden, delta_scale=args.delta_scale)
@@ -334,6 +341,7 @@ def main():
                                                 "both": int((a & b).sum())}
         out["ler_high_p"].append(res)
 
+    progress("learned and paired-LER stages done")
     if not args.no_sequential:
         # the paper's sequential mode: one shot per decode call, host clock around each
         lat = []
@@ -345,10 +353,23 @@ def main():
             torch.cuda.synchronize()
             lat.append(1e6 * (time.perf_counter() - ta))
         out["latency_us"]["sequential_single_shot"] = stats.percentiles(np.array(lat))
+        # the same shots through the resident decoder: one launch, the syndrome
+        # handed over and the correction returned through pinned host memory
+        hsyn = syn[:200].cpu().numpy().view(np.uint32)
+        with code.resident(dem.priors, params, idle_seconds=10.0) as rd:
+            rd.decode(hsyn[0])
+            lat = []
+            for i in range(200):
+                ta = time.perf_counter()
+                rd.decode(hsyn[i])
+                lat.append(1e6 * (time.perf_counter() - ta))
+        out["latency_us"]["resident_single_shot"] = stats.percentiles(np.array(lat))
 
+    progress("sequential latency done")
     if not args.no_extras:
         out["extras"] = extras(args.seed)
 
+    progress("extras done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dem, args.seed, params, args.cpu_seconds)
     code.close()
@@ -379,12 +400,14 @@ def extras(seed: int) -> dict:
                       "launch": code.launch_config()}
     code.close()
     # batched uneven decode: 4 codes (ZSZ-LP-160/320/550/775, 9 rounds), shots interleaved
+    progress("extras: phen160 done")
     res["uneven_batch"] = experiments.multi(["phen160", "phen320", "phen550", "phen775"], 50000, seed=seed)
+    progress("extras: uneven batch done")
     # the paper's latency-table workload: circuit-level ZSZ-LP-320 memory (1920 x 28992), p = 1e-3
     gmin, gmax = experiments.CIRCUIT_GAMMA["ZSZ-LP-320"]
     prm = rbp.RelayParams(num_sets=1000, gamma_min=gmin, gamma_max=gmax)
     cl = {"code": "ZSZ-LP-320", "p": 1e-3, "relay": {"num_sets": 1000, "gamma": [gmin, gmax]}}
-    lat_all = []
+    lat_all, res_all = [], []
     for basis in "XZ":
         d = circuits.memory_dem("ZSZ-LP-320", basis, 1e-3)
         c = rbp.Code.from_dem(d)
@@ -397,15 +420,27 @@ def extras(seed: int) -> dict:
             c.decode_coop(d.priors, s[i:i + 1], prm, out=o)
             torch.cuda.synchronize()
             lat.append(1e6 * (time.perf_counter() - t0))
+        hs = s[:100].cpu().numpy().view(np.uint32)
+        with c.resident(d.priors, prm, idle_seconds=10.0) as rd:
+            rd.decode(hs[0])
+            rlat = []
+            for i in range(100):
+                t0 = time.perf_counter()
+                rd.decode(hs[i])
+                rlat.append(1e6 * (time.perf_counter() - t0))
         ms, out = experiments._timed(lambda: c.decode(d.priors, s, prm), repeats=2)
         cl[f"{basis}_memory"] = {"dem": [d.M, d.N], "latency_mode_us": stats.percentiles(np.array(lat)),
+                                 "resident_us": stats.percentiles(np.array(rlat)),
                                  "batched_shots_per_s": 4000 / (ms * 1e-3),
                                  "mean_iters": float(rbp.stats_to_numpy(out[2])["iters"].mean())}
         lat_all += lat
+        res_all += rlat
         c.close()
     cl["latency_mode_us_xz"] = stats.percentiles(np.array(lat_all))
+    cl["resident_us_xz"] = stats.percentiles(np.array(res_all))
     cl["paper_l40s_ms"] = {"mean": 1.2, "p99": 2.0, "p99.9": 3.2, "note": "NVIDIA L40S, Table 'decoding latency'"}
     res["circuit_latency"] = cl
+    progress("extras: circuit latency done")
     # classical ZSZ-2BGA [310,155] code over BPSK-AWGN at 2.5 dB, sum-product BP
     r = experiments.awgn_fer(["ZSZ-2BGA-310"], [2.5], max_frames=2_000_000, min_errors=10 ** 12, chunk=1_000_000)
     pt = r["codes"]["ZSZ-2BGA-310"]["points"][0]

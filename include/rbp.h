@@ -247,6 +247,56 @@ rbp_status rbp_decode_coop(rbp_code_t code, const double* priors, const uint32_t
  * RBP_ERR_ABORTED).  Synchronizes the stream. */
 rbp_status rbp_coop_aborted(rbp_code_t code, void* stream, int32_t* aborted);
 
+/* Resident decoder: the sequential single-shot decoding of the latency tables
+ * (Sec. 6.1, Table "decoding latency"; one shot at a time) without a kernel
+ * launch per shot.  rbp_resident_start launches the latency-mode kernel (the
+ * decoder of rbp_decode_coop, same arithmetic and results) once, on a
+ * non-blocking stream of its own; the kernel stays on the GPU and takes shots
+ * from a mailbox in pinned, coherent host memory.  rbp_resident_decode copies
+ * one syndrome into the mailbox, raises its shot counter and spins on the host
+ * until the kernel has written the correction, observable prediction and
+ * statistics back: a shot's latency holds no launch, no stream
+ * synchronization and no copy call, only the mailbox's PCIe round trips.
+ *
+ * coop: workgroups, stride, waves, spin_limit, device_fences as for
+ *   rbp_decode_coop (0 = its defaults; workgroups = 1 decodes on one CU).
+ * idle_seconds: the kernel ends itself when no shot comes for this long
+ *   (0: 1 s), so a forgotten handle never holds the GPU; the next
+ *   rbp_resident_decode launches it again (that shot's latency then includes
+ *   the launch).  wait_seconds: bound on one rbp_resident_decode's wait
+ *   (0: 60 s); on expiry the kernel is stopped and ABORTED returned.
+ *
+ * While a resident decoder runs: its kernel occupies `workgroups` CUs; calls
+ * that synchronize the whole device (hipDeviceSynchronize, a hipFree that
+ * waits for the device) wait until it ends (rbp_resident_stop, or
+ * idle_seconds without a shot); decode calls on the same code handle that
+ * would change its priors or relay parameters, and rbp_code_destroy, return
+ * INVALID_ARG.  One host thread at a time per resident handle.
+ * Errors: INVALID_ARG (NULL pointers, parameter ranges), UNSUPPORTED (the
+ * workgroups cannot all be resident), OOM (pinned mailbox), ABORTED (a
+ * barrier wait expired or wait_seconds passed; the kernel has ended, the next
+ * decode relaunches it). */
+typedef struct rbp_resident* rbp_resident_t;
+typedef struct {
+    rbp_coop_params coop;
+    double idle_seconds;
+    double wait_seconds;
+} rbp_resident_params;
+rbp_status rbp_resident_start(rbp_code_t code, const double* priors, const rbp_relay_params* params,
+                              const rbp_resident_params* rp, rbp_resident_t* out);
+/* One shot: syndrome (host, WM words) in; correction (host, WN words),
+ * obs_pred (host, WK words; may be NULL when k = 0) and stats (host, may be
+ * NULL) out, each laid out as one row of rbp_decode's outputs.  Blocks until
+ * the shot is decoded. */
+rbp_status rbp_resident_decode(rbp_resident_t r, const uint32_t* syndrome, uint32_t* correction, uint32_t* obs_pred,
+                               rbp_shot_stats* stats);
+/* Shots decoded so far, kernel launches so far (1 + relaunches after idle or
+ * aborted ends), and whether the kernel is running now (any may be NULL). */
+rbp_status rbp_resident_info(rbp_resident_t r, uint64_t* shots, int32_t* launches, int32_t* running);
+/* Ends the kernel (after the shot it is decoding, if any), waits for it and
+ * frees the handle and its mailbox.  NULL is a no-op. */
+rbp_status rbp_resident_stop(rbp_resident_t r);
+
 /* Debug trace of one shot: the marginals M (float[N]) and check-to-variable
  * messages (float[nnz], CSC edge order of H) right after iteration t (>= 1) of
  * leg `leg` of phase `phase` (0 plain Relay-BP, 1 proposal leg).  syndrome_dev

@@ -124,6 +124,7 @@ struct rbp_code {
     rbp::DevBuf cvar;                   // int32, layout of rposp: LDS address of each row edge's marginal
     rbp::DevBuf vrec;                   // uint32[S]: 16 * row position + edge code in the row, per edge slot
     rbp::DevBuf r1rec;                  // uint4[64 GR]: first-iteration records of a plain leg (per priors)
+    int32_t residents = 0;              // resident decoders running on this handle
     int32_t coop_phantom = 0;           // test hook: extra barrier arrivals that never come
     rbp::LaunchCfg cfg;
 };

@@ -20,9 +20,12 @@
 //                      weight, so convergence and solution weights cost no extra
 //                      sweep or reduction.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -2184,8 +2187,25 @@ __global__ void first_record_kernel(const int32_t* row_ptr, const int32_t* col_i
 constexpr int kCoopLpr = 8;
 
 struct CoopShared {
-    unsigned int abort, xmask, pad0, pad1;  // xmask: XCDs of the participants
+    unsigned int abort, xmask;  // xmask: XCDs of the participants
+    unsigned int go;            // resident mode: ((shot + 1) mod 2^30) << 2 | decision, from rank 0
+    unsigned int pad;
 };
+
+// Resident mode: the mailbox in fine-grained (coherent) pinned host memory
+// through which the host hands the resident kernel one shot at a time.  The
+// header is followed by the shot's syndrome [WM words], correction [WN],
+// observable prediction [WK] and statistics record, at offsets the launch
+// carries in m.syn, m.corr, m.obsp and stats.
+struct ResidentBox {
+    unsigned long long published;  // host: shots handed over so far (shot s is decoded once published > s)
+    unsigned long long done;       // kernel: shots whose outputs are written
+    unsigned int stop;             // host: 1 = end at the next wait
+    unsigned int state;            // kernel: kResident* below
+    unsigned int pad[10];
+};
+static_assert(sizeof(ResidentBox) == 64, "mailbox header is one 64-byte line");
+constexpr unsigned kResidentRunning = 1, kResidentStopped = 2, kResidentIdle = 3, kResidentAborted = 4;
 
 struct CoopLaunch {
     DecodeModel m;
@@ -2206,6 +2226,11 @@ struct CoopLaunch {
     int32_t force_device;  // device-scope fences even on one XCD (for comparison)
     int32_t T0, Tr, R, S, crit;
     int32_t off_sig, off_sigp, off_obs, off_misc;
+    // resident mode only
+    ResidentBox* box;
+    uint64_t res_start;   // index of the first shot this launch waits for
+    uint64_t res_idle;    // clock ticks rank 0 waits for a shot before the launch ends itself
+    uint64_t res_grace;   // further ticks the other workgroups wait for rank 0's decision
 };
 
 struct CoopMisc {
@@ -2289,7 +2314,74 @@ __device__ __forceinline__ T coop_total(const T* v, int n, int lane) {
     return acc;
 }
 
-template <int RD>
+// Resident mode: whether shot s is decoded (true) or the launch ends.  Rank 0
+// polls the mailbox (system-scope loads of host memory) until the host has
+// published shot s, asked to stop, or res_idle ticks have passed; it records
+// an ending in the mailbox and hands its decision, tagged with the shot, to
+// the other workgroups through device memory.  They wait for it at most
+// res_idle + res_grace ticks (then the launch aborts), so every wait ends.
+// All of these loads and stores are relaxed: the only data that crosses with
+// them is the syndrome, which is read with system-scope loads that bypass the
+// caches, so no acquire is needed, and an acquire at system scope would
+// invalidate the L2 that holds the model's tables on every poll.
+__device__ __forceinline__ bool resident_next(const CoopLaunch& a, int rank, uint64_t s, CoopMisc* ms) {
+    if (threadIdx.x == 0) {
+        ResidentBox* box = a.box;
+        const unsigned want = (unsigned)((s + 1) & 0x3fffffffu);
+        const uint64_t t0 = wall_clock64();
+        unsigned dec = 0;
+        if (rank == 0) {
+            for (;;) {
+                const unsigned long long pub =
+                    __hip_atomic_load(&box->published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                if (pub > s) {
+                    dec = kResidentRunning;
+                    break;
+                }
+                if (__hip_atomic_load(&box->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+                    dec = kResidentStopped;
+                    break;
+                }
+                if (wall_clock64() - t0 > a.res_idle) {
+                    dec = kResidentIdle;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            if (dec != kResidentRunning)
+                __hip_atomic_store(&box->state, dec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&a.sh->go, (want << 2) | dec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            for (;;) {
+                const unsigned g = __hip_atomic_load(&a.sh->go, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((g >> 2) == want) {
+                    dec = g & 3u;
+                    break;
+                }
+                if (wall_clock64() - t0 > a.res_idle + a.res_grace) {
+                    dec = kResidentAborted;
+                    atomicExch(&a.sh->abort, 1u);
+                    __hip_atomic_store(&box->state, dec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        ms->flag = (int)dec;
+    }
+    __syncthreads();
+    // (ms->flag is next written inside a grid barrier, after a __syncthreads
+    // that every thread reaches only after this read)
+    return ms->flag == (int)kResidentRunning;
+}
+
+// One grid-synchronous single-shot decoder.  RES = false: the `shots` shots of
+// the launch's arrays in turn.  RES = true (resident mode): shots handed over
+// one at a time through the mailbox, from res_start on, until the host stops
+// the launch or none comes for res_idle ticks; the syndrome is read from and
+// the outputs written to the mailbox (host memory, system scope), and rank 0
+// raises `done` once a shot's outputs are visible to the host.
+template <int RD, bool RES>
 __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch a) {
     extern __shared__ __align__(16) unsigned char smem[];
     if (blockIdx.x % (unsigned)a.stride) return;
@@ -2310,14 +2402,26 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
     const unsigned nflags = a.arrivals;
     unsigned gen = 0;
     const int WM = m.WM, WN = m.WN;
+    // a grid barrier; in resident mode an expired wait is also recorded in the mailbox
+    auto sync = [&](bool loc) -> bool {
+        if (grid_sync(sh, a.flags, rank, nflags, gen, a.spin_limit, ms, loc)) return true;
+        if constexpr (RES) {
+            if (tid == 0) __hip_atomic_store(&a.box->state, kResidentAborted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        return false;
+    };
     // which XCDs the participants run on (hardware register XCC_ID, bits 3:0)
     if (tid == 0) atomicOr(&sh->xmask, 1u << (__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u));
-    if (!grid_sync(sh, a.flags, rank, nflags, gen, a.spin_limit, ms, false)) return;
+    if (!sync(false)) return;
     const bool local =
         __popc(__hip_atomic_load(&sh->xmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 1 && !a.force_device;
 
-    for (uint64_t s = 0; s < a.shots; ++s) {
+    for (uint64_t s = RES ? a.res_start : 0; RES || s < a.shots; ++s) {
+        if constexpr (RES) {
+            if (!resident_next(a, rank, s, ms)) return;
+        }
         const uint64_t t_start = wall_clock64();
+        const uint64_t row = RES ? 0 : s;  // the mailbox holds one shot
         // ---- set-up: every workgroup keeps the syndrome and its row-group
         // ballots in LDS; rank 0 resets the shared arrays
         if (tid == 0) {
@@ -2330,7 +2434,8 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
         __syncthreads();
         int pc = 0;
         for (int w = tid; w < WM; w += nth) {
-            const uint32_t v = m.syn[s * WM + w];
+            const uint32_t v = RES ? __hip_atomic_load(m.syn + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)
+                                   : m.syn[s * WM + w];
             sig[w] = v;
             pc += __popc(v);
             if (rank == 0) a.par[w] = v;
@@ -2353,7 +2458,7 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
             }
         }
         for (int g = gw; g < m.GV; g += GW) Mg[g * 64 + lane] = ldg(m.lamp, (uint32_t)(g * 64 + lane));
-        if (!grid_sync(sh, a.flags, rank, nflags, gen, a.spin_limit, ms, local)) return;
+        if (!sync(local)) return;
 
         int nconv = 0, legs = 0, iters = 0, path = 0;
         bool x_mu1 = false, have_best = false;
@@ -2399,7 +2504,7 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
                     }
                     // after the check sweep (or, when it is skipped, after every
                     // workgroup has read the previous count and weight)
-                    if (!grid_sync(sh, a.flags, rank, nflags, gen, a.spin_limit, ms, local)) return;
+                    if (!sync(local)) return;
                     int dcount = 0;
                     double dW = 0.0;
                     for (int g = gw; g < m.GV; g += GW) {
@@ -2431,7 +2536,7 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
                         ms->dcnt = 0;
                         ms->dW = 0.0;
                     }
-                    if (!grid_sync(sh, a.flags, rank, nflags, gen, a.spin_limit, ms, local)) return;
+                    if (!sync(local)) return;
                     ++iters;
                     const int cnt = coop_total(a.cnt, a.nwg, lane);
                     if (base + uniform(cnt) == 0) {
@@ -2445,7 +2550,7 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
                             extrinsic_dispatch(X, 4u * ((uint32_t)uniform(gi.x) + (uint32_t)lane), uniform(gi.y),
                                                Mg[pp]);
                         }
-                        if (!grid_sync(sh, a.flags, rank, nflags, gen, a.spin_limit, ms, local)) return;
+                        if (!sync(local)) return;
                         x_mu1 = false;
                     }
                 }
@@ -2483,11 +2588,11 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
                 }
             }
         }
-        if (!grid_sync(sh, a.flags, rank, nflags, gen, a.spin_limit, ms, local)) return;
+        if (!sync(local)) return;
         if (rank == 0) {
             for (int w = tid; w < WN; w += nth) {
                 const uint32_t bits = __hip_atomic_load(a.best + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                m.corr[s * WN + w] = bits;
+                m.corr[row * WN + w] = bits;
                 uint32_t b = bits;
                 while (b) {
                     const int j = w * 32 + __builtin_ctz(b);
@@ -2500,7 +2605,7 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
             }
             __syncthreads();
             if (m.obsp)
-                for (int w = tid; w < m.WK; w += nth) m.obsp[s * m.WK + w] = obw[w];
+                for (int w = tid; w < m.WK; w += nth) m.obsp[row * m.WK + w] = obw[w];
             if (a.stats && tid == 0) {
                 rbp_shot_stats st;
                 st.converged = have_best ? 1 : 0;
@@ -2513,11 +2618,22 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
                 st.reserved3 = 0;
                 st.t_start = t_start;
                 st.t_end = wall_clock64();
-                a.stats[s] = st;
+                a.stats[row] = st;
+            }
+            if constexpr (RES) {
+                // every thread's mailbox stores have left the CU (they sit in this
+                // XCD's L2, which rank 0's waves share); then one system-scope
+                // release (an L2 write-back, no invalidation) publishes them with
+                // `done`
+                coop_release(true);
+                __syncthreads();
+                if (tid == 0)
+                    __hip_atomic_store(&a.box->done, (unsigned long long)(s + 1), __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
             }
         }
         // the next shot's set-up rewrites the shared arrays
-        if (!grid_sync(sh, a.flags, rank, nflags, gen, a.spin_limit, ms, local)) return;
+        if (!sync(local)) return;
     }
 }
 
@@ -2548,6 +2664,7 @@ static rbp_status ensure_llr(rbp_code* c, const double* priors, hipStream_t stre
     if (c->lam.p && c->lam_key.size() == (size_t)c->N &&
         std::memcmp(c->lam_key.data(), priors, sizeof(double) * c->N) == 0)
         return RBP_OK;
+    if (c->residents) return fail(RBP_ERR_INVALID_ARG, "a resident decoder runs on this code with other priors; stop it first");
     std::vector<float> lam(c->N), lamp(c->Np, 0.0f);
     for (int j = 0; j < c->N; ++j) lam[j] = (float)std::log((1.0 - priors[j]) / priors[j]);
     for (int p = 0; p < c->Np; ++p)
@@ -2615,6 +2732,8 @@ static rbp_status ensure_gamma(rbp_code* c, const rbp_relay_params* p, hipStream
     if (c->gtab.p && c->gtab_R == R && c->gtab_seed == p->gamma_seed && c->gtab_lo == p->gamma_min &&
         c->gtab_hi == p->gamma_max)
         return RBP_OK;
+    if (c->residents)
+        return fail(RBP_ERR_INVALID_ARG, "a resident decoder runs on this code with other relay parameters; stop it first");
     const int64_t total = (int64_t)c->Np * std::max(R, 0);
     RBP_HIP_CHECK(hipStreamSynchronize(stream));
     // at least one row: the first leg reads (and discards) row 0
@@ -2639,6 +2758,8 @@ static rbp_status ensure_lam_gamma(rbp_code* c, const rbp_relay_params* p, hipSt
     if (c->lg.p && c->lg_lam_gen == c->lam_gen && c->lg_gtab_gen == c->gtab_gen && c->lg_gamma0 == p->gamma0 &&
         c->lg_R == R)
         return RBP_OK;
+    if (c->residents)
+        return fail(RBP_ERR_INVALID_ARG, "a resident decoder runs on this code with other relay parameters; stop it first");
     const int64_t total = (int64_t)c->Np * (R + 1);
     RBP_HIP_CHECK(hipStreamSynchronize(stream));
     rbp_status st = c->lg.reserve(sizeof(float2) * total);
@@ -3279,6 +3400,7 @@ rbp_status rbp_code_create(int32_t M, int32_t N, const int32_t* col_ptr, const i
 
 rbp_status rbp_code_destroy(rbp_code_t c) {
     if (!c) return RBP_OK;
+    if (c->residents) return fail(RBP_ERR_INVALID_ARG, "a resident decoder runs on this code; stop it first");
     (void)hipDeviceSynchronize();
     for (DevBuf* b : {&c->row_ptr, &c->col_idx, &c->col_ptr, &c->csc_row, &c->rgrp, &c->rposp, &c->rposw, &c->rord, &c->vgrp,
                       &c->vord, &c->vdeg, &c->scheck, &c->scsc, &c->orow_ptr, &c->ocol_idx, &c->ocol_ptr,
@@ -3459,37 +3581,28 @@ rbp_status rbp_decode_noalloc(rbp_code_t c, const double* priors, const uint32_t
     return launch_decode(cs, 1, a, shots, stream, reinterpret_cast<unsigned long long*>(sp));
 }
 
-rbp_status rbp_decode_coop(rbp_code_t c, const double* priors, const uint32_t* syndromes, uint64_t shots,
-                           const rbp_relay_params* params, const rbp_coop_params* coop, uint32_t* corrections,
-                           uint32_t* obs_pred, rbp_shot_stats* stats, void* stream_) {
-    if (!c) return fail(RBP_ERR_INVALID_ARG, "code is NULL");
-    rbp_status st = check_params(params);
-    if (st) return st;
-    if (!syndromes || !corrections) return fail(RBP_ERR_INVALID_ARG, "syndromes/corrections is NULL");
-    if (c->k > 0 && !obs_pred) return fail(RBP_ERR_INVALID_ARG, "obs_pred is NULL");
-    st = check_priors(priors, c->N);
-    if (st) return st;
-    rbp_coop_params cp = {0, 0, 0, 0u, 0};
-    if (coop) cp = *coop;
-    if (cp.workgroups < 0 || cp.stride < 0 || cp.waves < 0 || cp.waves > 8)
-        return fail(RBP_ERR_INVALID_ARG, "coop: workgroups, stride >= 0, waves in 0..8");
-    if (shots == 0) return RBP_OK;
-    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
-    st = ensure_llr(c, priors, stream);
-    if (!st) st = ensure_gamma(c, params, stream);
-    if (!st) st = ensure_lam_gamma(c, params, stream);
-    if (st) return st;
+// Launch shape, scratch layout and kernel of the latency mode, shared by
+// rbp_decode_coop and the resident decoder.  Fills everything in `a` but the
+// model (a.m), the shot range and the outputs; (re)serves the shot state in
+// `xbuf` and the parity / best-solution / barrier words in `scratch`.
+struct CoopPlan {
+    CoopLaunch a;
+    int64_t grid = 0;
+    int waves = 0, lds = 0;
+    int clear_words = 0;  // barrier words cleared before each launch, from a.sh on
+    const void* kern = nullptr;
+};
+
+static rbp_status coop_plan(rbp_code* c, const rbp_relay_params* params, const rbp_coop_params& cp, bool resident,
+                            DevBuf& xbuf, DevBuf& scratch, CoopPlan& P) {
     const int cus = std::max(c->num_cus, 1);
     const int waves = cp.waves > 0 ? cp.waves : 8;
     int nwg = cp.workgroups > 0 ? cp.workgroups : std::max(cus / 8, 1);
     nwg = std::min(nwg, cus);
     int stride = cp.stride > 0 ? cp.stride : (nwg * 8 <= cus ? 8 : 1);
     if ((int64_t)nwg * stride > cus) stride = 1;
-    CoopLaunch a;
+    CoopLaunch& a = P.a;
     std::memset(&a, 0, sizeof(a));
-    a.m = model_of(c, syndromes, corrections, obs_pred);
-    a.shots = shots;
-    a.stats = stats;
     a.Smax = c->S;
     a.nwg = nwg;
     a.stride = stride;
@@ -3507,11 +3620,11 @@ rbp_status rbp_decode_coop(rbp_code_t c, const double* priors, const uint32_t* s
                   o_sh = o_best + align16(4 * (int64_t)WN), o_flags = o_sh + (int64_t)sizeof(CoopShared),
                   o_cnt = o_flags + align16(4 * (int64_t)a.arrivals), o_wsum = o_cnt + align16(4 * (int64_t)nwg),
                   coop_bytes = o_wsum + 8 * (int64_t)nwg;
-    st = c->gstate.reserve(sizeof(float) * (size_t)xfloats);
-    if (!st) st = c->coop.reserve((size_t)coop_bytes);
+    rbp_status st = xbuf.reserve(sizeof(float) * (size_t)xfloats);
+    if (!st) st = scratch.reserve((size_t)coop_bytes);
     if (st) return st;
-    a.X = c->gstate.as<float>();
-    char* cb = reinterpret_cast<char*>(c->coop.p);
+    a.X = xbuf.as<float>();
+    char* cb = reinterpret_cast<char*>(scratch.p);
     a.par = reinterpret_cast<uint32_t*>(cb + o_par);
     a.bestp = reinterpret_cast<uint32_t*>(cb + o_bestp);
     a.best = reinterpret_cast<uint32_t*>(cb + o_best);
@@ -3519,6 +3632,7 @@ rbp_status rbp_decode_coop(rbp_code_t c, const double* priors, const uint32_t* s
     a.flags = reinterpret_cast<uint32_t*>(cb + o_flags);
     a.cnt = reinterpret_cast<int32_t*>(cb + o_cnt);
     a.wsum = reinterpret_cast<double*>(cb + o_wsum);
+    P.clear_words = (int)((o_cnt - o_sh) / 4);
     int64_t off = 0;
     a.off_sig = (int)off;
     off += align16(4 * (int64_t)WM);
@@ -3530,7 +3644,11 @@ rbp_status rbp_decode_coop(rbp_code_t c, const double* priors, const uint32_t* s
     off += align16(sizeof(CoopMisc));
     if (off > kMaxLds) return fail(RBP_ERR_UNSUPPORTED, "syndrome bits do not fit in LDS");
     const int lds = (int)off;
-    void (*kern)(CoopLaunch) = c->max_stored_row_deg <= 12 ? relay_bp_coop_kernel<12> : relay_bp_coop_kernel<32>;
+    void (*kern)(CoopLaunch);
+    if (resident)
+        kern = c->max_stored_row_deg <= 12 ? relay_bp_coop_kernel<12, true> : relay_bp_coop_kernel<32, true>;
+    else
+        kern = c->max_stored_row_deg <= 12 ? relay_bp_coop_kernel<12, false> : relay_bp_coop_kernel<32, false>;
     RBP_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                       lds));
     int per_cu = 0;
@@ -3539,18 +3657,256 @@ rbp_status rbp_decode_coop(rbp_code_t c, const double* priors, const uint32_t* s
     const int64_t grid = (int64_t)nwg * stride;
     if (per_cu < 1 || grid > (int64_t)per_cu * cus)
         return fail(RBP_ERR_UNSUPPORTED, "coop: the workgroups cannot all be resident");
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, stream, reinterpret_cast<uint32_t*>(a.sh),
-                       (int)((o_cnt - o_sh) / 4));
+    P.grid = grid;
+    P.waves = waves;
+    P.lds = lds;
+    P.kern = reinterpret_cast<const void*>(kern);
+    return RBP_OK;
+}
+
+static rbp_status coop_check(const rbp_coop_params& cp) {
+    if (cp.workgroups < 0 || cp.stride < 0 || cp.waves < 0 || cp.waves > 8)
+        return fail(RBP_ERR_INVALID_ARG, "coop: workgroups, stride >= 0, waves in 0..8");
+    return RBP_OK;
+}
+
+// clears the barrier words, then launches the plan's kernel cooperatively
+static rbp_status coop_launch(CoopPlan& P, hipStream_t stream) {
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, stream, reinterpret_cast<uint32_t*>(P.a.sh),
+                       P.clear_words);
     RBP_HIP_CHECK(hipGetLastError());
-    void* args[] = {&a};
-    RBP_HIP_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3((unsigned)grid),
-                                             dim3(64 * waves), args, (unsigned)lds, stream));
+    void* args[] = {&P.a};
+    RBP_HIP_CHECK(hipLaunchCooperativeKernel(P.kern, dim3((unsigned)P.grid), dim3(64 * P.waves), args,
+                                             (unsigned)P.lds, stream));
+    return RBP_OK;
+}
+
+rbp_status rbp_decode_coop(rbp_code_t c, const double* priors, const uint32_t* syndromes, uint64_t shots,
+                           const rbp_relay_params* params, const rbp_coop_params* coop, uint32_t* corrections,
+                           uint32_t* obs_pred, rbp_shot_stats* stats, void* stream_) {
+    if (!c) return fail(RBP_ERR_INVALID_ARG, "code is NULL");
+    rbp_status st = check_params(params);
+    if (st) return st;
+    if (!syndromes || !corrections) return fail(RBP_ERR_INVALID_ARG, "syndromes/corrections is NULL");
+    if (c->k > 0 && !obs_pred) return fail(RBP_ERR_INVALID_ARG, "obs_pred is NULL");
+    st = check_priors(priors, c->N);
+    if (st) return st;
+    rbp_coop_params cp = {0, 0, 0, 0u, 0};
+    if (coop) cp = *coop;
+    st = coop_check(cp);
+    if (st) return st;
+    if (shots == 0) return RBP_OK;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    st = ensure_llr(c, priors, stream);
+    if (!st) st = ensure_gamma(c, params, stream);
+    if (!st) st = ensure_lam_gamma(c, params, stream);
+    if (st) return st;
+    CoopPlan P;
+    st = coop_plan(c, params, cp, false, c->gstate, c->coop, P);
+    if (st) return st;
+    P.a.m = model_of(c, syndromes, corrections, obs_pred);
+    P.a.shots = shots;
+    P.a.stats = stats;
+    st = coop_launch(P, stream);
+    if (st) return st;
     // the launch's end: an expired barrier wait is reported as ABORTED
     unsigned int aborted = 0;
-    RBP_HIP_CHECK(hipMemcpyAsync(&aborted, &a.sh->abort, sizeof(aborted), hipMemcpyDeviceToHost, stream));
+    RBP_HIP_CHECK(hipMemcpyAsync(&aborted, &P.a.sh->abort, sizeof(aborted), hipMemcpyDeviceToHost, stream));
     RBP_HIP_CHECK(hipStreamSynchronize(stream));
     if (aborted) return fail(RBP_ERR_ABORTED, "latency mode: a barrier wait expired; later shots were not decoded");
     return RBP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Resident decoder: the latency-mode kernel launched once and fed one shot at
+// a time through a mailbox in pinned host memory (ResidentBox).
+// ---------------------------------------------------------------------------
+struct rbp_resident {
+    rbp_code* c = nullptr;
+    hipStream_t stream = nullptr;
+    char* host = nullptr;  // the mailbox (hipHostMalloc, coherent)
+    size_t bytes = 0;
+    int64_t o_syn = 0, o_corr = 0, o_obs = 0, o_stats = 0;
+    rbp::DevBuf x, scratch;
+    CoopPlan P;
+    uint64_t next = 0;     // shots handed over (and finished) so far
+    int32_t launches = 0;
+    bool running = false;
+    double wait_s = 60.0;
+    rbp::ResidentBox* box() { return reinterpret_cast<rbp::ResidentBox*>(host); }
+};
+
+static rbp_status resident_launch(rbp_resident* r) {
+    ResidentBox* b = r->box();
+    __atomic_store_n(&b->published, (unsigned long long)r->next, __ATOMIC_RELAXED);
+    __atomic_store_n(&b->done, (unsigned long long)r->next, __ATOMIC_RELAXED);
+    __atomic_store_n(&b->stop, 0u, __ATOMIC_RELAXED);
+    __atomic_store_n(&b->state, 0u, __ATOMIC_RELEASE);
+    r->P.a.res_start = r->next;
+    rbp_status st = coop_launch(r->P, r->stream);
+    if (st) return st;
+    r->running = true;
+    ++r->launches;
+    return RBP_OK;
+}
+
+// ends the kernel (it finishes the shot it is decoding, if any) and waits for it
+static rbp_status resident_halt(rbp_resident* r) {
+    if (!r->running) return RBP_OK;
+    __atomic_store_n(&r->box()->stop, 1u, __ATOMIC_RELEASE);
+    r->running = false;
+    RBP_HIP_CHECK(hipStreamSynchronize(r->stream));
+    r->next = __atomic_load_n(&r->box()->done, __ATOMIC_ACQUIRE);
+    return RBP_OK;
+}
+
+rbp_status rbp_resident_start(rbp_code_t c, const double* priors, const rbp_relay_params* params,
+                              const rbp_resident_params* rp, rbp_resident_t* out) {
+    if (!c || !out) return fail(RBP_ERR_INVALID_ARG, "code/out is NULL");
+    *out = nullptr;
+    rbp_status st = check_params(params);
+    if (st) return st;
+    st = check_priors(priors, c->N);
+    if (st) return st;
+    rbp_resident_params q;
+    std::memset(&q, 0, sizeof(q));
+    if (rp) q = *rp;
+    st = coop_check(q.coop);
+    if (st) return st;
+    if (!(q.idle_seconds >= 0.0 && q.idle_seconds <= 3600.0) || !(q.wait_seconds >= 0.0 && q.wait_seconds <= 3600.0))
+        return fail(RBP_ERR_INVALID_ARG, "resident: idle_seconds and wait_seconds in [0, 3600]");
+    int dev = 0, khz = 0;
+    RBP_HIP_CHECK(hipGetDevice(&dev));
+    RBP_HIP_CHECK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) return fail(RBP_ERR_UNSUPPORTED, "resident: device wall clock rate unknown");
+    std::unique_ptr<rbp_resident> r(new (std::nothrow) rbp_resident());
+    if (!r) return fail(RBP_ERR_OOM, "resident: handle");
+    r->c = c;
+    r->wait_s = q.wait_seconds > 0.0 ? q.wait_seconds : 60.0;
+    // its own non-blocking stream, at the default priority: the resident kernel
+    // never holds up work on the legacy default stream
+    RBP_HIP_CHECK(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking));
+    auto undo = [&](rbp_status e) {
+        if (r->stream) (void)hipStreamSynchronize(r->stream);
+        r->x.release();
+        r->scratch.release();
+        if (r->host) (void)hipHostFree(r->host);
+        if (r->stream) (void)hipStreamDestroy(r->stream);
+        return e;
+    };
+    st = ensure_llr(c, priors, r->stream);
+    if (!st) st = ensure_gamma(c, params, r->stream);
+    if (!st) st = ensure_lam_gamma(c, params, r->stream);
+    if (!st) st = coop_plan(c, params, q.coop, true, r->x, r->scratch, r->P);
+    if (st) return undo(st);
+    const int WM = ceil_div(c->M, 32), WN = ceil_div(c->N, 32), WK = std::max(ceil_div(c->k, 32), 1);
+    r->o_syn = (int64_t)sizeof(ResidentBox);
+    r->o_corr = r->o_syn + (4 * (int64_t)WM + 63) / 64 * 64;
+    r->o_obs = r->o_corr + (4 * (int64_t)WN + 63) / 64 * 64;
+    r->o_stats = r->o_obs + (4 * (int64_t)WK + 63) / 64 * 64;
+    r->bytes = (size_t)(r->o_stats + 64);
+    void* h = nullptr;
+    if (hipHostMalloc(&h, r->bytes, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess || !h) {
+        (void)hipGetLastError();
+        return undo(fail(RBP_ERR_OOM, "resident: pinned mailbox"));
+    }
+    r->host = reinterpret_cast<char*>(h);
+    std::memset(r->host, 0, r->bytes);
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess || !d) {
+        (void)hipGetLastError();
+        return undo(fail(RBP_ERR_HIP, "resident: no device view of the mailbox"));
+    }
+    char* db = reinterpret_cast<char*>(d);
+    CoopLaunch& a = r->P.a;
+    a.m = model_of(c, reinterpret_cast<const uint32_t*>(db + r->o_syn), reinterpret_cast<uint32_t*>(db + r->o_corr),
+                   reinterpret_cast<uint32_t*>(db + r->o_obs));
+    a.stats = reinterpret_cast<rbp_shot_stats*>(db + r->o_stats);
+    a.box = reinterpret_cast<ResidentBox*>(db);
+    const double ticks_per_s = 1e3 * (double)khz;
+    a.res_idle = (uint64_t)((q.idle_seconds > 0.0 ? q.idle_seconds : 1.0) * ticks_per_s);
+    a.res_grace = (uint64_t)ticks_per_s;
+    st = resident_launch(r.get());
+    if (st) return undo(st);
+    ++c->residents;
+    *out = r.release();
+    return RBP_OK;
+}
+
+rbp_status rbp_resident_decode(rbp_resident_t r, const uint32_t* syndrome, uint32_t* correction, uint32_t* obs_pred,
+                               rbp_shot_stats* stats) {
+    if (!r) return fail(RBP_ERR_INVALID_ARG, "resident handle is NULL");
+    if (!syndrome || !correction) return fail(RBP_ERR_INVALID_ARG, "syndrome/correction is NULL");
+    rbp_code* c = r->c;
+    if (c->k > 0 && !obs_pred) return fail(RBP_ERR_INVALID_ARG, "obs_pred is NULL");
+    const int WM = ceil_div(c->M, 32), WN = ceil_div(c->N, 32), WK = ceil_div(c->k, 32);
+    rbp_status st;
+    if (!r->running) {
+        st = resident_launch(r);
+        if (st) return st;
+    }
+    ResidentBox* b = r->box();
+    const uint64_t s = r->next;
+    std::memcpy(r->host + r->o_syn, syndrome, 4 * (size_t)WM);
+    __atomic_store_n(&b->published, (unsigned long long)(s + 1), __ATOMIC_RELEASE);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint64_t k = 1;; ++k) {
+        if (__atomic_load_n(&b->done, __ATOMIC_ACQUIRE) > s) break;
+        const unsigned state = __atomic_load_n(&b->state, __ATOMIC_ACQUIRE);
+        if (state == kResidentIdle) {
+            // the kernel ended for want of a shot before it saw this one (it ends
+            // only while waiting for shot `done`, and done <= s): launch it again
+            r->running = false;
+            RBP_HIP_CHECK(hipStreamSynchronize(r->stream));
+            st = resident_launch(r);
+            if (st) return st;
+            __atomic_store_n(&b->published, (unsigned long long)(s + 1), __ATOMIC_RELEASE);
+            continue;
+        }
+        if (state == kResidentAborted || state == kResidentStopped) {
+            st = resident_halt(r);
+            if (st) return st;
+            return fail(RBP_ERR_ABORTED, "resident: the kernel ended (a barrier wait expired); the shot was not decoded");
+        }
+        if ((k & 1023u) == 0) {
+            const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (el > r->wait_s) {
+                st = resident_halt(r);
+                if (st) return st;
+                return fail(RBP_ERR_ABORTED, "resident: no result within wait_seconds; the kernel was stopped");
+            }
+        }
+        __builtin_ia32_pause();
+    }
+    std::memcpy(correction, r->host + r->o_corr, 4 * (size_t)WN);
+    if (obs_pred && WK > 0) std::memcpy(obs_pred, r->host + r->o_obs, 4 * (size_t)WK);
+    if (stats) std::memcpy(stats, r->host + r->o_stats, sizeof(rbp_shot_stats));
+    r->next = s + 1;
+    return RBP_OK;
+}
+
+rbp_status rbp_resident_info(rbp_resident_t r, uint64_t* shots, int32_t* launches, int32_t* running) {
+    if (!r) return fail(RBP_ERR_INVALID_ARG, "resident handle is NULL");
+    if (shots) *shots = r->next;
+    if (launches) *launches = r->launches;
+    if (running) {
+        const unsigned state = __atomic_load_n(&r->box()->state, __ATOMIC_ACQUIRE);
+        *running = r->running && state != kResidentIdle && state != kResidentAborted && state != kResidentStopped;
+    }
+    return RBP_OK;
+}
+
+rbp_status rbp_resident_stop(rbp_resident_t r) {
+    if (!r) return RBP_OK;
+    rbp_status st = resident_halt(r);
+    (void)hipStreamSynchronize(r->stream);
+    r->x.release();
+    r->scratch.release();
+    if (r->host) (void)hipHostFree(r->host);
+    (void)hipStreamDestroy(r->stream);
+    --r->c->residents;
+    delete r;
+    return st;
 }
 
 rbp_status rbp_test_set_coop_phantom(rbp_code_t c, int32_t phantom) {

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "librbp.so")
 LIB_MLP_F32_PATH = os.path.join(HERE, "librbp_mlp_f32.so")
 
 RBP_OK = 0
+RBP_ERR_INVALID_ARG = -1
 RBP_ERR_ABORTED = -6
 _ERRNAMES = {-1: "INVALID_ARG", -2: "SHAPE", -3: "UNSUPPORTED", -4: "OOM", -5: "HIP", -6: "ABORTED"}
 
@@ -102,6 +103,10 @@ class CoopParams:
 
     def c(self) -> CoopParamsC:
         return CoopParamsC(self.workgroups, self.stride, self.waves, self.spin_limit, self.device_fences)
+
+
+class ResidentParamsC(ctypes.Structure):
+    _fields_ = [("coop", CoopParamsC), ("idle_seconds", ctypes.c_double), ("wait_seconds", ctypes.c_double)]
 
 
 _lib = None
@@ -186,6 +191,10 @@ def _load(path: str, required: bool):
         "rbp_mlp_save": [vp, ctypes.c_char_p],
         "rbp_mlp_load": [vp, ctypes.c_char_p],
         "rbp_test_set_coop_phantom": [vp, i32],
+        "rbp_resident_start": [vp, vp, P(RelayParamsC), P(ResidentParamsC), P(vp)],
+        "rbp_resident_decode": [vp, vp, vp, vp, vp],
+        "rbp_resident_info": [vp, P(u64), P(i32), P(i32)],
+        "rbp_resident_stop": [vp],
     }
     sigs["rbp_measure_lds_bandwidth"] = [i32, ctypes.POINTER(ctypes.c_double)]
     for name, args in sigs.items():
@@ -263,6 +272,7 @@ class Code:
         check(lib().rbp_code_create(self.M, self.N, cp.ctypes.data, ri.ctypes.data, self.k, ocp.ctypes.data,
                                     ori.ctypes.data, ctypes.byref(h)))
         self.h = h
+        self._residents = weakref.WeakSet()
         _live.add(self)
 
     @classmethod
@@ -271,6 +281,8 @@ class Code:
 
     def close(self):
         if getattr(self, "h", None):
+            for r in list(getattr(self, "_residents", ())):
+                r.close()
             if not _finalized:
                 lib().rbp_code_destroy(self.h)
             self.h = None
@@ -387,6 +399,11 @@ class Code:
         check(lib().rbp_decode_coop(self.h, pr.ctypes.data, _ptr(syndromes), shots, ctypes.byref(prm),
                                     ctypes.byref(cp), _ptr(corr), _ptr(obsp), _ptr(st), _stream(stream)))
         return corr, obsp, st
+
+    def resident(self, priors, params: RelayParams, coop: Optional[CoopParams] = None, idle_seconds: float = 0.0,
+                 wait_seconds: float = 0.0) -> "Resident":
+        """Starts a resident decoder on this code (see Resident)."""
+        return Resident(self, priors, params, coop, idle_seconds, wait_seconds)
 
     def set_coop_phantom(self, phantom: int):
         """Test hook (rbp_test_set_coop_phantom): latency-mode barriers also wait for
@@ -579,6 +596,78 @@ def measure_lds_bandwidth(width_bytes: int = 16) -> float:
     v = ctypes.c_double()
     check(lib().rbp_measure_lds_bandwidth(width_bytes, ctypes.byref(v)))
     return v.value
+
+
+def _host_u32(x, n: int, name: str) -> np.ndarray:
+    """A host array of n uint32 words (numpy, or a CPU tensor) as a contiguous
+    uint32 array; device tensors are refused (the mailbox takes host memory)."""
+    if isinstance(x, torch.Tensor):
+        if x.device.type != "cpu":
+            raise ValueError(f"{name} must be in host memory (got {x.device})")
+        x = x.numpy()
+    a = np.ascontiguousarray(x)
+    if a.dtype == np.int32:
+        a = a.view(np.uint32)
+    if a.dtype != np.uint32:
+        raise TypeError(f"{name} must be uint32 or int32 words (got {a.dtype})")
+    if a.shape != (n,):
+        raise ValueError(f"{name} must have shape ({n},) (got {a.shape})")
+    return a
+
+
+class Resident:
+    """Resident decoder (rbp_resident_*): the latency-mode kernel launched once
+    and fed one shot at a time through a mailbox in pinned host memory, so a
+    shot's latency holds no launch.  decode() takes one host syndrome and
+    returns host arrays; the kernel ends itself after idle_seconds without a
+    shot and is relaunched by the next decode()."""
+
+    def __init__(self, code: "Code", priors, params: RelayParams, coop: Optional[CoopParams] = None,
+                 idle_seconds: float = 0.0, wait_seconds: float = 0.0):
+        self.M, self.N, self.k = code.M, code.N, code.k
+        pr = code._priors(priors)
+        prm = params.c()
+        rp = ResidentParamsC((coop or CoopParams()).c(), float(idle_seconds), float(wait_seconds))
+        h = ctypes.c_void_p()
+        check(lib().rbp_resident_start(code.h, pr.ctypes.data, ctypes.byref(prm), ctypes.byref(rp), ctypes.byref(h)))
+        self.h = h
+        self.code = code
+        code._residents.add(self)
+        _live.add(self)
+
+    def decode(self, syndrome):
+        """One shot: syndrome (words(M) uint32/int32 host words) -> correction
+        (words(N) uint32), observable prediction (max(words(k), 1) uint32) and
+        the statistics record (SHOT_STATS_DTYPE)."""
+        syn = _host_u32(syndrome, words(self.M), "syndrome")
+        corr = np.empty(words(self.N), dtype=np.uint32)
+        obs = np.zeros(max(words(self.k), 1), dtype=np.uint32)
+        st = np.zeros(1, dtype=SHOT_STATS_DTYPE)
+        check(lib().rbp_resident_decode(self.h, syn.ctypes.data, corr.ctypes.data, obs.ctypes.data, st.ctypes.data))
+        return corr, obs, st[0]
+
+    def info(self) -> dict:
+        shots, launches, running = ctypes.c_uint64(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().rbp_resident_info(self.h, ctypes.byref(shots), ctypes.byref(launches), ctypes.byref(running)))
+        return {"shots": shots.value, "launches": launches.value, "running": bool(running.value)}
+
+    def close(self):
+        if getattr(self, "h", None):
+            h, self.h = self.h, None
+            if not _finalized:
+                check(lib().rbp_resident_stop(h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def stats_to_numpy(st: torch.Tensor) -> np.ndarray:
