@@ -386,7 +386,7 @@ def extras(seed: int) -> dict:
     import numpy as np
     import torch
 
-    from paper_2607_27644_amd import circuits, experiments, rbp, stats, workloads
+    from paper_2607_27644_amd import autotune, circuits, experiments, rbp, stats, workloads
     res = {}
     # phenomenological ZSZ-LP-160 (576 x 1952), 10^5 shots per launch
     dem = workloads.workload("phen160")
@@ -428,9 +428,12 @@ def extras(seed: int) -> dict:
                 t0 = time.perf_counter()
                 rd.decode(hs[i])
                 rlat.append(1e6 * (time.perf_counter() - t0))
+        # batched: the launch shape tuned for this DEM (waves per shot, device-memory state)
+        tr = autotune.tune(c, d.H, d.priors, prm, shots=2000, waves=(4, 8, 16), states=(2,), use_cache=False)
         ms, out = experiments._timed(lambda: c.decode(d.priors, s, prm), repeats=2)
         cl[f"{basis}_memory"] = {"dem": [d.M, d.N], "latency_mode_us": stats.percentiles(np.array(lat)),
                                  "resident_us": stats.percentiles(np.array(rlat)),
+                                 "batched_launch": {"waves_per_shot": tr["waves_per_shot"], "state": tr["state"]},
                                  "batched_shots_per_s": 4000 / (ms * 1e-3),
                                  "mean_iters": float(rbp.stats_to_numpy(out[2])["iters"].mean())}
         lat_all += lat

@@ -170,6 +170,27 @@ rbp_status rbp_decode_multi(int32_t n_codes, const rbp_code_t* codes, const doub
                             uint32_t* const* corrections_dev, uint32_t* const* obs_pred_dev,
                             rbp_shot_stats* stats_dev, void* stream);
 
+/* Batched decode of several detector error models, each in a persistent
+ * launch of its own with its own launch shape (the handle's rbp_launch_config:
+ * waves per shot, state, slots), all issued at once on side streams forked
+ * from `stream` and joined back into it (the largest model first), so that
+ * each launch's tail is filled by the others' work (the batched uneven decode
+ * of several codes; one launch over all models, rbp_decode_multi, must size
+ * every slot for the largest model).  Model c decodes shots[c] rows (shots is
+ * a host array; 0 skips the model) of its own arrays syndromes_dev[c],
+ * corrections_dev[c], obs_pred_dev[c] and stats_dev[c] (may be NULL, or hold
+ * NULL entries), exactly as rbp_decode would, with the same params.  Each
+ * handle may appear once.  The side streams (8 per device, non-blocking,
+ * default priority) are created on first use and kept until the process
+ * ends.  Errors as rbp_decode: arguments, priors and tables are checked for
+ * every model before anything is launched; a launch shape that cannot run
+ * (UNSUPPORTED) stops the issue at that model, and the launches issued
+ * before it still complete before later work on `stream`. */
+rbp_status rbp_decode_each(int32_t n_codes, const rbp_code_t* codes, const double* const* priors,
+                           const uint64_t* shots, const uint32_t* const* syndromes_dev,
+                           const rbp_relay_params* params, uint32_t* const* corrections_dev,
+                           uint32_t* const* obs_pred_dev, rbp_shot_stats* const* stats_dev, void* stream);
+
 /* Block failures of a decoded batch (paper Sec. 6.1: a shot fails when any
  * logical observable is predicted wrong or the decoder did not converge):
  * *count_dev (uint64, device) += number of shots s with obs_pred_dev[s] !=

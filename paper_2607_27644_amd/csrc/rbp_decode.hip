@@ -3139,6 +3139,24 @@ static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 constexpr int kMaxDevices = 64;
 static unsigned char* g_scratch[kMaxDevices];
+// Side streams of rbp_decode_each, kMaxModels per device, created on first
+// use (non-blocking, default priority) and kept until the process ends.
+static std::mutex g_side_mu;
+static std::vector<std::vector<hipStream_t>> g_side;
+
+static rbp_status side_streams(int dev, hipStream_t** out) {
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    if ((int)g_side.size() <= dev) g_side.resize(dev + 1);
+    std::vector<hipStream_t>& v = g_side[dev];
+    while ((int)v.size() < kMaxModels) {
+        hipStream_t s = nullptr;
+        RBP_HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        v.push_back(s);
+    }
+    *out = v.data();
+    return RBP_OK;
+}
+
 static std::mutex g_scratch_mu;
 
 // the device address of this device's scratch (set up on first use)
@@ -3967,6 +3985,73 @@ rbp_status rbp_decode_multi(int32_t n_codes, const rbp_code_t* codes, const doub
     a.stats = stats;
     fill_params(a, params);
     return launch_decode(cs.data(), n_codes, a, shots, stream);
+}
+
+rbp_status rbp_decode_each(int32_t n_codes, const rbp_code_t* codes, const double* const* priors,
+                           const uint64_t* shots, const uint32_t* const* syndromes, const rbp_relay_params* params,
+                           uint32_t* const* corrections, uint32_t* const* obs_pred, rbp_shot_stats* const* stats,
+                           void* stream_) {
+    if (n_codes < 1 || n_codes > kMaxModels) return fail(RBP_ERR_INVALID_ARG, "n_codes must be 1..8");
+    if (!codes || !priors || !shots || !syndromes || !corrections) return fail(RBP_ERR_INVALID_ARG, "NULL array");
+    rbp_status st = check_params(params);
+    if (st) return st;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    // every argument and table first, on the caller's stream: nothing is
+    // launched unless every model can be
+    for (int i = 0; i < n_codes; ++i) {
+        rbp_code* c = codes[i];
+        if (!c) return fail(RBP_ERR_INVALID_ARG, "code is NULL");
+        for (int j = 0; j < i; ++j)
+            if (codes[j] == c) return fail(RBP_ERR_INVALID_ARG, "each handle may appear once");
+        if (shots[i] == 0) continue;
+        if (!syndromes[i] || !corrections[i]) return fail(RBP_ERR_INVALID_ARG, "syndromes/corrections is NULL");
+        if (c->k > 0 && (!obs_pred || !obs_pred[i])) return fail(RBP_ERR_INVALID_ARG, "obs_pred is NULL");
+        st = check_priors(priors[i], c->N);
+        if (!st) st = ensure_llr(c, priors[i], stream);
+        if (!st) st = ensure_gamma(c, params, stream);
+        if (!st) st = ensure_lam_gamma(c, params, stream);
+        if (st) return st;
+    }
+    int dev = 0;
+    RBP_HIP_CHECK(hipGetDevice(&dev));
+    hipStream_t* pool = nullptr;
+    st = side_streams(dev, &pool);
+    if (st) return st;
+    // fork: every side stream waits for the caller's stream; the largest
+    // model is issued first, so the smaller launches fill its tail
+    std::vector<int> order(n_codes);
+    for (int i = 0; i < n_codes; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return (int64_t)codes[x]->E * (int64_t)shots[x] > (int64_t)codes[y]->E * (int64_t)shots[y];
+    });
+    hipEvent_t fork = nullptr;
+    RBP_HIP_CHECK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    std::vector<hipEvent_t> joins;
+    auto finish = [&](rbp_status e) {
+        // join whatever was issued, so the caller's stream orders after it
+        for (hipEvent_t j : joins) {
+            (void)hipStreamWaitEvent(stream, j, 0);
+            (void)hipEventDestroy(j);
+        }
+        (void)hipEventDestroy(fork);
+        return e;
+    };
+    if (hipEventRecord(fork, stream) != hipSuccess) return finish(fail(RBP_ERR_HIP, "hipEventRecord failed"));
+    for (int k = 0; k < n_codes; ++k) {
+        const int i = order[k];
+        if (shots[i] == 0) continue;
+        hipStream_t side = pool[k];
+        if (hipStreamWaitEvent(side, fork, 0) != hipSuccess)
+            return finish(fail(RBP_ERR_HIP, "hipStreamWaitEvent failed"));
+        st = rbp_decode(codes[i], priors[i], syndromes[i], shots[i], params, nullptr, corrections[i],
+                        obs_pred ? obs_pred[i] : nullptr, stats ? stats[i] : nullptr, side);
+        hipEvent_t j = nullptr;
+        if (hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess || hipEventRecord(j, side) != hipSuccess)
+            return finish(st ? st : fail(RBP_ERR_HIP, "join event failed"));
+        joins.push_back(j);
+        if (st) return finish(st);
+    }
+    return finish(RBP_OK);
 }
 
 rbp_status rbp_count_failures(const uint32_t* obsp, const uint32_t* obs, const rbp_shot_stats* st, uint64_t shots,

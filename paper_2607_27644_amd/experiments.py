@@ -112,6 +112,9 @@ def multi(names, shots_each: int, seed: int = 11, params: rbp.RelayParams | None
                                          "waves": tr["waves_per_shot"], "state": tr["state"],
                                          "shots_per_wg": tr["shots_per_wg"]}
     res["per_model_total"] = {"ms": tot_ms, "shots_per_s": total / (tot_ms * 1e-3)}
+    # the same tuned launches issued together on side streams (rbp_decode_each)
+    ms, _ = _timed(lambda: rbp.decode_each(codes, [d.priors for d in dems], syns, params))
+    res["per_model_concurrent"] = {"ms": ms, "shots_per_s": total / (ms * 1e-3)}
     return res
 
 

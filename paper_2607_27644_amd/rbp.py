@@ -191,6 +191,7 @@ def _load(path: str, required: bool):
         "rbp_mlp_save": [vp, ctypes.c_char_p],
         "rbp_mlp_load": [vp, ctypes.c_char_p],
         "rbp_test_set_coop_phantom": [vp, i32],
+        "rbp_decode_each": [i32, vp, vp, vp, vp, P(RelayParamsC), vp, vp, vp, vp],
         "rbp_resident_start": [vp, vp, P(RelayParamsC), P(ResidentParamsC), P(vp)],
         "rbp_resident_decode": [vp, vp, vp, vp, vp],
         "rbp_resident_info": [vp, P(u64), P(i32), P(i32)],
@@ -487,6 +488,32 @@ class Code:
         check(lib().rbp_get_launch_config(self.h, ctypes.byref(cfg), ctypes.byref(slots), ctypes.byref(lds)))
         return dict(waves_per_shot=cfg.waves_per_shot, state=cfg.state, max_slots=cfg.max_slots,
                     shots_per_wg=cfg.shots_per_wg, slots=slots.value, lds_bytes=lds.value)
+
+
+def decode_each(codes: Sequence[Code], priors: Sequence, syndromes: Sequence[torch.Tensor], params: RelayParams,
+                outs: Optional[Sequence] = None, stream=None):
+    """Several models, each in its own launch with its own launch shape (the
+    code's launch config), issued together on side streams and joined into
+    `stream` (rbp_decode_each).  Returns one (corrections, obs_pred, stats)
+    tuple per model, as Code.decode would."""
+    n = len(codes)
+    if not 1 <= n <= 8 or not (len(priors) == len(syndromes) == n):
+        raise ValueError("decode_each needs 1..8 models and one priors/syndromes entry each")
+    res = []
+    for i, c in enumerate(codes):
+        _need(syndromes[i], f"syndromes[{i}]", torch.int32)
+        r = syndromes[i].shape[0]
+        _need(syndromes[i], f"syndromes[{i}]", torch.int32, (r, words(c.M)))
+        res.append(c._outputs(r, syndromes[i].device, True, None if outs is None else outs[i]))
+    VP = ctypes.c_void_p * n
+    prs = [c._priors(p) for c, p in zip(codes, priors)]
+    shots = (ctypes.c_uint64 * n)(*[s.shape[0] for s in syndromes])
+    prm = params.c()
+    check(lib().rbp_decode_each(n, VP(*[c.h.value for c in codes]), VP(*[p.ctypes.data for p in prs]), shots,
+                                VP(*[s.data_ptr() for s in syndromes]), ctypes.byref(prm),
+                                VP(*[r[0].data_ptr() for r in res]), VP(*[r[1].data_ptr() for r in res]),
+                                VP(*[r[2].data_ptr() if r[2] is not None else None for r in res]), _stream(stream)))
+    return res
 
 
 def decode_multi(codes: Sequence[Code], priors: Sequence, shot_code: torch.Tensor, shot_index: torch.Tensor,
