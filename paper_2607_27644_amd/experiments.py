@@ -257,11 +257,26 @@ CODE_DISTANCE = {"cc160": 10, "phen160": 10, "phen240": 12, "phen320": 14, "phen
                  "phen775": 22}
 
 
+# shots per decode call of the LER experiments: slow points (circuit-level DEMs
+# near threshold, where non-converging shots run every relay leg) report
+# progress after each chunk
+CHUNK = 20000
+
+
 def _failures(code, dem, priors, syn, obs, params) -> tuple:
-    corr, obsp, st = code.decode(priors, syn, params)
-    s = rbp.stats_to_numpy(st)
-    f = stats.block_failures(rbp.to_u32(obsp), rbp.to_u32(obs), s["converged"])
-    return int(f.sum()), float(s["iters"].mean()), int((s["converged"] == 0).sum())
+    import sys
+    n = syn.shape[0]
+    f = it = nc = 0
+    for a in range(0, n, CHUNK):
+        b = min(n, a + CHUNK)
+        corr, obsp, st = code.decode(priors, syn[a:b], params)
+        s = rbp.stats_to_numpy(st)
+        f += int(stats.block_failures(rbp.to_u32(obsp), rbp.to_u32(obs[a:b]), s["converged"]).sum())
+        it += float(s["iters"].astype(np.float64).sum())
+        nc += int((s["converged"] == 0).sum())
+        if n > CHUNK:
+            print(f"[chunk] {b}/{n} shots: {f} failures", file=sys.stderr, flush=True)
+    return f, it / max(n, 1), nc
 
 
 def _model_at(name: str, p: float):
@@ -486,7 +501,10 @@ def main():
     ap.add_argument("--all-shots", type=int, default=3)
     ap.add_argument("--num-sets", type=int, default=1000)
     ap.add_argument("--bases", default="XZ")
+    ap.add_argument("--chunk", type=int, default=20000, help="shots per decode call of the LER experiments")
     a = ap.parse_args()
+    global CHUNK
+    CHUNK = max(1, a.chunk)
     torch.cuda.set_device(0)
     if a.what == "multi":
         r = multi(a.models.split(","), a.shots)
