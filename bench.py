@@ -343,27 +343,29 @@ def main():
 
     progress("learned and paired-LER stages done")
     if not args.no_sequential:
-        # the paper's sequential mode: one shot per decode call, host clock around each
-        lat = []
+        # the paper's sequential mode: one shot per decode call, host clock around
+        # each; and the same shots through the resident decoder (one launch, the
+        # syndrome handed over and the correction returned through pinned host
+        # memory); the two alternate in blocks of 40 shots, so that they are
+        # compared under the same conditions
+        lat, rlat = np.zeros(200), np.zeros(200)
         c1, o1, s1 = corr[:1], obsp[:1], st[:1]
-        for i in range(200):
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            code.decode(dem.priors, syn[i:i + 1], params, out=(c1, o1, s1))
-            torch.cuda.synchronize()
-            lat.append(1e6 * (time.perf_counter() - ta))
-        out["latency_us"]["sequential_single_shot"] = stats.percentiles(np.array(lat))
-        # the same shots through the resident decoder: one launch, the syndrome
-        # handed over and the correction returned through pinned host memory
         hsyn = syn[:200].cpu().numpy().view(np.uint32)
-        with code.resident(dem.priors, params, idle_seconds=10.0) as rd:
-            rd.decode(hsyn[0])
-            lat = []
-            for i in range(200):
+        for b0 in range(0, 200, 40):
+            for i in range(b0, b0 + 40):
+                torch.cuda.synchronize()
                 ta = time.perf_counter()
-                rd.decode(hsyn[i])
-                lat.append(1e6 * (time.perf_counter() - ta))
-        out["latency_us"]["resident_single_shot"] = stats.percentiles(np.array(lat))
+                code.decode(dem.priors, syn[i:i + 1], params, out=(c1, o1, s1))
+                torch.cuda.synchronize()
+                lat[i] = 1e6 * (time.perf_counter() - ta)
+            with code.resident(dem.priors, params, idle_seconds=10.0) as rd:
+                rd.decode(hsyn[b0])
+                for i in range(b0, b0 + 40):
+                    ta = time.perf_counter()
+                    rd.decode(hsyn[i])
+                    rlat[i] = 1e6 * (time.perf_counter() - ta)
+        out["latency_us"]["sequential_single_shot"] = stats.percentiles(lat)
+        out["latency_us"]["resident_single_shot"] = stats.percentiles(rlat)
 
     progress("sequential latency done")
     if not args.no_extras:
@@ -414,20 +416,22 @@ def extras(seed: int) -> dict:
         s, _, _ = c.sample(d.priors, 4000, seed)
         o = c.decode_coop(d.priors, s[:1], prm)
         torch.cuda.synchronize()
-        lat = []
-        for i in range(100):
-            t0 = time.perf_counter()
-            c.decode_coop(d.priors, s[i:i + 1], prm, out=o)
-            torch.cuda.synchronize()
-            lat.append(1e6 * (time.perf_counter() - t0))
+        # per-call latency mode and the resident decoder on the same shots, in
+        # alternating blocks of 20
+        lat, rlat = [0.0] * 100, [0.0] * 100
         hs = s[:100].cpu().numpy().view(np.uint32)
-        with c.resident(d.priors, prm, idle_seconds=10.0) as rd:
-            rd.decode(hs[0])
-            rlat = []
-            for i in range(100):
+        for b0 in range(0, 100, 20):
+            for i in range(b0, b0 + 20):
                 t0 = time.perf_counter()
-                rd.decode(hs[i])
-                rlat.append(1e6 * (time.perf_counter() - t0))
+                c.decode_coop(d.priors, s[i:i + 1], prm, out=o)
+                torch.cuda.synchronize()
+                lat[i] = 1e6 * (time.perf_counter() - t0)
+            with c.resident(d.priors, prm, idle_seconds=10.0) as rd:
+                rd.decode(hs[b0])
+                for i in range(b0, b0 + 20):
+                    t0 = time.perf_counter()
+                    rd.decode(hs[i])
+                    rlat[i] = 1e6 * (time.perf_counter() - t0)
         # batched: the launch shape tuned for this DEM (waves per shot, device-memory state)
         tr = autotune.tune(c, d.H, d.priors, prm, shots=2000, waves=(4, 8, 16), states=(2,), use_cache=False)
         ms, out = experiments._timed(lambda: c.decode(d.priors, s, prm), repeats=2)

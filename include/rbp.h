@@ -312,8 +312,11 @@ rbp_status rbp_resident_start(rbp_code_t code, const double* priors, const rbp_r
 rbp_status rbp_resident_decode(rbp_resident_t r, const uint32_t* syndrome, uint32_t* correction, uint32_t* obs_pred,
                                rbp_shot_stats* stats);
 /* Shots decoded so far, kernel launches so far (1 + relaunches after idle or
- * aborted ends), and whether the kernel is running now (any may be NULL). */
-rbp_status rbp_resident_info(rbp_resident_t r, uint64_t* shots, int32_t* launches, int32_t* running);
+ * aborted ends), whether the kernel is running now, and the bit mask of the
+ * XCDs its participating workgroups run on (0 until the current launch has
+ * started); any pointer may be NULL. */
+rbp_status rbp_resident_info(rbp_resident_t r, uint64_t* shots, int32_t* launches, int32_t* running,
+                             uint32_t* xcds);
 /* Ends the kernel (after the shot it is decoding, if any), waits for it and
  * frees the handle and its mailbox.  NULL is a no-op. */
 rbp_status rbp_resident_stop(rbp_resident_t r);

@@ -2202,7 +2202,8 @@ struct ResidentBox {
     unsigned long long done;       // kernel: shots whose outputs are written
     unsigned int stop;             // host: 1 = end at the next wait
     unsigned int state;            // kernel: kResident* below
-    unsigned int pad[10];
+    unsigned int xcds;             // kernel: bit mask of the XCDs the participants run on
+    unsigned int pad[9];
 };
 static_assert(sizeof(ResidentBox) == 64, "mailbox header is one 64-byte line");
 constexpr unsigned kResidentRunning = 1, kResidentStopped = 2, kResidentIdle = 3, kResidentAborted = 4;
@@ -2413,8 +2414,13 @@ __global__ void __launch_bounds__(512, 1) relay_bp_coop_kernel(const CoopLaunch 
     // which XCDs the participants run on (hardware register XCC_ID, bits 3:0)
     if (tid == 0) atomicOr(&sh->xmask, 1u << (__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u));
     if (!sync(false)) return;
-    const bool local =
-        __popc(__hip_atomic_load(&sh->xmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 1 && !a.force_device;
+    const unsigned xmask = __hip_atomic_load(&sh->xmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool local = __popc(xmask) == 1 && !a.force_device;
+    if constexpr (RES) {
+        // which XCDs this launch runs on, for the host (rbp_resident_info)
+        if (rank == 0 && tid == 0)
+            __hip_atomic_store(&a.box->xcds, xmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 
     for (uint64_t s = RES ? a.res_start : 0; RES || s < a.shots; ++s) {
         if constexpr (RES) {
@@ -3759,6 +3765,7 @@ static rbp_status resident_launch(rbp_resident* r) {
     __atomic_store_n(&b->published, (unsigned long long)r->next, __ATOMIC_RELAXED);
     __atomic_store_n(&b->done, (unsigned long long)r->next, __ATOMIC_RELAXED);
     __atomic_store_n(&b->stop, 0u, __ATOMIC_RELAXED);
+    __atomic_store_n(&b->xcds, 0u, __ATOMIC_RELAXED);
     __atomic_store_n(&b->state, 0u, __ATOMIC_RELEASE);
     r->P.a.res_start = r->next;
     rbp_status st = coop_launch(r->P, r->stream);
@@ -3903,10 +3910,12 @@ rbp_status rbp_resident_decode(rbp_resident_t r, const uint32_t* syndrome, uint3
     return RBP_OK;
 }
 
-rbp_status rbp_resident_info(rbp_resident_t r, uint64_t* shots, int32_t* launches, int32_t* running) {
+rbp_status rbp_resident_info(rbp_resident_t r, uint64_t* shots, int32_t* launches, int32_t* running,
+                             uint32_t* xcds) {
     if (!r) return fail(RBP_ERR_INVALID_ARG, "resident handle is NULL");
     if (shots) *shots = r->next;
     if (launches) *launches = r->launches;
+    if (xcds) *xcds = __atomic_load_n(&r->box()->xcds, __ATOMIC_ACQUIRE);
     if (running) {
         const unsigned state = __atomic_load_n(&r->box()->state, __ATOMIC_ACQUIRE);
         *running = r->running && state != kResidentIdle && state != kResidentAborted && state != kResidentStopped;

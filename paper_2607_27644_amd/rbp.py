@@ -194,7 +194,7 @@ def _load(path: str, required: bool):
         "rbp_decode_each": [i32, vp, vp, vp, vp, P(RelayParamsC), vp, vp, vp, vp],
         "rbp_resident_start": [vp, vp, P(RelayParamsC), P(ResidentParamsC), P(vp)],
         "rbp_resident_decode": [vp, vp, vp, vp, vp],
-        "rbp_resident_info": [vp, P(u64), P(i32), P(i32)],
+        "rbp_resident_info": [vp, P(u64), P(i32), P(i32), P(ctypes.c_uint32)],
         "rbp_resident_stop": [vp],
     }
     sigs["rbp_measure_lds_bandwidth"] = [i32, ctypes.POINTER(ctypes.c_double)]
@@ -675,8 +675,11 @@ class Resident:
 
     def info(self) -> dict:
         shots, launches, running = ctypes.c_uint64(), ctypes.c_int32(), ctypes.c_int32()
-        check(lib().rbp_resident_info(self.h, ctypes.byref(shots), ctypes.byref(launches), ctypes.byref(running)))
-        return {"shots": shots.value, "launches": launches.value, "running": bool(running.value)}
+        xcds = ctypes.c_uint32()
+        check(lib().rbp_resident_info(self.h, ctypes.byref(shots), ctypes.byref(launches), ctypes.byref(running),
+                                      ctypes.byref(xcds)))
+        return {"shots": shots.value, "launches": launches.value, "running": bool(running.value),
+                "xcds": xcds.value}
 
     def close(self):
         if getattr(self, "h", None):

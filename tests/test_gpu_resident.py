@@ -77,6 +77,7 @@ def test_resident_equals_latency_mode(rbp, name, shots, wg):
         got = run_resident(res, syn)
         info = res.info()
     assert info["shots"] == shots and info["launches"] == 1
+    assert bin(info["xcds"]).count("1") == 1  # the default stride keeps the participants on one XCD
     same(got, ref)
 
 
