@@ -83,3 +83,34 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(rbp, "LIB_PATH", os.path.join(PKG, "does_not_exist.so"))
     with pytest.raises(RuntimeError, match="not built"):
         rbp.lib()
+
+
+def test_resident_and_each_validation_without_gpu():
+    """The resident decoder's and rbp_decode_each's argument checks return
+    INVALID_ARG before any device call; stopping a NULL handle is a no-op."""
+    lib = ctypes.CDLL(os.path.join(PKG, "librbp.so"))
+    lib.rbp_last_error.restype = ctypes.c_char_p
+    vp = ctypes.c_void_p
+    out = vp()
+    assert lib.rbp_resident_start(None, None, None, None, ctypes.byref(out)) == -1
+    assert out.value is None
+    assert lib.rbp_resident_decode(None, None, None, None, None) == -1
+    assert b"NULL" in lib.rbp_last_error()
+    assert lib.rbp_resident_info(None, None, None, None, None) == -1
+    assert lib.rbp_resident_stop(None) == 0
+    # rbp_decode_each: model count out of range, NULL arrays, NULL handle
+    assert lib.rbp_decode_each(0, None, None, None, None, None, None, None, None, None) == -1
+    assert lib.rbp_decode_each(9, None, None, None, None, None, None, None, None, None) == -1
+    assert lib.rbp_decode_each(1, None, None, None, None, None, None, None, None, None) == -1
+    codes = (vp * 1)(None)
+    shots = (ctypes.c_uint64 * 1)(0)
+    arr = (vp * 1)(None)
+
+    class Params(ctypes.Structure):
+        _fields_ = [("gamma0", ctypes.c_float), ("gamma_min", ctypes.c_float), ("gamma_max", ctypes.c_float),
+                    ("pre_iter", ctypes.c_int32), ("max_iterations", ctypes.c_int32), ("num_sets", ctypes.c_int32),
+                    ("stop_nconv", ctypes.c_int32), ("stopping_criterion", ctypes.c_int32),
+                    ("gamma_seed", ctypes.c_uint64)]
+    prm = Params(0.125, -0.24, 0.66, 80, 60, 100, 5, 0, 0)
+    assert lib.rbp_decode_each(1, codes, arr, shots, arr, ctypes.byref(prm), arr, arr, None, None) == -1
+    assert b"code is NULL" in lib.rbp_last_error()
