@@ -142,7 +142,7 @@ def main():
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; shots shard across GPUs by "
                                    "shot_offset with no communication, so one process per GPU would each "
-                                   "run it on its own shot range (multi-GPU launch is not part of this build)",
+                                   "run it on its own shot range; no multi-GPU launcher is provided",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
