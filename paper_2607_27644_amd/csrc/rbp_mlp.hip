@@ -164,8 +164,11 @@ __global__ void __launch_bounds__(256, TN == 2 ? kMinWaves64 : kMinWaves128) gem
     constexpr int BNT = 64 * TN;
     // two LDS stages: the tiles of step k are read by the matrix cores while
     // those of step k + 1 arrive in registers
-    __shared__ __align__(16) elem As[2][BM][LDSK];
-    __shared__ __align__(16) elem Bs[2][BNT][LDSK];
+    // the two operand stages in one buffer, which the BF16-only epilogues reuse
+    // to stage the output tile
+    __shared__ __align__(16) elem stage[2 * BM * LDSK + 2 * BNT * LDSK];
+    elem(*As)[BM][LDSK] = reinterpret_cast<elem(*)[BM][LDSK]>(stage);
+    elem(*Bs)[BNT][LDSK] = reinterpret_cast<elem(*)[BNT][LDSK]>(stage + 2 * BM * LDSK);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     // Workgroups are dealt to the 8 XCDs round-robin.  Renumber them so that
     // each XCD takes a contiguous run of tiles in row-major order: the column
@@ -245,6 +248,42 @@ __global__ void __launch_bounds__(256, TN == 2 ? kMinWaves64 : kMinWaves128) gem
         cur ^= 1;
     }
     // 32x32 accumulator layout: register r of lane l is C[8*(r/4) + 4*(l/32) + r%4][l%32]
+    if constexpr (EPI == EPI_BIAS_BF16 || EPI == EPI_BIAS_RELU_BF16) {
+        // BF16-only outputs: the rounded tile is staged in LDS (the K loop ended
+        // with a barrier, so the operand stages are free) and written with
+        // 16-byte stores, eight consecutive columns per thread
+        constexpr int CLD = BNT + 8;  // padded row of the staged tile
+        static_assert(BM * CLD <= 2 * BM * LDSK + 2 * BNT * LDSK, "output tile fits the operand stages");
+        elem* ct = stage;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int ml = wm + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    const int nl = wn + j * 32 + (lane & 31);
+                    const int n = n0 + nl;
+                    float v = acc[i][j][r] + (n < g.N ? g.bias[n] : 0.0f);
+                    if constexpr (EPI == EPI_BIAS_RELU_BF16) v = fmaxf(v, 0.0f);
+                    ct[ml * CLD + nl] = (elem)v;
+                }
+        __syncthreads();
+        const bool vec = ((reinterpret_cast<uintptr_t>(g.out_bf16) & 15) == 0) && ((g.ldc & 7) == 0);
+        for (int q = threadIdx.x; q < BM * (BNT / 8); q += 256) {
+            const int r = q / (BNT / 8), c = (q % (BNT / 8)) * 8;
+            const int m = m0 + r, n = n0 + c;
+            if (m >= g.M || n >= g.N) continue;
+            elem* dst = g.out_bf16 + (int64_t)m * g.ldc + n;
+            const elem* src = ct + r * CLD + c;
+            if (vec && n + 8 <= g.N) {
+                *reinterpret_cast<elemx8*>(dst) = *reinterpret_cast<const elemx8*>(src);
+            } else {
+                for (int e = 0; e < 8 && n + e < g.N; ++e) dst[e] = src[e];
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
