@@ -29,6 +29,11 @@ names:
              intervals": batched throughput and service times, sequential
              single-shot latency, the all-legs worst case, block LER, per code
              and memory basis
+  resident   sequential single-shot latency of one model, per call (the
+             latency mode, rbp_decode_coop) and through the resident decoder
+             (rbp_resident_*), in alternating blocks on the same shots: host
+             clock, the kernel's own time per shot (device timestamps) and the
+             XCDs each resident launch ran on
   awgn       block error rate of the classical ZSZ-2BGA codes over BPSK-AWGN
              against E_b/N_0, sum-product BP (numerics appendix, "classical
              channel coding"), with the decoder's throughput and the Shannon
@@ -159,6 +164,57 @@ def latency(name: str, shots: int = 300, all_shots: int = 100, seed: int = 31) -
     return {"model": {"name": name, "M": dem.M, "N": dem.N, "nnz": dem.nnz},
             "sequential_us": stats.percentiles(np.array(lat)),
             "all_legs_us": stats.percentiles(np.array(lat_all)), "launch": code.launch_config()}
+
+
+def resident_exp(name: str, p: float = 1e-3, shots: int = 100, block: int = 20, workgroups: int = 0,
+                 seed: int = 51) -> dict:
+    """Per-call latency mode against the resident decoder on the same shots, in
+    alternating blocks (a fresh resident launch per block), so that both see
+    the same conditions.  Circuit-level models ("circ320x") take the relay
+    interval of Table "relay gamma intervals" and 1,000 legs; the others the
+    default parameters."""
+    import sys
+    dem, priors = _model_at(name, p)
+    if name.startswith("circ"):
+        gmin, gmax = CIRCUIT_GAMMA[f"ZSZ-LP-{name[4:-1]}"]
+        params = rbp.RelayParams(num_sets=1000, gamma_min=gmin, gamma_max=gmax)
+    else:
+        params = rbp.RelayParams()
+    code = rbp.Code.from_dem(dem)
+    coop = rbp.CoopParams(workgroups=workgroups)
+    syn, _, _ = code.sample(priors, shots, seed)
+    hsyn = syn.cpu().numpy().view(np.uint32)
+    out = code.decode_coop(priors, syn[:1], params, coop)
+    torch.cuda.synchronize()
+    host = {"per_call": np.zeros(shots), "resident": np.zeros(shots)}
+    dev = {"per_call": np.zeros(shots), "resident": np.zeros(shots)}
+    xcds = []
+    for b0 in range(0, shots, block):
+        idx = range(b0, min(shots, b0 + block))
+        for i in idx:
+            t0 = time.perf_counter()
+            code.decode_coop(priors, syn[i:i + 1], params, coop, out=out)
+            torch.cuda.synchronize()
+            host["per_call"][i] = 1e6 * (time.perf_counter() - t0)
+            st = rbp.stats_to_numpy(out[2])
+            dev["per_call"][i] = (int(st["t_end"][0]) - int(st["t_start"][0])) / 100.0
+        with code.resident(priors, params, coop, idle_seconds=10.0) as rd:
+            rd.decode(hsyn[idx[0]])
+            for i in idx:
+                t0 = time.perf_counter()
+                _, _, st = rd.decode(hsyn[i])
+                host["resident"][i] = 1e6 * (time.perf_counter() - t0)
+                dev["resident"][i] = (int(st["t_end"]) - int(st["t_start"])) / 100.0
+            xcds.append(rd.info()["xcds"])
+        print(f"[resident] {name}: block {b0 // block + 1} done", file=sys.stderr, flush=True)
+    code.close()
+    ratio = dev["resident"] / np.maximum(dev["per_call"], 1e-9)
+    return {"model": name, "p": p, "dem": [dem.M, dem.N], "shots": shots, "block": block,
+            "coop_workgroups": workgroups, "device_clock_mhz": 100,
+            "host_us": {k: stats.percentiles(v) for k, v in host.items()},
+            "device_us": {k: stats.percentiles(v) for k, v in dev.items()},
+            "host_minus_device_us_p50": {k: float(np.median(host[k] - dev[k])) for k in host},
+            "resident_over_per_call_device_median": float(np.median(ratio)), "resident_xcd_masks": xcds}
 
 
 # Table "relay gamma intervals" (App. "more numerics"): [gamma_min, gamma_max]
@@ -525,6 +581,8 @@ def main():
     elif a.what == "circuit":
         r = circuit_exp(a.circuit_codes.split(","), a.p_circuit, a.shots, a.seq_shots, a.all_shots, a.num_sets,
                         a.bases)
+    elif a.what == "resident":
+        r = resident_exp(a.model, a.p_circuit, a.seq_shots, 20)
     elif a.what == "sweep":
         gmin, gmax = (float(x) for x in a.sweep_gamma.split(","))
         r = ler_sweep(a.model, [float(x) for x in a.ps.split(",")], a.shots, p_fit_max=a.p_fit_max,
