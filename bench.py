@@ -419,6 +419,7 @@ def extras(seed: int) -> dict:
         # per-call latency mode and the resident decoder on the same shots, in
         # alternating blocks of 20
         lat, rlat = [0.0] * 100, [0.0] * 100
+        dev, rdev, xcds = [0.0] * 100, [0.0] * 100, []  # the kernel's own time per shot (device clock)
         hs = s[:100].cpu().numpy().view(np.uint32)
         for b0 in range(0, 100, 20):
             for i in range(b0, b0 + 20):
@@ -426,17 +427,24 @@ def extras(seed: int) -> dict:
                 c.decode_coop(d.priors, s[i:i + 1], prm, out=o)
                 torch.cuda.synchronize()
                 lat[i] = 1e6 * (time.perf_counter() - t0)
+                so = rbp.stats_to_numpy(o[2])
+                dev[i] = float(so["t_end"][0] - so["t_start"][0]) * 0.01
             with c.resident(d.priors, prm, idle_seconds=10.0) as rd:
                 rd.decode(hs[b0])
                 for i in range(b0, b0 + 20):
                     t0 = time.perf_counter()
-                    rd.decode(hs[i])
+                    _, _, sr = rd.decode(hs[i])
                     rlat[i] = 1e6 * (time.perf_counter() - t0)
+                    rdev[i] = float(sr["t_end"] - sr["t_start"]) * 0.01
+                xcds.append(rd.info()["xcds"])
         # batched: the launch shape tuned for this DEM (waves per shot, device-memory state)
         tr = autotune.tune(c, d.H, d.priors, prm, shots=2000, waves=(4, 8, 16), states=(2,), use_cache=False)
         ms, out = experiments._timed(lambda: c.decode(d.priors, s, prm), repeats=2)
         cl[f"{basis}_memory"] = {"dem": [d.M, d.N], "latency_mode_us": stats.percentiles(np.array(lat)),
                                  "resident_us": stats.percentiles(np.array(rlat)),
+                                 "kernel_us_p50": {"latency_mode": float(np.median(dev)),
+                                                   "resident": float(np.median(rdev))},
+                                 "resident_xcd_masks": xcds,
                                  "batched_launch": {"waves_per_shot": tr["waves_per_shot"], "state": tr["state"]},
                                  "batched_shots_per_s": 4000 / (ms * 1e-3),
                                  "mean_iters": float(rbp.stats_to_numpy(out[2])["iters"].mean())}
