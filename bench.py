@@ -190,7 +190,7 @@ def main():
         if record:
             e[2].record()
         if path in ("learned", "proposal_zero"):
-            code.decode_proposal(dem.priors, syn, prm, state["delta"], out=(corr, obsp, st))
+            code.decode_proposal(dem.priors, syn, prm, state["delta"], out=(corr, obsp, st), by_position=True)
         else:
             code.decode(dem.priors, syn, prm, out=(corr, obsp, st))
         if record:
@@ -274,11 +274,15 @@ def main():
         net = rbp.MLP(dem.M, cfg.hidden, dem.N, seed=cfg.seed)
         hist = learned.train(net, chunks, cfg)
         learned.scale_output(net, cfg.delta_scale)
+        # the network writes its adjustments in the decoder's position order, which
+        # the proposal leg copies to LDS with contiguous loads
+        vord = code.positions()
+        net.set_output_order(vord)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         del chunks
         state["net"] = net
-        state["delta"] = torch.empty((S, dem.N), dtype=torch.bfloat16, device=dev)
+        state["delta"] = torch.empty((S, len(vord)), dtype=torch.bfloat16, device=dev)
         paths["learned"] = timed("learned", params)
         state["delta"].zero_()
         paths["proposal_zero"] = timed("proposal_zero", params)
@@ -297,8 +301,9 @@ def main():
             L["vs_first_solution"] = L["value"] / paths["first_solution"]["value"]
         L["vs_plain"] = L["value"] / P["value"]
         paths["proposal_zero"]["note"] = "control: the same proposal leg with delta = 0 (no network)"
-        L["note"] = ("network -> BF16 adjustments (rbp_mlp_forward_bf16) -> proposal leg with the adjustments "
-                     "in LDS, plain Relay-BP as the fallback (rbp_decode_proposal)")
+        L["note"] = ("network -> BF16 adjustments in the decoder's position order (rbp_mlp_forward_bf16 after "
+                     "rbp_mlp_set_output_order) -> proposal leg with the adjustments in LDS, plain Relay-BP as the "
+                     "fallback (rbp_decode_proposal_pos)")
     out.update(paths)
 
     # logical error rates at higher p, every path on the same syndromes
@@ -319,9 +324,9 @@ def main():
             if dk == "net":
                 d = state["net"].forward_bf16(hsyn)
             elif dk == "zero":
-                d = torch.zeros((n, dem.N), dtype=torch.bfloat16, device=dev)
+                d = torch.zeros((n, len(code.positions())), dtype=torch.bfloat16, device=dev)
             if d is not None:
-                c, o, s = code.decode_proposal(pri, hsyn, prm, d)
+                c, o, s = code.decode_proposal(pri, hsyn, prm, d, by_position=True)
             else:
                 c, o, s = code.decode(pri, hsyn, prm)
             e1.record()

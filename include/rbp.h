@@ -141,6 +141,25 @@ rbp_status rbp_decode_proposal(rbp_code_t code, const double* priors, const uint
                                uint32_t* corrections_dev, uint32_t* obs_pred_dev, rbp_shot_stats* stats_dev,
                                void* stream);
 
+/* The same decode with the BF16 adjustments laid out by decoder position
+ * instead of by mechanism: delta_bf16_pos_dev uint16[shots][Np] (16-byte
+ * aligned), entry p the adjustment of mechanism var_of_position[p]
+ * (rbp_code_positions), entries of padding positions ignored (taken as 0).
+ * Results are identical to rbp_decode_proposal with the same values by
+ * mechanism; the decoder then copies each row with contiguous loads instead
+ * of a gather (a network whose output layer is ordered by position writes
+ * this layout directly: rbp_mlp_set_output_order). */
+rbp_status rbp_decode_proposal_pos(rbp_code_t code, const double* priors, const uint32_t* syndromes_dev,
+                                   uint64_t shots, const rbp_relay_params* params, const uint16_t* delta_bf16_pos_dev,
+                                   uint32_t* corrections_dev, uint32_t* obs_pred_dev, rbp_shot_stats* stats_dev,
+                                   void* stream);
+
+/* The decoder's position order of a handle: *np = Np (N rounded up to whole
+ * groups of 64; positions N..Np-1 are padding) and, if var_of_position is not
+ * NULL (host, Np entries), the mechanism decoded at each position (-1 for
+ * padding).  Positions 0..N-1 hold every mechanism once. */
+rbp_status rbp_code_positions(rbp_code_t code, int32_t* np, int32_t* var_of_position);
+
 /* rbp_decode for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation): the
  * same decode, arguments, outputs and results, but its scratch -- the shot
@@ -349,6 +368,15 @@ rbp_status rbp_mlp_forward(rbp_mlp_t mlp, const uint32_t* syndromes_dev, uint64_
  * rbp_decode_proposal. */
 rbp_status rbp_mlp_forward_bf16(rbp_mlp_t mlp, const uint32_t* syndromes_dev, uint64_t shots, uint16_t* delta_dev,
                                 void* stream);
+/* Column order of rbp_mlp_forward_bf16's output: with n > 0 it writes n
+ * columns, column p the output order[p] (host array of n entries, each -1 for
+ * a column of zeros, or an output index < out_dim), e.g. the decoder's
+ * position order (rbp_code_positions) so that rbp_decode_proposal_pos can
+ * take the network's rows directly.  The output layer's rows are gathered
+ * into that order once here and again whenever the weights change.  n = 0
+ * restores the natural order.  rbp_mlp_forward (FP32) and training are not
+ * affected.  Synchronizes the device's default stream. */
+rbp_status rbp_mlp_set_output_order(rbp_mlp_t mlp, const int32_t* order, int32_t n);
 /* One Adam step on a batch: loss = mean over the batch of
  * sum_j BCEWithLogits(z_j, y_j), z_j = -(Lambda_j + delta_j), y = target bits
  * (uint32[batch][ceil(out_dim/32)]), Lambda = llr_dev float[out_dim].

@@ -330,6 +330,7 @@ struct DecodeLaunch {
     uint64_t shots;
     const float* delta;
     const uint16_t* delta16;  // BF16 proposal adjustments (rbp_decode_proposal), else null
+    int32_t d16_pos;          // delta16 rows by position (Np entries), not by variable (N entries)
     rbp_shot_stats* stats;
     unsigned long long* queue;
     float* gstate;
@@ -680,6 +681,12 @@ __device__ __forceinline__ float delta_of(const float* dlt, const uint16_t* dl16
     return dl16 ? bf16_to_f32(dl16[j]) : dlt[j];
 }
 
+// the adjustment of the variable j at position pp: by position when the BF16
+// rows are laid out by position
+__device__ __forceinline__ float delta_at(const float* dlt, const uint16_t* dl16, bool by_pos, int j, uint32_t pp) {
+    return by_pos ? bf16_to_f32(dl16[pp]) : delta_of(dlt, dl16, j);
+}
+
 constexpr int kQuarterRegs = 32;  // edges per lane kept in registers (rows up to 128)
 
 // the four lanes of a row exchange their two smallest magnitudes and sign
@@ -836,7 +843,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
             a.shot_index ? (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(a.shot_index[s]) : (uint64_t)s;
         const int N = m.N, WM = m.WM, WN = m.WN;
         const float* dlt = a.delta ? a.delta + row * (uint64_t)N : nullptr;
-        const uint16_t* dl16 = a.delta16 ? a.delta16 + row * (uint64_t)N : nullptr;
+        const uint16_t* dl16 = a.delta16 ? a.delta16 + row * (uint64_t)(a.d16_pos ? m.Np : N) : nullptr;
         if (tid == 0) X.st(4u * (uint32_t)m.S, INFINITY);  // read-only padding cell
         int4* const lrg = lvg + m.GV;
         if (grp_lds && mi != cur_model) {
@@ -903,7 +910,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                         float x = l;
                         if (prop) {
                             const int j = ldg(m.vord, pp);
-                            x = j >= 0 ? l + delta_of(dlt, dl16, j) : 0.0f;
+                            x = j >= 0 ? l + delta_at(dlt, dl16, a.d16_pos != 0, j, (uint32_t)pp) : 0.0f;
                             const int vd = ldg(m.vdeg, pp);
                             const uint32_t sb = 4u * ((uint32_t)ldg(m.vgrp, pp >> 6).x + (uint32_t)(pp & 63));
                             for (int q = 0; q < vd; ++q) X.st(sb + 256u * q, x);
@@ -997,7 +1004,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_kernel(const DecodeLaunch
                             float lt = l;
                             if (lp) {
                                 const int j = ldg(m.vord, pp);
-                                if (j >= 0) lt = l + delta_of(dlt, dl16, j);
+                                if (j >= 0) lt = l + delta_at(dlt, dl16, a.d16_pos != 0, j, pp);
                             }
                             const float mo = Mg[pp];
                             float acc = __builtin_fmaf(gm, mo - lt, lt);
@@ -1407,7 +1414,7 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
             a.shot_index ? (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(a.shot_index[s]) : (uint64_t)s;
         const int N = m.N, WM = m.WM, WN = m.WN;
         const float* dlt = a.delta ? a.delta + row * (uint64_t)N : nullptr;
-        const uint16_t* dl16 = a.delta16 ? a.delta16 + row * (uint64_t)N : nullptr;
+        const uint16_t* dl16 = a.delta16 ? a.delta16 + row * (uint64_t)(a.d16_pos ? m.Np : N) : nullptr;
         // BF16 adjustments are copied to LDS by position once per shot and read
         // from there by every iteration of the proposal leg
         uint16_t* dpos = dl16 ? reinterpret_cast<uint16_t*>(smem + a.off_d16) : nullptr;
@@ -1467,7 +1474,14 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
                     // independent loads, four in flight per thread before their LDS
                     // stores: 6.5 % off a proposal decode of the [[840,168]] model)
                     // and placed in LDS by position; padding 0
-                    int j = tid;
+                    if (a.d16_pos) {
+                        // rows by position (Np entries, a multiple of 64, padding 0):
+                        // contiguous 16-byte copies
+                        for (int q = tid; q < (m.Np >> 3); q += nth)
+                            reinterpret_cast<uint4*>(dpos)[q] = reinterpret_cast<const uint4*>(dl16)[q];
+                        __syncthreads();
+                    }
+                    int j = a.d16_pos ? N : tid;
                     for (; j + 3 * nth < N; j += 4 * nth) {
                         const uint16_t d0 = dl16[j + 0 * nth];
                         const uint16_t d1 = dl16[j + 1 * nth];
@@ -3555,6 +3569,44 @@ rbp_status rbp_decode_proposal(rbp_code_t c, const double* priors, const uint32_
     fill_params(a, params);
     rbp_code* cs[1] = {c};
     return launch_decode(cs, 1, a, shots, stream);
+}
+
+rbp_status rbp_decode_proposal_pos(rbp_code_t c, const double* priors, const uint32_t* syndromes, uint64_t shots,
+                                   const rbp_relay_params* params, const uint16_t* delta_bf16_pos,
+                                   uint32_t* corrections, uint32_t* obs_pred, rbp_shot_stats* stats, void* stream_) {
+    if (!c) return fail(RBP_ERR_INVALID_ARG, "code is NULL");
+    if (delta_bf16_pos && (reinterpret_cast<uintptr_t>(delta_bf16_pos) & 15) != 0)
+        return fail(RBP_ERR_INVALID_ARG, "delta (by position) must be 16-byte aligned");
+    rbp_status st = check_params(params);
+    if (st) return st;
+    if (shots == 0) return RBP_OK;
+    if (!syndromes || !corrections || !delta_bf16_pos)
+        return fail(RBP_ERR_INVALID_ARG, "syndromes/corrections/delta is NULL");
+    if (c->k > 0 && !obs_pred) return fail(RBP_ERR_INVALID_ARG, "obs_pred is NULL");
+    st = check_priors(priors, c->N);
+    if (st) return st;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    st = ensure_llr(c, priors, stream);
+    if (!st) st = ensure_gamma(c, params, stream);
+    if (!st) st = ensure_lam_gamma(c, params, stream);
+    if (st) return st;
+    DecodeLaunch a;
+    std::memset(&a, 0, sizeof(a));
+    a.m[0] = model_of(c, syndromes, corrections, obs_pred);
+    a.n_models = 1;
+    a.delta16 = delta_bf16_pos;
+    a.d16_pos = 1;
+    a.stats = stats;
+    fill_params(a, params);
+    rbp_code* cs[1] = {c};
+    return launch_decode(cs, 1, a, shots, stream);
+}
+
+rbp_status rbp_code_positions(rbp_code_t c, int32_t* np, int32_t* var_of_position) {
+    if (!c || !np) return fail(RBP_ERR_INVALID_ARG, "code/np is NULL");
+    *np = c->Np;
+    if (var_of_position) std::memcpy(var_of_position, c->h_vord.data(), sizeof(int32_t) * (size_t)c->Np);
+    return RBP_OK;
 }
 
 rbp_status rbp_decode_noalloc(rbp_code_t c, const double* priors, const uint32_t* syndromes, uint64_t shots,

@@ -413,6 +413,18 @@ __global__ void adam_kernel(float* w, float* mo, float* ve, const float* g, int6
     w[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
 }
 
+// output layer in a caller's order: row p of W3o (and b3o[p]) is row ord[p] of
+// W3 (b3), or zero where ord[p] < 0
+__global__ void order_rows_kernel(const elem* w3, const float* b3, const int32_t* ord, int n, int hid, elem* w3o,
+                                  float* b3o) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * hid) return;
+    const int p = (int)(i / hid), k = (int)(i % hid);
+    const int o = ord[p];
+    w3o[i] = o >= 0 ? w3[(int64_t)o * hid + k] : (elem)0.0f;
+    if (k == 0) b3o[p] = o >= 0 ? b3[o] : 0.0f;
+}
+
 __global__ void to_bf16_kernel(const float* w, elem* o, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) o[i] = (elem)w[i];
@@ -436,6 +448,8 @@ struct rbp_mlp {
     DevBuf xb, h1, h2, d3b, dh2b, dh1b;    // BF16 activations / gradients
     DevBuf delta, d3f, dh2f, dh1f, partial, loss;
     DevBuf tA, tB, csum;                   // transposed operands of the weight gradients, column-sum partials
+    int ord_n = 0;                         // rbp_mlp_set_output_order: columns of the BF16 forward (0: out)
+    DevBuf ord, w3o, b3o;                  // the order, and the output layer's rows in that order
 };
 
 namespace {
@@ -547,6 +561,11 @@ rbp_status forward(rbp_mlp* p, const uint32_t* syn, int B, float* dout, hipStrea
     a = ga(B, p->out, p->hid, h2, p->hid, wb + p->oW3, p->hid, p->out);
     a.bias = w + p->ob3;
     if (dout16) {
+        if (p->ord_n > 0) {
+            // output columns in the caller's order (rbp_mlp_set_output_order)
+            a = ga(B, p->ord_n, p->hid, h2, p->hid, p->w3o.as<elem>(), p->hid, p->ord_n);
+            a.bias = p->b3o.as<float>();
+        }
         a.out_bf16 = dout16;
         return gemm<K_CONTIG, K_CONTIG, EPI_BIAS_BF16, kFwdTN>(a, s);
     }
@@ -609,13 +628,24 @@ rbp_status gradients(rbp_mlp* p, const uint32_t* syn, const uint32_t* tgt, const
     return colsum(p, p->dh1f.as<float>(), B, p->hid, g + p->ob1, s);
 }
 
+rbp_status reorder_output(rbp_mlp* p, hipStream_t s) {
+    if (p->ord_n <= 0) return RBP_OK;
+    hipLaunchKernelGGL(order_rows_kernel, dim3(blocks((int64_t)p->ord_n * p->hid, 256)), dim3(256), 0, s,
+                       p->wb.as<elem>() + p->oW3, p->w.as<float>() + p->ob3, p->ord.as<int32_t>(), p->ord_n, p->hid,
+                       p->w3o.as<elem>(), p->b3o.as<float>());
+    RBP_HIP_CHECK(hipGetLastError());
+    return RBP_OK;
+}
+
 rbp_status refresh_bf16(rbp_mlp* p, hipStream_t s) {
     hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(p->n_params, 256)), dim3(256), 0, s, p->w.as<float>(),
                        p->wb.as<elem>(), p->n_params);
     RBP_HIP_CHECK(hipGetLastError());
     rbp_status st = transpose(p->wb.as<elem>() + p->oW2, p->hid, p->hid, p->w2t.as<elem>(), s);
     if (st) return st;
-    return transpose(p->wb.as<elem>() + p->oW3, p->out, p->hid, p->w3t.as<elem>(), s);
+    st = transpose(p->wb.as<elem>() + p->oW3, p->out, p->hid, p->w3t.as<elem>(), s);
+    if (st) return st;
+    return reorder_output(p, s);
 }
 
 rbp_status zero_adam(rbp_mlp* p) {
@@ -691,7 +721,7 @@ rbp_status rbp_mlp_destroy(rbp_mlp_t p) {
     (void)hipDeviceSynchronize();
     for (DevBuf* b : {&p->w, &p->m, &p->v, &p->g, &p->wb, &p->w2t, &p->w3t, &p->xb, &p->h1, &p->h2, &p->d3b,
                       &p->dh2b, &p->dh1b, &p->delta, &p->d3f, &p->dh2f, &p->dh1f, &p->partial, &p->loss, &p->tA,
-                      &p->tB, &p->csum})
+                      &p->tB, &p->csum, &p->ord, &p->w3o, &p->b3o})
         b->release();
     delete p;
     return RBP_OK;
@@ -734,9 +764,31 @@ rbp_status rbp_mlp_forward_bf16(rbp_mlp_t p, const uint32_t* syndromes, uint64_t
     for (uint64_t b0 = 0; b0 < shots; b0 += chunk) {
         const int B = (int)std::min<uint64_t>(chunk, shots - b0);
         st = forward(p, syndromes + b0 * words, B, nullptr, s, false,
-                     reinterpret_cast<elem*>(delta) + b0 * (uint64_t)p->out);
+                     reinterpret_cast<elem*>(delta) + b0 * (uint64_t)(p->ord_n > 0 ? p->ord_n : p->out));
         if (st) return st;
     }
+    return RBP_OK;
+}
+
+rbp_status rbp_mlp_set_output_order(rbp_mlp_t p, const int32_t* order, int32_t n) {
+    if (!p) return fail(RBP_ERR_INVALID_ARG, "mlp is NULL");
+    if (n < 0 || (n > 0 && !order)) return fail(RBP_ERR_INVALID_ARG, "order: n >= 0, NULL only with n = 0");
+    if (n == 0) {
+        p->ord_n = 0;
+        return RBP_OK;
+    }
+    for (int i = 0; i < n; ++i)
+        if (order[i] < -1 || order[i] >= p->out)
+            return fail(RBP_ERR_INVALID_ARG, "order entries must be -1 or output indices");
+    rbp_status st = p->ord.reserve(sizeof(int32_t) * (size_t)n);
+    if (!st) st = p->w3o.reserve(sizeof(elem) * (size_t)n * p->hid);
+    if (!st) st = p->b3o.reserve(sizeof(float) * (size_t)n);
+    if (st) return st;
+    RBP_HIP_CHECK(hipMemcpy(p->ord.p, order, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
+    p->ord_n = n;
+    st = reorder_output(p, nullptr);
+    if (st) return st;
+    RBP_HIP_CHECK(hipStreamSynchronize(nullptr));
     return RBP_OK;
 }
 

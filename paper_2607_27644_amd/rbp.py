@@ -166,6 +166,9 @@ def _load(path: str, required: bool):
         "rbp_decode_multi": [i32, vp, vp, vp, vp, u64, vp, P(RelayParamsC), vp, vp, vp, vp],
         "rbp_decode_noalloc": [vp, vp, vp, u64, P(RelayParamsC), vp, vp, vp, vp, vp],
         "rbp_decode_proposal": [vp, vp, vp, u64, P(RelayParamsC), vp, vp, vp, vp, vp],
+        "rbp_decode_proposal_pos": [vp, vp, vp, u64, P(RelayParamsC), vp, vp, vp, vp, vp],
+        "rbp_code_positions": [vp, P(i32), vp],
+        "rbp_mlp_set_output_order": [vp, vp, i32],
         "rbp_mlp_forward_bf16": [vp, vp, u64, vp, vp],
         "rbp_set_launch_config": [vp, P(LaunchConfigC)],
         "rbp_get_launch_config": [vp, P(LaunchConfigC), P(i32), P(i32)],
@@ -350,19 +353,34 @@ class Code:
                                _ptr(corr), _ptr(obsp), _ptr(st), _stream(stream)))
         return corr, obsp, st
 
+    def positions(self) -> np.ndarray:
+        """rbp_code_positions: the mechanism decoded at each decoder position
+        (Np entries, -1 for padding)."""
+        n = ctypes.c_int32()
+        check(lib().rbp_code_positions(self.h, ctypes.byref(n), None))
+        out = np.empty(n.value, dtype=np.int32)
+        check(lib().rbp_code_positions(self.h, ctypes.byref(n), out.ctypes.data))
+        return out
+
     def decode_proposal(self, priors, syndromes: torch.Tensor, params: RelayParams, delta_bf16: torch.Tensor,
-                        stats: bool = True, stream=None, out=None):
+                        stats: bool = True, stream=None, out=None, by_position: bool = False):
         """rbp_decode_proposal: the learned-proposal decode with BF16 adjustments
-        (torch.bfloat16 [shots][N], e.g. from MLP.forward_bf16)."""
+        (torch.bfloat16 [shots][N], e.g. from MLP.forward_bf16); by_position:
+        rbp_decode_proposal_pos, adjustments [shots][Np] in the decoder's
+        position order (positions(), MLP.set_output_order)."""
         _need(syndromes, "syndromes", torch.int32)
         shots = syndromes.shape[0]
         _need(syndromes, "syndromes", torch.int32, (shots, words(self.M)))
-        _need(delta_bf16, "delta_bf16", torch.bfloat16, (shots, self.N))
+        if by_position and getattr(self, "_np", None) is None:
+            self._np = len(self.positions())
+        width = self._np if by_position else self.N
+        _need(delta_bf16, "delta_bf16", torch.bfloat16, (shots, width))
         corr, obsp, st = self._outputs(shots, syndromes.device, stats, out)
         pr = self._priors(priors)
         prm = params.c()
-        check(lib().rbp_decode_proposal(self.h, pr.ctypes.data, _ptr(syndromes), shots, ctypes.byref(prm),
-                                        _ptr(delta_bf16), _ptr(corr), _ptr(obsp), _ptr(st), _stream(stream)))
+        fn = lib().rbp_decode_proposal_pos if by_position else lib().rbp_decode_proposal
+        check(fn(self.h, pr.ctypes.data, _ptr(syndromes), shots, ctypes.byref(prm), _ptr(delta_bf16), _ptr(corr),
+                 _ptr(obsp), _ptr(st), _stream(stream)))
         return corr, obsp, st
 
     def decode_noalloc(self, priors, syndromes: torch.Tensor, params: RelayParams,
@@ -750,14 +768,27 @@ class MLP:
         self._check(self._L.rbp_mlp_forward(self.h, _ptr(syndromes), shots, _ptr(out), _stream(stream)))
         return out
 
+    def set_output_order(self, order: Optional[np.ndarray]):
+        """rbp_mlp_set_output_order: forward_bf16 then writes len(order) columns,
+        column p the output order[p] (-1: zero); None restores the natural order."""
+        if order is None:
+            self._check(self._L.rbp_mlp_set_output_order(self.h, None, 0))
+            self._ord_n = 0
+            return
+        o = np.ascontiguousarray(order, dtype=np.int32)
+        self._check(self._L.rbp_mlp_set_output_order(self.h, o.ctypes.data, len(o)))
+        self._ord_n = len(o)
+
     def forward_bf16(self, syndromes: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-        """The forward pass with BF16 output (rbp_mlp_forward_bf16): torch.bfloat16 [shots][out_dim]."""
+        """The forward pass with BF16 output (rbp_mlp_forward_bf16): torch.bfloat16
+        [shots][out_dim], or [shots][len(order)] after set_output_order."""
         _need(syndromes, "syndromes", torch.int32)
         shots = syndromes.shape[0]
         _need(syndromes, "syndromes", torch.int32, (shots, words(self.in_dim)))
+        cols = getattr(self, "_ord_n", 0) or self.out_dim
         if out is None:
-            out = torch.empty((shots, self.out_dim), dtype=torch.bfloat16, device=syndromes.device)
-        _need(out, "out", torch.bfloat16, (shots, self.out_dim))
+            out = torch.empty((shots, cols), dtype=torch.bfloat16, device=syndromes.device)
+        _need(out, "out", torch.bfloat16, (shots, cols))
         self._check(self._L.rbp_mlp_forward_bf16(self.h, _ptr(syndromes), shots, _ptr(out), _stream(stream)))
         return out
 

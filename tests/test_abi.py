@@ -114,3 +114,14 @@ def test_resident_and_each_validation_without_gpu():
     prm = Params(0.125, -0.24, 0.66, 80, 60, 100, 5, 0, 0)
     assert lib.rbp_decode_each(1, codes, arr, shots, arr, ctypes.byref(prm), arr, arr, None, None) == -1
     assert b"code is NULL" in lib.rbp_last_error()
+
+
+def test_position_order_validation_without_gpu():
+    """rbp_code_positions, rbp_decode_proposal_pos and rbp_mlp_set_output_order
+    reject NULL handles before any device call."""
+    lib = ctypes.CDLL(os.path.join(PKG, "librbp.so"))
+    lib.rbp_last_error.restype = ctypes.c_char_p
+    n = ctypes.c_int32()
+    assert lib.rbp_code_positions(None, ctypes.byref(n), None) == -1
+    assert lib.rbp_decode_proposal_pos(None, None, None, 0, None, None, None, None, None, None) == -1
+    assert lib.rbp_mlp_set_output_order(None, None, 0) == -1

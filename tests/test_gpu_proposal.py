@@ -83,3 +83,78 @@ def test_proposal_bf16_against_oracle(rbp):
     s = rbp.stats_to_numpy(st)
     for key in ("converged", "nconv", "path", "legs", "iters"):
         assert np.array_equal(s[key][same], ref[key][same]), key
+
+
+def by_position(d16, vord):
+    """[shots][N] adjustments by mechanism -> [shots][Np] by decoder position
+    (padding 0), the plain gather"""
+    out = torch.zeros((d16.shape[0], len(vord)), dtype=torch.bfloat16, device=d16.device)
+    live = np.flatnonzero(vord >= 0)
+    idx = torch.from_numpy(vord[live].astype(np.int64)).cuda()
+    out[:, torch.from_numpy(live).cuda()] = d16[:, idx]
+    return out
+
+
+@pytest.mark.parametrize("name,state", [("phen160", 1), ("phen160", 3), ("phen840", 3), ("phen840", 2),
+                                        ("cc160", 3)])
+def test_proposal_by_position_equals_by_mechanism(rbp, name, state):
+    """rbp_decode_proposal_pos on the adjustments gathered into position order
+    gives the same outputs as rbp_decode_proposal, bit for bit, in every state."""
+    dem = W.workload(name)
+    code = rbp.Code.from_dem(dem)
+    code.set_launch_config(0, state, 0)
+    params = rbp.RelayParams(num_sets=20)
+    shots = 4000 if dem.N > 5000 else 10000
+    syn, _, _ = code.sample(dem.priors, shots, seed=19)
+    rng = np.random.default_rng(4)
+    sd = np.where(np.arange(shots) % 2 == 0, 1.0, 12.0)[:, None]
+    d16 = torch.from_numpy((rng.normal(0, 1.0, (shots, dem.N)) * sd).astype(np.float32)).cuda().to(torch.bfloat16)
+    vord = code.positions()
+    assert sorted(vord[vord >= 0].tolist()) == list(range(dem.N)) and (vord[dem.N:] == -1).all()
+    dpos = by_position(d16, vord)
+    dpos[:, dem.N:] = 7.0  # padding entries are ignored
+    a = code.decode_proposal(dem.priors, syn, params, d16)
+    b = code.decode_proposal(dem.priors, syn, params, dpos, by_position=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert torch.equal(a[2][:, :16], b[2][:, :16])
+    path = rbp.stats_to_numpy(b[2])["path"]
+    assert (path == 1).any() and (path == 2).any()
+
+
+def test_network_output_in_position_order(rbp):
+    """MLP.set_output_order: the BF16 forward writes the output columns in the
+    given order (zeros at -1), equal to the gathered natural output, also after
+    the weights change (a training step, set_params); None restores the order."""
+    dem = W.workload("phen160")
+    code = rbp.Code.from_dem(dem)
+    vord = code.positions()
+    net = rbp.MLP(dem.M, 128, dem.N, seed=5)
+    p = net.get_params()
+    p[-dem.N:] = np.random.default_rng(1).normal(0, 0.5, dem.N).astype(np.float32)
+    net.set_params(p)
+    syn, _, err = code.sample(np.full(dem.N, 5e-3), 3000, seed=2, errors=True)
+    nat = net.forward_bf16(syn)
+    net.set_output_order(vord)
+    pos = net.forward_bf16(syn)
+    torch.cuda.synchronize()
+    assert pos.shape == (3000, len(vord))
+    assert torch.equal(pos, by_position(nat, vord))
+    llr = code.llr(np.full(dem.N, 5e-3))
+    net.train_step(syn[:1024], err[:1024], llr, lr=1e-3)
+    net.set_output_order(None)
+    nat2 = net.forward_bf16(syn)
+    net.set_output_order(vord)
+    pos2 = net.forward_bf16(syn)
+    torch.cuda.synchronize()
+    assert not torch.equal(nat2, nat)
+    assert torch.equal(pos2, by_position(nat2, vord))
+    # a training step with the order set keeps the ordered copy current
+    net.train_step(syn[:1024], err[:1024], llr, lr=1e-3)
+    pos3 = net.forward_bf16(syn)
+    net.set_output_order(None)
+    nat3 = net.forward_bf16(syn)
+    torch.cuda.synchronize()
+    assert torch.equal(pos3, by_position(nat3, vord))
+    with pytest.raises(rbp.RbpError, match="INVALID_ARG"):
+        net.set_output_order(np.array([0, dem.N], dtype=np.int32))
