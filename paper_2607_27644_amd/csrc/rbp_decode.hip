@@ -1428,6 +1428,37 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
             for (int i = tid; i < m.GR; i += nth) lrg[i] = m.rgrp[i];
             cur_model = mi;
         }
+        if (PROP && dpos) {
+            // the shot's BF16 adjustments, placed in LDS by position (padding 0) at
+            // the shot's start, where their loads overlap the syndrome's (the
+            // barrier after the syndrome orders the stores before any read:
+            // 1-7 % off a proposal decode); by mechanism, a gather through the
+            // mechanism-to-position table with four loads in flight per thread
+            if (a.d16_pos) {
+                // rows by position (Np entries, a multiple of 64, padding 0):
+                // contiguous 16-byte copies
+                for (int q = tid; q < (m.Np >> 3); q += nth)
+                    reinterpret_cast<uint4*>(dpos)[q] = reinterpret_cast<const uint4*>(dl16)[q];
+                __syncthreads();
+            }
+            int j = a.d16_pos ? N : tid;
+            for (; j + 3 * nth < N; j += 4 * nth) {
+                const uint16_t d0 = dl16[j + 0 * nth];
+                const uint16_t d1 = dl16[j + 1 * nth];
+                const uint16_t d2 = dl16[j + 2 * nth];
+                const uint16_t d3 = dl16[j + 3 * nth];
+                const int p0 = ldg(m.vinv, j + 0 * nth);
+                const int p1 = ldg(m.vinv, j + 1 * nth);
+                const int p2 = ldg(m.vinv, j + 2 * nth);
+                const int p3 = ldg(m.vinv, j + 3 * nth);
+                dpos[p0] = d0;
+                dpos[p1] = d1;
+                dpos[p2] = d2;
+                dpos[p3] = d3;
+            }
+            for (; j < N; j += nth) dpos[ldg(m.vinv, j)] = dl16[j];
+            for (int pp = N + tid; pp < m.Np; pp += nth) dpos[pp] = 0;
+        }
         int pc = 0;
         for (int w = tid; w < WM; w += nth) {
             const uint32_t v = m.syn[row * WM + w];
@@ -1469,37 +1500,6 @@ __global__ void __launch_bounds__(1024, MINW) relay_bp_compact_kernel(const Deco
                 }
                 for (int w = tid; w < 2 * m.GR; w += nth) par[w] = sigp[w];
                 __syncthreads();
-                if (prop && dpos) {
-                    // the shot's BF16 adjustments, read in variable order (coalesced,
-                    // independent loads, four in flight per thread before their LDS
-                    // stores: 6.5 % off a proposal decode of the [[840,168]] model)
-                    // and placed in LDS by position; padding 0
-                    if (a.d16_pos) {
-                        // rows by position (Np entries, a multiple of 64, padding 0):
-                        // contiguous 16-byte copies
-                        for (int q = tid; q < (m.Np >> 3); q += nth)
-                            reinterpret_cast<uint4*>(dpos)[q] = reinterpret_cast<const uint4*>(dl16)[q];
-                        __syncthreads();
-                    }
-                    int j = a.d16_pos ? N : tid;
-                    for (; j + 3 * nth < N; j += 4 * nth) {
-                        const uint16_t d0 = dl16[j + 0 * nth];
-                        const uint16_t d1 = dl16[j + 1 * nth];
-                        const uint16_t d2 = dl16[j + 2 * nth];
-                        const uint16_t d3 = dl16[j + 3 * nth];
-                        const int p0 = ldg(m.vinv, j + 0 * nth);
-                        const int p1 = ldg(m.vinv, j + 1 * nth);
-                        const int p2 = ldg(m.vinv, j + 2 * nth);
-                        const int p3 = ldg(m.vinv, j + 3 * nth);
-                        dpos[p0] = d0;
-                        dpos[p1] = d1;
-                        dpos[p2] = d2;
-                        dpos[p3] = d3;
-                    }
-                    for (; j < N; j += nth) dpos[ldg(m.vinv, j)] = dl16[j];
-                    for (int pp = N + tid; pp < m.Np; pp += nth) dpos[pp] = 0;
-                    __syncthreads();
-                }
                 {
                     // M(0) = Lambda (or Lambda + delta), then the starting hard decision:
                     // the (few) negative entries flip their checks.  Two passes, so that
