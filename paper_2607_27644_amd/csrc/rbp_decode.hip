@@ -1206,22 +1206,26 @@ __device__ __forceinline__ void compact_row(const int32_t* cp, uint32_t rpx, uin
     uint4 old = make_uint4(0u, 0u, 0u, 0u);
     if (!FIRST) old = lds_rec(rpx);
     const uint32_t pa = old.w - rpx;
-    uint32_t m1 = 0x7f800000u, m2 = 0x7f800000u, nb = 0u, am = 0u;
+    // the minima as floats: |nu| enters the float median and compare as a
+    // source modifier; on these operands (no NaN, not negative) the float and
+    // unsigned orders agree, and both results are one of the inputs' bits
+    float m1 = __uint_as_float(0x7f800000u), m2 = m1;
+    uint32_t nb = 0u, am = 0u;
 #pragma unroll
     for (int p = 0; p < D; ++p) {
         const int c = D - 1 - p;  // the edge's code
         const float M = lds_f(pos[p]);
-        uint32_t nu;
+        float nu;
         if (FIRST) {
-            nu = __float_as_uint(M);
+            nu = M;
         } else {
             const uint32_t mag = pa == (uint32_t)c ? old.y : old.x;
             const float mu = __uint_as_float(mag | ((old.z << (31 - c)) & 0x80000000u));
-            nu = __float_as_uint(M - mu);
+            nu = M - mu;
         }
-        const uint32_t av = nu & 0x7fffffffu;
-        nb = __builtin_amdgcn_alignbit(nb, nu, 31);  // (nb << 1) | sign: edge p lands on bit c
-        m2 = umed3(m1, m2, av);
+        const float av = __builtin_fabsf(nu);
+        nb = __builtin_amdgcn_alignbit(nb, __float_as_uint(nu), 31);  // (nb << 1) | sign: edge p lands on bit c
+        m2 = __builtin_amdgcn_fmed3f(m1, m2, av);
         const bool lt = av < m1;
         m1 = lt ? av : m1;
         am = lt ? (uint32_t)c : am;
@@ -1229,7 +1233,7 @@ __device__ __forceinline__ void compact_row(const int32_t* cp, uint32_t rpx, uin
     // sign of mu = sigma xor (parity of all signs) xor sign(nu)
     const uint32_t flip = 0u - ((((uint32_t)__popc(nb)) ^ sigma) & 1u);
     const uint32_t sg = (nb ^ flip) & 0xFFFFu;
-    lds_rec_st(rpx, make_uint4(m1, m2, sg | (sg << 16), rpx + am));
+    lds_rec_st(rpx, make_uint4(__float_as_uint(m1), __float_as_uint(m2), sg | (sg << 16), rpx + am));
 }
 
 // stored row degrees of the compact form: 2..12 exactly, 13..16 padded to 16
