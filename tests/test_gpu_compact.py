@@ -193,6 +193,39 @@ def test_compact_equals_per_edge_state_for_every_launch_shape(rbp):
             assert np.array_equal(a, b), (waves, slots)
 
 
+def test_compact_zero_and_tied_magnitudes(rbp):
+    """Priors of exactly 0.5 (Lambda = +0) on about 2 % of the mechanisms and
+    one shared prior on the rest: the check sweep meets |nu| = 0, messages of
+    either zero sign and exact ties between the two least magnitudes, where
+    the row minima must still select the same bits as an unsigned minimum.
+    The compact decode of the 12-round [[840,168]] model equals the per-edge
+    decode (device-memory state) bit for bit, and the oracle on a spread
+    sample of 200 shots."""
+    dem = dem_of("phen840")
+    rng = np.random.default_rng(23)
+    pri = np.full(dem.N, 2e-3)
+    pri[rng.random(dem.N) < 0.02] = 0.5
+    code = rbp.Code.from_dem(dem)
+    params = rbp.RelayParams(num_sets=10)
+    syn, _, _ = code.sample(pri, 2000, seed=29)
+    outs = []
+    for state in (COMPACT, 2):
+        code.set_launch_config(0, state, 0)
+        corr, obsp, st = code.decode(pri, syn, params)
+        torch.cuda.synchronize()
+        assert code.launch_config()["state"] == state
+        s = rbp.stats_to_numpy(st)
+        outs.append((u32(corr), u32(obsp), s["converged"], s["nconv"], s["path"], s["legs"], s["iters"]))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    idx = np.linspace(0, 1999, 200).astype(int)
+    syn_np = u32(syn)[idx]
+    ref = oracle.decode(oracle.Graph(dem.H, dem.O), pri, syn_np, oparams(params), nthreads=16)
+    assert np.array_equal(outs[0][0][idx], ref["corrections"])
+    for key, got in zip(("converged", "nconv", "path", "legs", "iters"), outs[0][2:]):
+        assert np.array_equal(got[idx], ref[key]), key
+
+
 def test_compact_wide_and_mixed_rows(rbp):
     """Rows of 13 to 16 edges (stored as 16, padding read from the +inf cell),
     mixed row and variable groups, and a mechanism in no check."""
