@@ -405,8 +405,8 @@ def ler_sweep(name: str, ps, shots: int, seed: int = 51, params: rbp.RelayParams
                                                                    stats.per_round(hi, dem.rounds * dem.k)],
                      "mean_iters": it, "nonconverged": nc})
         print(f"[sweep] {name} p = {p:g}: {f} failures, {it:.1f} iterations", file=sys.stderr, flush=True)
-    out = {"model": name, "rounds": dem.rounds, "k": dem.k, "shots_per_point": shots, "d_circ": d_circ,
-           "gamma": [params.gamma_min, params.gamma_max], "points": rows}
+    out = {"model": name, "rounds": dem.rounds, "k": dem.k, "shots_per_point": shots, "seed": seed,
+           "d_circ": d_circ, "gamma": [params.gamma_min, params.gamma_max], "points": rows}
     fit = [r for r in rows if r["p"] <= p_fit_max and r["failures"] > 0]
     if len(fit) >= 3 and d_circ > 0:
         c = stats.fit_ler([r["p"] for r in fit], [r["per_qubit_round"] for r in fit], d_circ,
@@ -558,6 +558,8 @@ def main():
     ap.add_argument("--num-sets", type=int, default=1000)
     ap.add_argument("--bases", default="XZ")
     ap.add_argument("--chunk", type=int, default=20000, help="shots per decode call of the LER experiments")
+    ap.add_argument("--seed", type=int, default=51,
+                    help="syndrome seed of the sweep (point i draws from seed + i); change it to add shots to a point")
     a = ap.parse_args()
     global CHUNK
     CHUNK = max(1, a.chunk)
@@ -585,7 +587,7 @@ def main():
         r = resident_exp(a.model, a.p_circuit, a.seq_shots, 20)
     elif a.what == "sweep":
         gmin, gmax = (float(x) for x in a.sweep_gamma.split(","))
-        r = ler_sweep(a.model, [float(x) for x in a.ps.split(",")], a.shots, p_fit_max=a.p_fit_max,
+        r = ler_sweep(a.model, [float(x) for x in a.ps.split(",")], a.shots, seed=a.seed, p_fit_max=a.p_fit_max,
                       params=rbp.RelayParams(gamma_min=gmin, gamma_max=gmax, num_sets=a.num_sets_grid))
     else:
         raise SystemExit(__doc__)
